@@ -1,0 +1,94 @@
+/*
+ * cpc_oracle.h — plain FP64 CPU oracle for the partition-and-combine
+ * maximum-pseudo-likelihood (MPL) copula estimator of Wei, Kim & Conlon,
+ * "Parallel Computing for Copula Parameter Estimation with Big Data:
+ * A Simulation Study" (arXiv:1609.05530).
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library. It shares no code,
+ * header or table with the GPU library; the numeric codes below are an
+ * interface agreement, written out separately on each side.
+ */
+#ifndef CPC_ORACLE_H
+#define CPC_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_GAUSSIAN = 0, OR_FRANK = 1, OR_GUMBEL = 2 };
+enum { OR_TIES_AVERAGE = 0, OR_TIES_FIRST = 1 };
+enum { OR_VAR_GGR = 0, OR_VAR_INVINFO = 1 };
+enum {
+  OR_OK = 0,
+  OR_BOUNDARY_NATURAL = 1, /* Gumbel estimate at theta = 1 */
+  OR_BOUNDARY_BOX = 2,     /* estimate at an edge of the search box */
+  OR_DEGENERATE = 3,       /* n < n_min or a margin with a single value */
+  OR_NONFINITE = 4,        /* NaN or Inf in the subset's data */
+  OR_NOCONV = 5,           /* iteration cap reached */
+  OR_BADVAR = 6            /* variance not positive and finite */
+};
+
+typedef struct {
+  int32_t ties;     /* OR_TIES_* */
+  int32_t var;      /* OR_VAR_* */
+  int32_t max_iter; /* Newton cap after the grid stage */
+  int32_t pad;
+  double tol;       /* |dtheta| <= tol * (1 + |theta|) */
+  int64_t n_min;    /* subsets smaller than this are DEGENERATE (>= 2) */
+} or_options;
+
+typedef struct {
+  double theta, var, loglik, score;
+  int64_t n;
+  int32_t iters, status;
+} or_subset;
+
+typedef struct {
+  double theta, var_combined;
+  int64_t n_used, n_excluded;
+  int32_t status, pad;
+} or_combined;
+
+void or_default_options(or_options* o);
+
+/* Doubled ranks of x[0..n) (eq. 12): R = 2 * rank, so average ties stay integer. */
+void or_ranks(const double* x, int64_t n, int32_t ties, int64_t* R);
+
+/* Standard normal quantile z with Phi(z) = p; omp = 1 - p given exactly. */
+double or_qnorm(double p, double omp);
+
+/* Per-row log copula density and its derivatives at theta:
+ * out[5*i + 0..4] = l, dl/dtheta, d2l/dtheta2, d2l/dtheta du, d2l/dtheta dv. */
+void or_logc_derivs(int32_t family, double theta, const double* u, const double* omu,
+                    const double* v, const double* omv, int64_t n, double* out);
+
+/* Kendall tau and Spearman rho of the one-parameter families. */
+double or_tau(int32_t family, double theta);
+double or_rho_s(int32_t family, double theta);
+double or_debye(int32_t k, double x);
+
+/* Fit one subset: ranks, MPL maximisation and asymptotic variance. */
+void or_fit_subset(const double* x, const double* y, int64_t n, int32_t family,
+                   const or_options* opt, or_subset* out);
+
+/* GGR influence terms for one subset at theta, for tests:
+ * psi_out[4*i + 0..3] = s_i, W1_i, W2_i, psi_i. Returns the variance. */
+double or_ggr(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, double theta,
+              int32_t var_method, double* psi_out);
+
+/* Combine (eq. 15/16) subset results over groups of consecutive subsets. */
+void or_combine(const or_subset* sub, const int64_t* group_offsets, int64_t G, or_combined* comb);
+
+/* Whole path: subsets [offsets[m], offsets[m+1]), groups of subsets
+ * [group_offsets[g], group_offsets[g+1]) with family_per_group[g]. */
+void or_fit(const double* x, const double* y, const int64_t* offsets, int64_t K,
+            const int64_t* group_offsets, int64_t G, const int32_t* family_per_group,
+            const or_options* opt, int32_t nthreads, or_subset* out, or_combined* comb);
+
+int32_t or_num_threads(int32_t requested);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

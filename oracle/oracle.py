@@ -1,0 +1,200 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``cpc_oracle.c``).
+
+TEST INFRASTRUCTURE. Only the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this module. It never touches the
+GPU library and the GPU library never touches it.
+
+The oracle follows arXiv:1609.05530: ranks by eq. (12) with N read as the
+subset size, the pseudo log-likelihood of eq. (13) for the copulas of eq. (8),
+(10) and (11) (densities by eq. (5)), its numerical maximisation and the
+Genest-Ghoudi-Rivest asymptotic variance (Sec. 2.3), the row partition of
+eq. (14) and the inverse-variance combination of eq. (15)/(16).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "cpc_oracle.c")
+LIB = os.path.join(_HERE, "liboracle.so")
+
+FAMILIES = {"gaussian": 0, "frank": 1, "gumbel": 2}
+TIES = {"average": 0, "first": 1}
+VARS = {"ggr": 0, "invinfo": 1}
+
+STATUS_NAMES = {
+    0: "OK",
+    1: "BOUNDARY_NATURAL",
+    2: "BOUNDARY_BOX",
+    3: "DEGENERATE",
+    4: "NONFINITE",
+    5: "NOCONV",
+    6: "BADVAR",
+}
+
+SUBSET_DTYPE = np.dtype(
+    [("theta", "f8"), ("var", "f8"), ("loglik", "f8"), ("score", "f8"), ("n", "i8"),
+     ("iters", "i4"), ("status", "i4")], align=True)
+COMBINED_DTYPE = np.dtype(
+    [("theta", "f8"), ("var_combined", "f8"), ("n_used", "i8"), ("n_excluded", "i8"),
+     ("status", "i4"), ("pad", "i4")], align=True)
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("ties", ctypes.c_int32), ("var", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tol", ctypes.c_double), ("n_min", ctypes.c_int64)]
+
+
+def build() -> str:
+    """Compile the oracle with gcc (IEEE double, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-o", LIB + ".tmp", SRC, "-lm"]
+    subprocess.check_call(cmd, cwd=_HERE)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ctypes.CDLL(LIB)
+        d = ctypes.c_double
+        i32 = ctypes.c_int32
+        i64 = ctypes.c_int64
+        p = ctypes.c_void_p
+        L.or_qnorm.restype = d
+        L.or_qnorm.argtypes = [d, d]
+        L.or_tau.restype = d
+        L.or_tau.argtypes = [i32, d]
+        L.or_rho_s.restype = d
+        L.or_rho_s.argtypes = [i32, d]
+        L.or_debye.restype = d
+        L.or_debye.argtypes = [i32, d]
+        L.or_ranks.restype = None
+        L.or_ranks.argtypes = [p, i64, i32, p]
+        L.or_logc_derivs.restype = None
+        L.or_logc_derivs.argtypes = [i32, d, p, p, p, p, i64, p]
+        L.or_ggr.restype = d
+        L.or_ggr.argtypes = [p, p, i64, i32, d, i32, p]
+        L.or_combine.restype = None
+        L.or_combine.argtypes = [p, p, i64, p]
+        L.or_fit.restype = None
+        L.or_fit.argtypes = [p, p, p, i64, p, i64, p, ctypes.POINTER(_Options), i32, p, p]
+        L.or_num_threads.restype = i32
+        L.or_num_threads.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _fam(f) -> int:
+    return FAMILIES[f] if isinstance(f, str) else int(f)
+
+
+def qnorm(p, omp=None) -> np.ndarray:
+    p = np.atleast_1d(np.asarray(p, dtype=np.float64))
+    omp = 1.0 - p if omp is None else np.atleast_1d(np.asarray(omp, dtype=np.float64))
+    L = lib()
+    return np.array([L.or_qnorm(float(a), float(b)) for a, b in zip(p, omp)])
+
+
+def tau(family, theta: float) -> float:
+    return lib().or_tau(_fam(family), float(theta))
+
+
+def rho_s(family, theta: float) -> float:
+    return lib().or_rho_s(_fam(family), float(theta))
+
+
+def debye(k: int, x: float) -> float:
+    return lib().or_debye(int(k), float(x))
+
+
+def ranks(x, ties: str = "average") -> np.ndarray:
+    """Doubled ranks R = 2 * rank of eq. (12) (average ties stay integer)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    R = np.empty(x.shape[0], dtype=np.int64)
+    lib().or_ranks(_ptr(x), x.shape[0], TIES[ties], _ptr(R))
+    return R
+
+
+def pobs_from_ranks(R: np.ndarray, n: int):
+    """u = R / (2(n+1)) and 1 - u = (2(n+1) - R) / (2(n+1)), both exact rationals."""
+    den = 2.0 * (n + 1.0)
+    R = np.asarray(R, dtype=np.float64)
+    return R / den, (den - R) / den
+
+
+def logc_derivs(family, theta: float, u, omu, v, omv) -> np.ndarray:
+    """Per row: l, l_theta, l_theta_theta, l_theta_u, l_theta_v (shape (n, 5))."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (u, omu, v, omv)]
+    n = arrs[0].shape[0]
+    out = np.empty((n, 5), dtype=np.float64)
+    lib().or_logc_derivs(_fam(family), float(theta), *[_ptr(a) for a in arrs], n, _ptr(out))
+    return out
+
+
+def ggr(R1, R2, family, theta: float, var: str = "ggr"):
+    """GGR plug-in variance at theta; also returns per-row (s, W1, W2, psi)."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    n = R1.shape[0]
+    terms = np.empty((n, 4), dtype=np.float64)
+    v = lib().or_ggr(_ptr(R1), _ptr(R2), n, _fam(family), float(theta), VARS[var], _ptr(terms))
+    return v, terms
+
+
+def options(ties="average", var="ggr", max_iter=100, tol=1e-13, n_min=2) -> _Options:
+    return _Options(TIES[ties], VARS[var], int(max_iter), 0, float(tol), int(n_min))
+
+
+def fit(x, y, offsets, family, group_offsets=None, *, ties="average", var="ggr", max_iter=100,
+        tol=1e-13, n_min=2, nthreads=0):
+    """Fit every subset [offsets[m], offsets[m+1]) and combine per group.
+
+    ``family`` is one family (all groups) or a sequence with one per group.
+    Returns (subsets, combined) as numpy structured arrays.
+    """
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    K = offsets.shape[0] - 1
+    if group_offsets is None:
+        group_offsets = np.array([0, K], dtype=np.int64)
+    group_offsets = np.ascontiguousarray(group_offsets, dtype=np.int64)
+    G = group_offsets.shape[0] - 1
+    if isinstance(family, (str, int, np.integer)):
+        fams = np.full(G, _fam(family), dtype=np.int32)
+    else:
+        fams = np.ascontiguousarray([_fam(f) for f in family], dtype=np.int32)
+    sub = np.zeros(K, dtype=SUBSET_DTYPE)
+    comb = np.zeros(G, dtype=COMBINED_DTYPE)
+    opt = options(ties, var, max_iter, tol, n_min)
+    lib().or_fit(_ptr(x), _ptr(y), _ptr(offsets), K, _ptr(group_offsets), G, _ptr(fams),
+                 ctypes.byref(opt), int(nthreads), _ptr(sub), _ptr(comb))
+    return sub, comb
+
+
+def combine(sub: np.ndarray, group_offsets) -> np.ndarray:
+    sub = np.ascontiguousarray(sub, dtype=SUBSET_DTYPE)
+    group_offsets = np.ascontiguousarray(group_offsets, dtype=np.int64)
+    G = group_offsets.shape[0] - 1
+    comb = np.zeros(G, dtype=COMBINED_DTYPE)
+    lib().or_combine(_ptr(sub), _ptr(group_offsets), G, _ptr(comb))
+    return comb
+
+
+def num_threads(requested: int = 0) -> int:
+    return lib().or_num_threads(int(requested))
