@@ -1,0 +1,194 @@
+/*
+ * cpc.h — C ABI of libcpc: partition-and-combine maximum-pseudo-likelihood
+ * (MPL) copula estimation on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wei, Kim & Conlon, "Parallel Computing for Copula Parameter
+ * Estimation with Big Data: A Simulation Study" (arXiv:1609.05530).
+ *   - eq. (14), Sec. 2.4: the N x 2 sample is split by rows into M disjoint
+ *     subsets. Here subset m is rows [offsets[m], offsets[m+1]).
+ *   - Sec. 2.3, eq. (12): within each subset each margin is replaced by its
+ *     normalised ranks u = r / (n_m + 1) (n_m = subset size).
+ *   - eq. (13): the pseudo log-likelihood sum_i log c(u_i1, u_i2; theta) is
+ *     maximised numerically for the Gaussian (eq. 8), Frank (eq. 10) or
+ *     Gumbel (eq. 11) copula, with c from eq. (5).
+ *   - Sec. 2.3: the asymptotic variance of each subset estimate after
+ *     Genest, Ghoudi & Rivest (1995).
+ *   - eq. (15) / (16): subset estimates are combined with weights
+ *     w_m = 1 / sigma_m^2, per group of subsets (one group per simulation
+ *     replicate in a batch).
+ *
+ * Conventions for every entry point:
+ *   - Data x, y are device pointers to n values each (structure of arrays),
+ *     FP64 or FP32 as given by cpc_dtype_t. The library only reads them.
+ *   - offsets / group_offsets / family tables are HOST arrays; they are
+ *     copied into the workspace during the call and may be reused on return.
+ *   - workspace is a caller-owned DEVICE buffer of at least the size reported
+ *     by cpc_workspace_bytes(); the library allocates no device memory in any
+ *     call except cpc_create().
+ *   - All outputs are DEVICE buffers owned by the caller. Work is enqueued on
+ *     `stream` (a hipStream_t passed as void*; NULL = default stream) and is
+ *     complete once the stream is synchronised.
+ *   - Return value 0 = success; a negative CPC_E_* code on misuse detected on
+ *     the host (nothing is enqueued then). cpc_last_error() gives a
+ *     thread-local description of the last failure.
+ *   - Data-dependent trouble is never an error: it is reported per subset in
+ *     cpc_subset_result_t.status (CPC_ST_*).
+ *   - A handle serves one call at a time (not re-entrant).
+ */
+#ifndef CPC_H
+#define CPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPC_VERSION_MAJOR 0
+#define CPC_VERSION_MINOR 1
+
+/* Copula families (Sec. 2.2): eq. (8), eq. (10), eq. (11). */
+typedef enum { CPC_GAUSSIAN = 0, CPC_FRANK = 1, CPC_GUMBEL = 2 } cpc_family_t;
+
+/* Storage type of x and y. */
+typedef enum { CPC_F64 = 0, CPC_F32 = 1 } cpc_dtype_t;
+
+/* Per-row arithmetic: plain FP64, or FP32 rows with compensated FP32 sums
+ * (per-subset totals, the Newton update and the combine stay FP64; rows near
+ * the family boundaries switch to FP64). */
+typedef enum { CPC_PREC_FP64 = 0, CPC_PREC_FP32C = 1 } cpc_prec_t;
+
+/* Tie rule for eq. (12) (the paper assumes continuous data). AVERAGE gives
+ * tied values their mean rank; FIRST breaks ties by row order. */
+typedef enum { CPC_TIES_AVERAGE = 0, CPC_TIES_FIRST = 1 } cpc_ties_t;
+
+/* Variance of a subset estimate: GGR sandwich (Sec. 2.3) or the inverse of
+ * the observed score variance (ignores the rank effect; for comparison). */
+typedef enum { CPC_VAR_GGR = 0, CPC_VAR_INVINFO = 1 } cpc_var_t;
+
+/* Per-subset status. Only OK and BOUNDARY_NATURAL enter the combination. */
+enum {
+  CPC_ST_OK = 0,
+  CPC_ST_BOUNDARY_NATURAL = 1, /* Gumbel estimate at theta = 1 (independence) */
+  CPC_ST_BOUNDARY_BOX = 2,     /* estimate at an edge of the search box */
+  CPC_ST_DEGENERATE = 3,       /* n_m < n_min, or a margin with a single value */
+  CPC_ST_NONFINITE = 4,        /* NaN or +-Inf in the subset's x or y */
+  CPC_ST_NOCONV = 5,           /* max_iter Newton passes without convergence */
+  CPC_ST_BADVAR = 6            /* variance not positive and finite */
+};
+
+/* Error codes (host-side misuse). */
+enum {
+  CPC_SUCCESS = 0,
+  CPC_E_NULL = -1,        /* a required pointer is NULL */
+  CPC_E_SIZE = -2,        /* n < 0, K < 1, G < 1, or a count out of range */
+  CPC_E_OFFSETS = -3,     /* offsets not non-decreasing from 0 to n, or groups not spanning 0..K */
+  CPC_E_ENUM = -4,        /* unknown family / dtype / precision / ties / variance value */
+  CPC_E_WORKSPACE = -5,   /* workspace NULL or smaller than required */
+  CPC_E_HIP = -6,         /* a HIP runtime call failed */
+  CPC_E_HANDLE = -7,      /* invalid handle */
+  CPC_E_OPTIONS = -8,     /* an option out of range (max_iter < 1, tol <= 0, ...) */
+  CPC_E_UNSUPPORTED = -9  /* a size this build cannot handle (e.g. n >= 2^31 rows in one subset) */
+};
+
+typedef struct {
+  int32_t prec;      /* cpc_prec_t, default CPC_PREC_FP64 */
+  int32_t ties;      /* cpc_ties_t, default CPC_TIES_AVERAGE */
+  int32_t var;       /* cpc_var_t, default CPC_VAR_GGR */
+  int32_t max_iter;  /* Newton passes per subset, default 60 */
+  double tol;        /* stop when |dtheta| <= tol (1 + |theta|); 0 = default (1e-12 FP64, 1e-9 FP32C) */
+  int64_t n_min;     /* subsets with fewer rows are DEGENERATE; default (and minimum) 2 */
+  int32_t schedule;  /* -1 = autotuned; otherwise a fixed schedule id (see DESIGN) */
+  int32_t flags;     /* bit 0: capture/replay the launch sequence as a hipGraph */
+} cpc_options_t;
+
+#define CPC_FLAG_GRAPH 1
+
+/* 48 bytes, natural alignment. */
+typedef struct {
+  double theta;   /* MPL estimate theta_m (NaN if DEGENERATE / NONFINITE) */
+  double var;     /* sigma_m^2, the estimated variance of theta_m (NaN unless OK / BOUNDARY_NATURAL / BADVAR) */
+  double loglik;  /* eq. (13) at theta_m */
+  double score;   /* d/dtheta of eq. (13) at theta_m */
+  int64_t n;      /* subset size n_m */
+  int32_t iters;  /* Newton passes over the rows */
+  int32_t status; /* CPC_ST_* */
+} cpc_subset_result_t;
+
+/* 40 bytes. One per group. */
+typedef struct {
+  double theta;        /* eq. (15): sum w_m theta_m / sum w_m over usable subsets (NaN if none) */
+  double var_combined; /* 1 / sum w_m */
+  int64_t n_used;      /* subsets that entered the combination */
+  int64_t n_excluded;  /* subsets left out (status other than OK / BOUNDARY_NATURAL) */
+  int32_t status;      /* 0 = ok, 1 = no usable subset in the group */
+  int32_t pad;
+} cpc_combined_t;
+
+typedef struct cpc_context* cpc_handle_t;
+
+/* Create a handle bound to HIP device `device` (makes it current). */
+int cpc_create(int device, cpc_handle_t* out);
+int cpc_destroy(cpc_handle_t h);
+
+/* Fill `opt` with the defaults listed above. */
+void cpc_default_options(cpc_options_t* opt);
+
+/* Workspace bytes that suffice for any call with at most n rows, K subsets
+ * and G groups of the given storage type and options (an upper bound). */
+size_t cpc_workspace_bytes(int64_t n, int64_t K, int64_t G, int32_t dtype, const cpc_options_t* opt);
+
+/* Fit every subset of one family and combine them (eq. 12-15).
+ *   x, y     : device, n values each, type `dtype`
+ *   offsets  : host, K+1 values, offsets[0] = 0, non-decreasing, offsets[K] = n
+ *   out      : device, K results;  comb : device, 1 combined result
+ */
+int cpc_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+            const int64_t* offsets, int64_t K, int32_t family, const cpc_options_t* opt,
+            void* workspace, size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb,
+            void* stream);
+
+/* Batched form (eq. 16): G groups of consecutive subsets, group g being
+ * subsets [group_offsets[g], group_offsets[g+1]) fitted with family
+ * family_per_group[g] and combined on their own.
+ *   group_offsets    : host, G+1 values, 0 .. K non-decreasing
+ *   family_per_group : host, G values (cpc_family_t)
+ *   comb             : device, G combined results
+ */
+int cpc_fit_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+                    const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                    const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
+                    size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
+
+/* Ranks of eq. (12) within each subset, as doubled integers R = 2 r (so
+ * average ties stay integral): u = R / (2 (n_m + 1)).
+ *   R1, R2 : device, n values each, row order (same indexing as x, y).
+ */
+int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+             const int64_t* offsets, int64_t K, const cpc_options_t* opt, void* workspace,
+             size_t ws_bytes, uint32_t* R1, uint32_t* R2, void* stream);
+
+/* Adjoint of eq. (13): for each subset m at theta[m] (device, K doubles),
+ * out[3m + 0..2] = sum_i l, sum_i dl/dtheta, sum_i d2l/dtheta2 (device, 3K
+ * doubles), from doubled ranks R1, R2 (device, n each) as made by cpc_rank.
+ * theta outside the family's domain gives NaN sums for that subset. */
+int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n,
+             const int64_t* offsets, int64_t K, int32_t family, const double* theta,
+             const cpc_options_t* opt, void* workspace, size_t ws_bytes, double* out, void* stream);
+
+/* Asymptotic variance of Sec. 2.3 for each subset at theta[m] (device, K):
+ * var[m] (device, K doubles), from doubled ranks R1, R2 (device, n each). */
+int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n,
+                 const int64_t* offsets, int64_t K, int32_t family, const double* theta,
+                 const cpc_options_t* opt, void* workspace, size_t ws_bytes, double* var,
+                 void* stream);
+
+/* Message for an error code, and the thread-local detail of the last error. */
+const char* cpc_strerror(int code);
+const char* cpc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPC_H */

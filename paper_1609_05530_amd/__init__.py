@@ -1,0 +1,258 @@
+"""Partition-and-combine maximum-pseudo-likelihood copula estimation on
+AMD Instinct MI355X (arXiv:1609.05530), Python binding of libcpc.
+
+Every step runs in the HIP kernels of libcpc.so; this module only moves
+arguments: torch tensors supply device memory and the current stream.
+
+    import paper_1609_05530_amd as cpc
+    res = cpc.fit(x, y, offsets, "frank", prec="fp32c")   # x, y: cuda tensors
+    res.theta, res.var, res.status, res.combined_theta
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+import torch
+
+from ._lib import CpcError, Options, check, lib
+
+FAMILIES = {"gaussian": 0, "frank": 1, "gumbel": 2}
+PRECISIONS = {"fp64": 0, "fp32c": 1}
+TIES = {"average": 0, "first": 1}
+VARIANCES = {"ggr": 0, "invinfo": 1}
+STATUS = {0: "OK", 1: "BOUNDARY_NATURAL", 2: "BOUNDARY_BOX", 3: "DEGENERATE", 4: "NONFINITE", 5: "NOCONV",
+          6: "BADVAR"}
+
+__all__ = ["fit", "fit_batched", "rank", "eval_subsets", "variance", "LogLik", "Score", "FitResult",
+           "CpcError", "workspace_bytes", "FAMILIES", "STATUS"]
+
+
+def _code(table, v):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def _options(prec="fp64", ties="average", var="ggr", max_iter=60, tol=0.0, n_min=2, graph=False) -> Options:
+    o = Options()
+    lib().cpc_default_options(ctypes.byref(o))
+    o.prec = _code(PRECISIONS, prec)
+    o.ties = _code(TIES, ties)
+    o.var = _code(VARIANCES, var)
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.n_min = int(n_min)
+    o.flags = 1 if graph else 0
+    return o
+
+
+_handles: Dict[int, ctypes.c_void_p] = {}
+
+
+def _handle(device: torch.device) -> ctypes.c_void_p:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _handles.get(idx)
+    if h is None:
+        h = ctypes.c_void_p()
+        check(lib().cpc_create(idx, ctypes.byref(h)))
+        _handles[idx] = h
+    return h
+
+
+def _i64(a) -> np.ndarray:
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return 0
+    if t.dtype == torch.float32:
+        return 1
+    raise TypeError(f"x and y must be float32 or float64, got {t.dtype}")
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace_bytes(n: int, K: int, G: int = 1, dtype=torch.float64, **opt) -> int:
+    o = _options(**opt)
+    return int(lib().cpc_workspace_bytes(int(n), int(K), int(G), 0 if dtype == torch.float64 else 1, ctypes.byref(o)))
+
+
+def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise ValueError(f"workspace holds {workspace.numel() * workspace.element_size()} bytes, need {nbytes}")
+        return workspace
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+@dataclasses.dataclass
+class FitResult:
+    """Per-subset and per-group results (device tensors)."""
+    raw: torch.Tensor       # (K, 6) float64 view of cpc_subset_result_t
+    raw_comb: torch.Tensor  # (G, 5) float64 view of cpc_combined_t
+
+    @property
+    def theta(self): return self.raw[:, 0]
+    @property
+    def var(self): return self.raw[:, 1]
+    @property
+    def loglik(self): return self.raw[:, 2]
+    @property
+    def score(self): return self.raw[:, 3]
+    @property
+    def n(self): return self.raw[:, 4].contiguous().view(torch.int64)
+    @property
+    def iters(self): return self.raw[:, 5].contiguous().view(torch.int32)[0::2]
+    @property
+    def status(self): return self.raw[:, 5].contiguous().view(torch.int32)[1::2]
+    @property
+    def combined_theta(self): return self.raw_comb[:, 0]
+    @property
+    def combined_var(self): return self.raw_comb[:, 1]
+    @property
+    def n_used(self): return self.raw_comb[:, 2].contiguous().view(torch.int64)
+    @property
+    def n_excluded(self): return self.raw_comb[:, 3].contiguous().view(torch.int64)
+    @property
+    def combined_status(self): return self.raw_comb[:, 4].contiguous().view(torch.int32)[0::2]
+
+
+def fit(x: torch.Tensor, y: torch.Tensor, offsets, family, *, workspace: Optional[torch.Tensor] = None,
+        **opt) -> FitResult:
+    """Fit every subset [offsets[m], offsets[m+1]) with one family and combine
+    them (eq. 12-15 of arXiv:1609.05530)."""
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    return fit_batched(x, y, offsets, np.array([0, K], dtype=np.int64), [family], workspace=workspace, **opt)
+
+
+def fit_batched(x: torch.Tensor, y: torch.Tensor, offsets, group_offsets, families: Sequence, *,
+                workspace: Optional[torch.Tensor] = None, out: Optional[FitResult] = None, **opt) -> FitResult:
+    """Batched fit (eq. 16): group g = subsets [group_offsets[g], group_offsets[g+1])
+    fitted with families[g] and combined on their own."""
+    x = _dev(x, "x")
+    y = _dev(y, "y")
+    if y.dtype != x.dtype or y.shape != x.shape or x.dim() != 1:
+        raise ValueError("x and y must be 1-D tensors of equal length and dtype")
+    offsets = _i64(offsets)
+    gofs = _i64(group_offsets)
+    K = offsets.shape[0] - 1
+    G = gofs.shape[0] - 1
+    fams = np.ascontiguousarray([_code(FAMILIES, f) for f in families], dtype=np.int32)
+    o = _options(**opt)
+    dt = _dtype_code(x)
+    n = x.shape[0]
+    nbytes = int(lib().cpc_workspace_bytes(n, K, G, dt, ctypes.byref(o)))
+    ws = _workspace(nbytes, x.device, workspace)
+    if out is None:
+        out = FitResult(torch.empty((K, 6), dtype=torch.float64, device=x.device),
+                        torch.empty((G, 5), dtype=torch.float64, device=x.device))
+    check(lib().cpc_fit_batched(
+        _handle(x.device), x.data_ptr(), y.data_ptr(), dt, n, offsets.ctypes.data, K, gofs.ctypes.data, G,
+        fams.ctypes.data, ctypes.byref(o), ws.data_ptr(), ws.numel() * ws.element_size(), out.raw.data_ptr(),
+        out.raw_comb.data_ptr(), _stream(x.device)))
+    return out
+
+
+def rank(x: torch.Tensor, y: torch.Tensor, offsets, *, workspace=None, **opt):
+    """Doubled ranks R = 2 r of eq. (12) within each subset (uint32 stored in int32 tensors)."""
+    x = _dev(x, "x")
+    y = _dev(y, "y")
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    o = _options(**opt)
+    dt = _dtype_code(x)
+    n = x.shape[0]
+    ws = _workspace(int(lib().cpc_workspace_bytes(n, K, 1, dt, ctypes.byref(o))), x.device, workspace)
+    R1 = torch.empty(n, dtype=torch.int32, device=x.device)
+    R2 = torch.empty(n, dtype=torch.int32, device=x.device)
+    check(lib().cpc_rank(_handle(x.device), x.data_ptr(), y.data_ptr(), dt, n, offsets.ctypes.data, K,
+                         ctypes.byref(o), ws.data_ptr(), ws.numel(), R1.data_ptr(), R2.data_ptr(),
+                         _stream(x.device)))
+    return R1, R2
+
+
+def eval_subsets(R1: torch.Tensor, R2: torch.Tensor, offsets, family, theta: torch.Tensor, *,
+                 workspace=None, **opt) -> torch.Tensor:
+    """Per subset (sum l, sum dl/dtheta, sum d2l/dtheta2) at theta (shape (K, 3), float64)."""
+    R1 = _dev(R1, "R1")
+    R2 = _dev(R2, "R2")
+    theta = _dev(theta.to(torch.float64).contiguous(), "theta")
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    n = R1.shape[0]
+    o = _options(**opt)
+    ws = _workspace(int(lib().cpc_workspace_bytes(n, K, 1, 0, ctypes.byref(o))), R1.device, workspace)
+    out = torch.empty((K, 3), dtype=torch.float64, device=R1.device)
+    check(lib().cpc_eval(_handle(R1.device), R1.data_ptr(), R2.data_ptr(), n, offsets.ctypes.data, K,
+                         _code(FAMILIES, family), theta.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                         out.data_ptr(), _stream(R1.device)))
+    return out
+
+
+def variance(R1: torch.Tensor, R2: torch.Tensor, offsets, family, theta: torch.Tensor, *, workspace=None,
+             **opt) -> torch.Tensor:
+    """Asymptotic variance of each subset estimate at theta (Sec. 2.3)."""
+    R1 = _dev(R1, "R1")
+    R2 = _dev(R2, "R2")
+    theta = _dev(theta.to(torch.float64).contiguous(), "theta")
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    n = R1.shape[0]
+    o = _options(**opt)
+    ws = _workspace(int(lib().cpc_workspace_bytes(n, K, 1, 0, ctypes.byref(o))), R1.device, workspace)
+    out = torch.empty(K, dtype=torch.float64, device=R1.device)
+    check(lib().cpc_variance(_handle(R1.device), R1.data_ptr(), R2.data_ptr(), n, offsets.ctypes.data, K,
+                             _code(FAMILIES, family), theta.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                             out.data_ptr(), _stream(R1.device)))
+    return out
+
+
+class LogLik(torch.autograd.Function):
+    """theta (K,) -> per-subset pseudo log-likelihood eq. (13); gradient from
+    the hand-written adjoint kernel (sum of dl/dtheta)."""
+
+    @staticmethod
+    def forward(ctx, theta, R1, R2, offsets, family, prec="fp32c"):
+        out = eval_subsets(R1, R2, offsets, family, theta.detach(), prec=prec)
+        ctx.save_for_backward(out[:, 1].clone(), out[:, 2].clone())
+        ctx.meta = (R1, R2, offsets, family, prec, theta.detach())
+        return out[:, 0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        score, _ = ctx.saved_tensors
+        R1, R2, offsets, family, prec, theta = ctx.meta
+        if ctx.needs_input_grad[0] and torch.is_grad_enabled():
+            return g * Score.apply(theta, R1, R2, offsets, family, prec), None, None, None, None, None
+        return g * score, None, None, None, None, None
+
+
+class Score(torch.autograd.Function):
+    """theta (K,) -> per-subset score sum dl/dtheta; its gradient is the
+    Hessian sum d2l/dtheta2 from the same adjoint kernel (double backward)."""
+
+    @staticmethod
+    def forward(ctx, theta, R1, R2, offsets, family, prec="fp32c"):
+        out = eval_subsets(R1, R2, offsets, family, theta.detach(), prec=prec)
+        ctx.save_for_backward(out[:, 2].clone())
+        return out[:, 1].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (hess,) = ctx.saved_tensors
+        return g * hess, None, None, None, None, None

@@ -1,0 +1,523 @@
+// cpc_api.cpp — host side of the libcpc C ABI (include/cpc.h): argument
+// validation, planning (subsets -> size classes -> launch lists, largest
+// subsets first), workspace carving, and the launch sequence
+//   rank -> fit -> variance -> combine
+// for the partition-and-combine MPL estimator of arXiv:1609.05530
+// (eq. 12-16). No device memory is allocated here: every buffer comes from
+// the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "cpc.h"
+#include "kernels.h"
+
+using namespace cpc;
+
+struct cpc_context {
+  int device;
+  int magic;
+  void* plan;  // host copy of the last call's launch tables, kept alive past the call
+};
+
+static constexpr int kMagic = 0x43504331;
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_OK(expr)                                                                \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) return fail(CPC_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+struct Options {
+  int prec, ties, var, max_iter;
+  double tol;
+  int64_t n_min;
+  int flags;
+};
+
+int read_options(const cpc_options_t* o, Options& r) {
+  cpc_options_t d;
+  cpc_default_options(&d);
+  if (!o) o = &d;
+  if (o->prec != CPC_PREC_FP64 && o->prec != CPC_PREC_FP32C) return fail(CPC_E_ENUM, "unknown precision %d", o->prec);
+  if (o->ties != CPC_TIES_AVERAGE && o->ties != CPC_TIES_FIRST) return fail(CPC_E_ENUM, "unknown tie rule %d", o->ties);
+  if (o->var != CPC_VAR_GGR && o->var != CPC_VAR_INVINFO) return fail(CPC_E_ENUM, "unknown variance method %d", o->var);
+  if (o->max_iter < 1) return fail(CPC_E_OPTIONS, "max_iter must be >= 1 (got %d)", o->max_iter);
+  if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(CPC_E_OPTIONS, "tol must be finite and >= 0");
+  if (o->n_min < 0) return fail(CPC_E_OPTIONS, "n_min must be >= 0");
+  r.prec = o->prec;
+  r.ties = o->ties;
+  r.var = o->var;
+  r.max_iter = o->max_iter;
+  r.tol = o->tol > 0.0 ? o->tol : (o->prec == CPC_PREC_FP64 ? 1e-12 : 1e-9);
+  r.n_min = o->n_min < 2 ? 2 : o->n_min;
+  r.flags = o->flags;
+  return CPC_SUCCESS;
+}
+
+int check_offsets(const int64_t* offsets, int64_t K, int64_t n) {
+  if (offsets[0] != 0) return fail(CPC_E_OFFSETS, "offsets[0] = %lld, expected 0", (long long)offsets[0]);
+  for (int64_t m = 0; m < K; ++m) {
+    if (offsets[m + 1] < offsets[m])
+      return fail(CPC_E_OFFSETS, "offsets decrease at subset %lld", (long long)m);
+    if (offsets[m + 1] - offsets[m] >= ((int64_t)1 << 31))
+      return fail(CPC_E_UNSUPPORTED, "subset %lld has >= 2^31 rows", (long long)m);
+  }
+  if (offsets[K] != n) return fail(CPC_E_OFFSETS, "offsets[K] = %lld, expected n = %lld", (long long)offsets[K], (long long)n);
+  return CPC_SUCCESS;
+}
+
+int size_class(int64_t rows) {
+  for (int c = 0; c < kNumClasses; ++c)
+    if (rows <= (int64_t)kClassThreads[c] * kClassItems[c]) return c;
+  return -1;
+}
+
+// Workspace layout shared by all entry points.
+struct Layout {
+  size_t subs, order_rank, order_fit, state, gofs, r1, r2, e1, e2, l1, l2, s, total;
+};
+
+Layout layout(int64_t n, int64_t K, int64_t G) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  L.subs = take(sizeof(SubDesc) * (size_t)K);
+  L.order_rank = take(sizeof(int32_t) * (size_t)K);
+  L.order_fit = take(sizeof(int32_t) * (size_t)K);
+  L.state = take(sizeof(SubState) * (size_t)K);
+  L.gofs = take(sizeof(int64_t) * (size_t)(G + 1));
+  L.r1 = take(2 * (size_t)n);
+  L.r2 = take(2 * (size_t)n);
+  L.e1 = take(2 * (size_t)n);
+  L.e2 = take(2 * (size_t)n);
+  L.l1 = take(2 * (size_t)n);
+  L.l2 = take(2 * (size_t)n);
+  L.s = take(8 * (size_t)n);
+  L.total = off;
+  return L;
+}
+
+// A launch list: subsets of one size class (and family) in decreasing size.
+struct Bucket {
+  int cls, fam;
+  int32_t first, count;  // range in the order array
+};
+
+struct Plan {
+  std::vector<SubDesc> subs;
+  std::vector<int32_t> order_rank, order_fit;
+  std::vector<Bucket> rank_buckets, fit_buckets;
+  std::vector<int64_t> gofs;
+};
+
+int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, Plan& P) {
+  P.subs.resize((size_t)K);
+  std::vector<int> cls((size_t)K);
+  for (int64_t m = 0; m < K; ++m) {
+    const int64_t rows = offsets[m + 1] - offsets[m];
+    P.subs[m].begin = offsets[m];
+    P.subs[m].n = (int32_t)rows;
+    P.subs[m].family = (int16_t)fam_of_subset[m];
+    P.subs[m].group = 0;
+    cls[m] = size_class(rows);
+    if (cls[m] < 0)
+      return fail(CPC_E_UNSUPPORTED, "subset %lld has %lld rows; this build fits subsets of up to %d rows",
+                  (long long)m, (long long)rows, kResidentMaxRows);
+  }
+  std::vector<int32_t> ids((size_t)K);
+  for (int64_t m = 0; m < K; ++m) ids[m] = (int32_t)m;
+  // rank lists: by class, largest first
+  std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+    if (cls[a] != cls[b]) return cls[a] > cls[b];
+    return P.subs[a].n > P.subs[b].n;
+  });
+  P.order_rank = ids;
+  P.rank_buckets.clear();
+  for (int64_t i = 0; i < K;) {
+    int64_t j = i;
+    while (j < K && cls[ids[j]] == cls[ids[i]]) ++j;
+    P.rank_buckets.push_back({cls[ids[i]], 0, (int32_t)i, (int32_t)(j - i)});
+    i = j;
+  }
+  // fit / variance lists: by (class, family), largest first
+  std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
+    if (cls[a] != cls[b]) return cls[a] > cls[b];
+    if (P.subs[a].family != P.subs[b].family) return P.subs[a].family < P.subs[b].family;
+    return P.subs[a].n > P.subs[b].n;
+  });
+  P.order_fit = ids;
+  P.fit_buckets.clear();
+  for (int64_t i = 0; i < K;) {
+    int64_t j = i;
+    while (j < K && cls[ids[j]] == cls[ids[i]] && P.subs[ids[j]].family == P.subs[ids[i]].family) ++j;
+    P.fit_buckets.push_back({cls[ids[i]], P.subs[ids[i]].family, (int32_t)i, (int32_t)(j - i)});
+    i = j;
+  }
+  return CPC_SUCCESS;
+}
+
+struct Carved {
+  SubDesc* subs;
+  int32_t *order_rank, *order_fit;
+  SubState* state;
+  int64_t* gofs;
+  RowArrays rows;
+};
+
+Carved carve(void* ws, const Layout& L) {
+  unsigned char* b = (unsigned char*)ws;
+  Carved c;
+  c.subs = (SubDesc*)(b + L.subs);
+  c.order_rank = (int32_t*)(b + L.order_rank);
+  c.order_fit = (int32_t*)(b + L.order_fit);
+  c.state = (SubState*)(b + L.state);
+  c.gofs = (int64_t*)(b + L.gofs);
+  c.rows.R1 = (uint16_t*)(b + L.r1);
+  c.rows.R2 = (uint16_t*)(b + L.r2);
+  c.rows.E1 = (uint16_t*)(b + L.e1);
+  c.rows.E2 = (uint16_t*)(b + L.e2);
+  c.rows.L1 = (uint16_t*)(b + L.l1);
+  c.rows.L2 = (uint16_t*)(b + L.l2);
+  c.rows.S = (void*)(b + L.s);
+  return c;
+}
+
+int upload_tables(cpc_context* h, const Plan& P, const Carved& c, const int64_t* gofs, int64_t G,
+                  hipStream_t s) {
+  const size_t K = P.subs.size();
+  HIP_OK(hipMemcpyAsync(c.subs, P.subs.data(), sizeof(SubDesc) * K, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(c.order_rank, P.order_rank.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(c.order_fit, P.order_fit.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+  if (gofs) HIP_OK(hipMemcpyAsync(c.gofs, gofs, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+  (void)h;
+  (void)G;
+  return CPC_SUCCESS;
+}
+
+Plan& plan_of(cpc_handle_t h) { return *(Plan*)h->plan; }
+
+int check_handle(cpc_handle_t h) {
+  if (!h || h->magic != kMagic) return fail(CPC_E_HANDLE, "invalid handle");
+  return CPC_SUCCESS;
+}
+
+// The full fit path for validated arguments.
+int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
+            int64_t K, const int64_t* gofs, int64_t G, const std::vector<int32_t>& fam_of_subset,
+            const Options& o, void* ws, size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb,
+            hipStream_t s) {
+  const Layout L = layout(n, K, G);
+  if (!ws) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < L.total)
+    return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
+  Plan& P = plan_of(h);
+  int rc = make_plan(offsets, K, fam_of_subset.data(), P);
+  if (rc) return rc;
+  HIP_OK(hipSetDevice(h->device));
+  const Carved c = carve(ws, L);
+  P.gofs.assign(gofs, gofs + G + 1);
+  rc = upload_tables(h, P, c, P.gofs.data(), G, s);
+  if (rc) return rc;
+  const int kw = (dtype == CPC_F64) ? 2 : 1;
+  const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
+
+  RankParams rp;
+  std::memset(&rp, 0, sizeof(rp));
+  rp.x = x;
+  rp.y = y;
+  rp.subs = c.subs;
+  rp.mode = MODE_FIT;
+  rp.ties = o.ties;
+  rp.int_keys = 0;
+  rp.n_min = o.n_min;
+  rp.rows = c.rows;
+  rp.state = c.state;
+  for (const Bucket& b : P.rank_buckets) {
+    rp.order = c.order_rank + b.first;
+    HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
+  }
+  FitParams fp;
+  std::memset(&fp, 0, sizeof(fp));
+  fp.subs = c.subs;
+  fp.rows = c.rows;
+  fp.state = c.state;
+  fp.max_iter = o.max_iter;
+  fp.tol = o.tol;
+  for (const Bucket& b : P.fit_buckets) {
+    fp.order = c.order_fit + b.first;
+    HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
+  }
+  VarParams vp;
+  std::memset(&vp, 0, sizeof(vp));
+  vp.subs = c.subs;
+  vp.rows = c.rows;
+  vp.state = c.state;
+  vp.mode = MODE_FIT;
+  vp.var_method = o.var;
+  vp.out = (ResultOut*)out;
+  for (const Bucket& b : P.fit_buckets) {
+    vp.order = c.order_fit + b.first;
+    HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
+  }
+  HIP_OK(launch_combine((const ResultOut*)out, c.gofs, G, (CombinedOut*)comb, s));
+  return CPC_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+void cpc_default_options(cpc_options_t* o) {
+  if (!o) return;
+  o->prec = CPC_PREC_FP64;
+  o->ties = CPC_TIES_AVERAGE;
+  o->var = CPC_VAR_GGR;
+  o->max_iter = 60;
+  o->tol = 0.0;
+  o->n_min = 2;
+  o->schedule = -1;
+  o->flags = 0;
+}
+
+int cpc_create(int device, cpc_handle_t* out) {
+  if (!out) return fail(CPC_E_NULL, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIP_OK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(CPC_E_SIZE, "device %d out of range (%d devices)", device, count);
+  HIP_OK(hipSetDevice(device));
+  cpc_context* h = new cpc_context();
+  h->device = device;
+  h->magic = kMagic;
+  h->plan = new Plan();
+  *out = h;
+  return CPC_SUCCESS;
+}
+
+int cpc_destroy(cpc_handle_t h) {
+  if (int rc = check_handle(h)) return rc;
+  h->magic = 0;
+  delete (Plan*)h->plan;
+  delete h;
+  return CPC_SUCCESS;
+}
+
+size_t cpc_workspace_bytes(int64_t n, int64_t K, int64_t G, int32_t dtype, const cpc_options_t* opt) {
+  (void)dtype;
+  (void)opt;
+  if (n < 0 || K < 0 || G < 0) return 0;
+  return layout(n, K, G < 1 ? 1 : G).total;
+}
+
+int cpc_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
+            int64_t K, int32_t family, const cpc_options_t* opt, void* workspace, size_t ws_bytes,
+            cpc_subset_result_t* out, cpc_combined_t* comb, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !y || !offsets || !out || !comb) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1) return fail(CPC_E_SIZE, "K < 1");
+  if (dtype != CPC_F64 && dtype != CPC_F32) return fail(CPC_E_ENUM, "unknown dtype %d", dtype);
+  if (family < 0 || family > 2) return fail(CPC_E_ENUM, "unknown family %d", family);
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  std::vector<int32_t> fam((size_t)K, family);
+  const int64_t gofs[2] = {0, K};
+  return run_fit(h, x, y, dtype, n, offsets, K, gofs, 1, fam, o, workspace, ws_bytes, out, comb,
+                 (hipStream_t)stream);
+}
+
+int cpc_fit_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+                    const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                    const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
+                    size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !y || !offsets || !group_offsets || !family_per_group || !out || !comb)
+    return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1) return fail(CPC_E_SIZE, "K < 1");
+  if (G < 1) return fail(CPC_E_SIZE, "G < 1");
+  if (dtype != CPC_F64 && dtype != CPC_F32) return fail(CPC_E_ENUM, "unknown dtype %d", dtype);
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  if (group_offsets[0] != 0 || group_offsets[G] != K)
+    return fail(CPC_E_OFFSETS, "group_offsets must run from 0 to K");
+  std::vector<int32_t> fam((size_t)K);
+  for (int64_t g = 0; g < G; ++g) {
+    if (group_offsets[g + 1] < group_offsets[g]) return fail(CPC_E_OFFSETS, "group_offsets decrease at %lld", (long long)g);
+    if (family_per_group[g] < 0 || family_per_group[g] > 2)
+      return fail(CPC_E_ENUM, "unknown family %d for group %lld", family_per_group[g], (long long)g);
+    for (int64_t m = group_offsets[g]; m < group_offsets[g + 1]; ++m) fam[m] = family_per_group[g];
+  }
+  return run_fit(h, x, y, dtype, n, offsets, K, group_offsets, G, fam, o, workspace, ws_bytes, out, comb,
+                 (hipStream_t)stream);
+}
+
+int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
+             int64_t K, const cpc_options_t* opt, void* workspace, size_t ws_bytes, uint32_t* R1, uint32_t* R2,
+             void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !y || !offsets || !R1 || !R2) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1) return fail(CPC_E_SIZE, "K < 1");
+  if (dtype != CPC_F64 && dtype != CPC_F32) return fail(CPC_E_ENUM, "unknown dtype %d", dtype);
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  const Layout L = layout(n, K, 1);
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
+  std::vector<int32_t> fam((size_t)K, 0);
+  Plan& P = plan_of(h);
+  if (int rc = make_plan(offsets, K, fam.data(), P)) return rc;
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  const Carved c = carve(workspace, L);
+  if (int rc = upload_tables(h, P, c, nullptr, 0, s)) return rc;
+  RankParams rp;
+  std::memset(&rp, 0, sizeof(rp));
+  rp.x = x;
+  rp.y = y;
+  rp.subs = c.subs;
+  rp.mode = MODE_RANK;
+  rp.ties = o.ties;
+  rp.n_min = o.n_min;
+  rp.rows = c.rows;
+  rp.R1out = R1;
+  rp.R2out = R2;
+  rp.state = c.state;
+  const int kw = (dtype == CPC_F64) ? 2 : 1;
+  for (const Bucket& b : P.rank_buckets) {
+    rp.order = c.order_rank + b.first;
+    HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
+  }
+  return CPC_SUCCESS;
+}
+
+int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets,
+                 int64_t K, int32_t family, const double* theta, const cpc_options_t* opt, void* workspace,
+                 size_t ws_bytes, double* var, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!R1 || !R2 || !offsets || !theta || !var) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1) return fail(CPC_E_SIZE, "K < 1");
+  if (family < 0 || family > 2) return fail(CPC_E_ENUM, "unknown family %d", family);
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  const Layout L = layout(n, K, 1);
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
+  std::vector<int32_t> fam((size_t)K, family);
+  Plan& P = plan_of(h);
+  if (int rc = make_plan(offsets, K, fam.data(), P)) return rc;
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  const Carved c = carve(workspace, L);
+  if (int rc = upload_tables(h, P, c, nullptr, 0, s)) return rc;
+  // re-rank from the given ranks (integer keys): sorted positions and tie groups
+  RankParams rp;
+  std::memset(&rp, 0, sizeof(rp));
+  rp.x = R1;
+  rp.y = R2;
+  rp.subs = c.subs;
+  rp.mode = MODE_VARIANCE;
+  rp.ties = o.ties;
+  rp.int_keys = 1;
+  rp.n_min = o.n_min;
+  rp.rows = c.rows;
+  rp.state = c.state;
+  for (const Bucket& b : P.rank_buckets) {
+    rp.order = c.order_rank + b.first;
+    HIP_OK(launch_rank_wg(b.cls, 1, rp, b.count, s));
+  }
+  VarParams vp;
+  std::memset(&vp, 0, sizeof(vp));
+  vp.subs = c.subs;
+  vp.rows = c.rows;
+  vp.state = c.state;
+  vp.mode = MODE_VARIANCE;
+  vp.var_method = o.var;
+  vp.theta_in = theta;
+  vp.var_out = var;
+  const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
+  for (const Bucket& b : P.fit_buckets) {
+    vp.order = c.order_fit + b.first;
+    HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
+  }
+  return CPC_SUCCESS;
+}
+
+int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets, int64_t K,
+             int32_t family, const double* theta, const cpc_options_t* opt, void* workspace, size_t ws_bytes,
+             double* out, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!R1 || !R2 || !offsets || !theta || !out) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1) return fail(CPC_E_SIZE, "K < 1");
+  if (family < 0 || family > 2) return fail(CPC_E_ENUM, "unknown family %d", family);
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  const Layout L = layout(n, K, 1);
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < L.total) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
+  std::vector<SubDesc> subs((size_t)K);
+  for (int64_t m = 0; m < K; ++m) {
+    subs[m].begin = offsets[m];
+    subs[m].n = (int32_t)(offsets[m + 1] - offsets[m]);
+    subs[m].family = (int16_t)family;
+    subs[m].group = 0;
+  }
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  const Carved c = carve(workspace, L);
+  HIP_OK(hipMemcpyAsync(c.subs, subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
+  HIP_OK(launch_eval_wg(R1, R2, c.subs, K, family, o.prec == CPC_PREC_FP64 ? 1 : 0, theta, out, s));
+  return CPC_SUCCESS;
+}
+
+const char* cpc_strerror(int code) {
+  switch (code) {
+    case CPC_SUCCESS: return "success";
+    case CPC_E_NULL: return "a required pointer is NULL";
+    case CPC_E_SIZE: return "size out of range";
+    case CPC_E_OFFSETS: return "offsets are not a partition of the rows";
+    case CPC_E_ENUM: return "unknown enumeration value";
+    case CPC_E_WORKSPACE: return "workspace missing or too small";
+    case CPC_E_HIP: return "HIP runtime error";
+    case CPC_E_HANDLE: return "invalid handle";
+    case CPC_E_OPTIONS: return "option out of range";
+    case CPC_E_UNSUPPORTED: return "unsupported size or feature";
+    default: return "unknown error code";
+  }
+}
+
+const char* cpc_last_error(void) { return g_last_error; }
+
+}  // extern "C"

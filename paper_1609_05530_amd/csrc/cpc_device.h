@@ -1,0 +1,144 @@
+// cpc_device.h — device-side building blocks shared by the libcpc kernels:
+// order-preserving sort keys, wave / workgroup reductions and scans with a
+// fixed combination order (bitwise reproducible), compensated FP32 sums, and
+// the descriptor types the host passes in.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "row_eval.h"
+
+namespace cpc {
+
+constexpr int WAVE = 64;
+
+// One subset as the kernels see it.
+struct SubDesc {
+  int64_t begin;   // first row
+  int32_t n;       // rows (the kernels handle n < 2^31 per subset)
+  int16_t family;  // Family
+  int16_t group;   // unused by kernels (kept for alignment / debugging)
+};
+
+struct ResultOut {  // identical layout to cpc_subset_result_t
+  double theta, var, loglik, score;
+  int64_t n;
+  int32_t iters, status;
+};
+
+enum Status {
+  ST_OK = 0,
+  ST_BOUNDARY_NATURAL = 1,
+  ST_BOUNDARY_BOX = 2,
+  ST_DEGENERATE = 3,
+  ST_NONFINITE = 4,
+  ST_NOCONV = 5,
+  ST_BADVAR = 6
+};
+
+// ---------------------------------------------------------------------------
+// Order-preserving keys: unsigned comparison of the key equals numeric
+// comparison of the value; -0 and +0 map to the same key.
+__device__ __forceinline__ uint32_t key_of(float f) {
+  uint32_t b = __float_as_uint(f);
+  if (f == 0.0f) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ uint64_t key_of(double d) {
+  uint64_t b = (uint64_t)__double_as_longlong(d);
+  if (d == 0.0) b = 0ull;
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t lane = __lane_id();
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+// ---------------------------------------------------------------------------
+// Compensated (Kahan) summation. For double the compensation is kept too; it
+// is cheap and keeps FP64 sums over long subsets at full accuracy.
+template <typename T>
+struct KSum {
+  T s, c;
+  __device__ __forceinline__ KSum() : s((T)0), c((T)0) {}
+  __device__ __forceinline__ void add(T x) {
+    const T y = x - c;
+    const T t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
+// ---------------------------------------------------------------------------
+// Reductions with a fixed tree: wave butterfly, then wave partials summed in
+// wave order by thread 0. Results are returned to thread 0 only.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Sums NV doubles over the workgroup; result valid in thread 0.
+// scratch: at least W * NV doubles of LDS.
+template <int W, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) scratch[w * NV + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double a = 0.0;
+      for (int k = 0; k < W; ++k) a += scratch[k * NV + i];
+      v[i] = a;
+    }
+  }
+  __syncthreads();
+}
+
+template <int W>
+__device__ __forceinline__ long long block_sum_ll(long long v, long long* scratch) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  v = wave_sum_ll(v);
+  if (lane == 0) scratch[w] = v;
+  __syncthreads();
+  long long a = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < W; ++k) a += scratch[k];
+  __syncthreads();
+  return a;
+}
+
+// Exclusive suffix sum over the workgroup: returns sum_{t' > t} v_t'.
+// scratch: W doubles.
+template <int W>
+__device__ __forceinline__ double block_excl_suffix(double v, double* scratch) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  double incl = v;
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const double x = __shfl_down(incl, off, WAVE);
+    if (lane + off < WAVE) incl += x;
+  }
+  if (lane == 0) scratch[w] = incl;
+  __syncthreads();
+  double carry = 0.0;
+  for (int k = W - 1; k > w; --k) carry += scratch[k];
+  __syncthreads();
+  return incl + carry - v;
+}
+
+}  // namespace cpc

@@ -1,0 +1,191 @@
+// k_fit.hip — maximisation of the pseudo log-likelihood eq. (13) of
+// arXiv:1609.05530 for every subset (Sec. 2.3, "numerically"), one
+// workgroup per subset of up to 16384 rows. The subset's rows stay in LDS
+// for the whole solve (packed doubled ranks; for Gumbel the theta-free
+// log(-log u), log(-log v) instead):
+//   - Spearman's rho of the ranks (exact integer sums) seeds the solve;
+//   - Gaussian: one pass for S+ = sum (z1 + z2)^2 and S- = sum (z1 - z2)^2,
+//     then the FP64 scalar solve on those sufficient statistics;
+//   - Frank / Gumbel: safeguarded Newton passes; each pass sums the per-row
+//     score and Hessian (FP32 rows with Kahan sums in the FP32-compensated
+//     mode, FP64 rows near the family boundaries or in the FP64 mode), the
+//     workgroup reduces them in a fixed order and thread 0 takes the FP64
+//     Newton step.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "solver.h"
+
+namespace cpc {
+
+template <int CAP, typename CT, int FAM>
+struct FitSmem {
+  // Gumbel keeps (log(-log u), log(-log v)) per row when they fit
+  static constexpr bool GC = FAM == FAM_GUMBEL && 2 * sizeof(CT) * CAP <= 144 * 1024;
+  uint32_t rr[GC ? 1 : CAP];
+  CT lx[GC ? CAP : 1];
+  CT ly[GC ? CAP : 1];
+};
+
+template <int T, int CAP, typename CT, int FAM>
+__global__ void __launch_bounds__(T) k_fit_wg(FitParams P) {
+  constexpr int W = T / WAVE;
+  using SM = FitSmem<CAP, CT, FAM>;
+  __shared__ SM sm;
+  __shared__ double red[W * 3];
+  __shared__ NewtonState nst;
+  __shared__ double bc[4];
+  const int tid = threadIdx.x;
+  const int sid = P.order[blockIdx.x];
+  if (P.state[sid].status != ST_OK) return;  // uniform: set by the rank kernel
+  const SubDesc sd = P.subs[sid];
+  const int n = sd.n;
+  const uint16_t* R1 = P.rows.R1 + sd.begin;
+  const uint16_t* R2 = P.rows.R2 + sd.begin;
+  const uint32_t twon1 = 2u * (uint32_t)(n + 1);
+  const CT inv = (CT)1 / (CT)twon1;
+  const double dn = (double)n;
+
+  long long sacc = 0;
+  for (int i = tid; i < n; i += T) {
+    const uint32_t a = R1[i], b = R2[i];
+    sacc += ((long long)a - (n + 1)) * ((long long)b - (n + 1));
+    if constexpr (SM::GC) {
+      gumbel_lxy<CT>(a, b, twon1, inv, sm.lx[i], sm.ly[i]);
+    } else {
+      sm.rr[i] = a | (b << 16);
+    }
+  }
+  const long long S = block_sum_ll<W>(sacc, (long long*)red);
+  if (tid == 0) {
+    const double rho_s = 3.0 * (double)S / (dn * (dn * dn - 1.0));
+    newton_init(nst, FAM, start_theta(FAM, rho_s));
+    bc[0] = rho_s;
+  }
+  __syncthreads();
+
+  if constexpr (FAM == FAM_GAUSSIAN) {
+    // z in double for near-perfect dependence (S- then needs the digits)
+    const bool zd = sizeof(CT) == 4 && fabs(bc[0]) > 0.98;
+    double v[2];
+    if (zd) {
+      KSum<double> kp, km;
+      for (int i = tid; i < n; i += T) {
+        const uint32_t r = sm.rr[i];
+        double z1, z2;
+        gauss_z<double>(r & 0xFFFFu, r >> 16, twon1, z1, z2);
+        kp.add((z1 + z2) * (z1 + z2));
+        km.add((z1 - z2) * (z1 - z2));
+      }
+      v[0] = kp.value();
+      v[1] = km.value();
+    } else {
+      KSum<CT> kp, km;
+      for (int i = tid; i < n; i += T) {
+        const uint32_t r = sm.rr[i];
+        CT z1, z2;
+        gauss_z<CT>(r & 0xFFFFu, r >> 16, twon1, z1, z2);
+        kp.add((z1 + z2) * (z1 + z2));
+        km.add((z1 - z2) * (z1 - z2));
+      }
+      v[0] = kp.value();
+      v[1] = km.value();
+    }
+    block_sum<W, 2>(v, red);
+    if (tid == 0) {
+      gauss_solve(nst, dn, v[0], v[1], 1e-14);
+      SubState& st = P.state[sid];
+      st.theta = nst.theta;
+      st.iters = nst.it;
+      st.status = nst.status;
+      st.Sp = v[0];
+      st.Sm = v[1];
+    }
+    return;
+  } else {
+    for (;;) {
+      const double th = nst.theta;
+      const Consts<CT> c = make_consts<CT>(FAM, th);
+      double v[3];
+      double noise;
+      if (FAM == FAM_FRANK && sizeof(CT) == 4 && c.use_d) {
+        // FP64 rows (Frank near independence or far out)
+        const Consts<double> cd = make_consts<double>(FAM, th);
+        const double invd = 1.0 / (double)twon1;
+        KSum<double> ks, kh;
+        double s2 = 0.0;
+        for (int i = tid; i < n; i += T) {
+          const uint32_t r = sm.rr[i];
+          double s, h;
+          frank_rsh<double>(cd, r & 0xFFFFu, r >> 16, twon1, invd, s, h);
+          ks.add(s);
+          kh.add(h);
+          s2 += s * s;
+        }
+        v[0] = ks.value();
+        v[1] = kh.value();
+        v[2] = s2;
+        noise = 16.0 * 1.1102230246251565e-16;
+      } else {
+        KSum<CT> ks, kh;
+        CT s2 = (CT)0;
+        for (int i = tid; i < n; i += T) {
+          CT s, h;
+          if constexpr (FAM == FAM_FRANK) {
+            const uint32_t r = sm.rr[i];
+            frank_rsh<CT>(c, r & 0xFFFFu, r >> 16, twon1, inv, s, h);
+          } else if constexpr (SM::GC) {
+            gumbel_sh(c.gk, sm.lx[i], sm.ly[i], s, h);
+          } else {
+            const uint32_t r = sm.rr[i];
+            CT lx, ly;
+            gumbel_lxy<CT>(r & 0xFFFFu, r >> 16, twon1, inv, lx, ly);
+            gumbel_sh(c.gk, lx, ly, s, h);
+          }
+          ks.add(s);
+          kh.add(h);
+          s2 += s * s;
+        }
+        v[0] = ks.value();
+        v[1] = kh.value();
+        v[2] = (double)s2;
+        noise = 16.0 * (sizeof(CT) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
+      }
+      block_sum<W, 3>(v, red);
+      if (tid == 0) newton_update(nst, FAM, v[0], v[1], v[2], P.tol, noise, P.max_iter);
+      __syncthreads();
+      if (nst.done) break;
+    }
+    if (tid == 0) {
+      SubState& st = P.state[sid];
+      st.theta = nst.theta;
+      st.iters = nst.it;
+      st.status = nst.status;
+      st.Sp = 0.0;
+      st.Sm = 0.0;
+    }
+  }
+}
+
+template <int T, int CAP, typename CT>
+static hipError_t launch_t(int fam, const FitParams& p, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  switch (fam) {
+    case FAM_GAUSSIAN: hipLaunchKernelGGL((k_fit_wg<T, CAP, CT, FAM_GAUSSIAN>), dim3(grid), dim3(T), 0, s, p); break;
+    case FAM_FRANK: hipLaunchKernelGGL((k_fit_wg<T, CAP, CT, FAM_FRANK>), dim3(grid), dim3(T), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_fit_wg<T, CAP, CT, FAM_GUMBEL>), dim3(grid), dim3(T), 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_wg(int cls, int fam, int fp64, const FitParams& p, int grid, hipStream_t s) {
+  switch (cls) {
+    case 0: return fp64 ? launch_t<64, 512, double>(fam, p, grid, s) : launch_t<64, 512, float>(fam, p, grid, s);
+    case 1: return fp64 ? launch_t<256, 2048, double>(fam, p, grid, s) : launch_t<256, 2048, float>(fam, p, grid, s);
+    case 2: return fp64 ? launch_t<512, 8192, double>(fam, p, grid, s) : launch_t<512, 8192, float>(fam, p, grid, s);
+    case 3: return fp64 ? launch_t<1024, 16384, double>(fam, p, grid, s) : launch_t<1024, 16384, float>(fam, p, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace cpc

@@ -1,0 +1,63 @@
+"""The C-ABI library: it loads without a GPU, exports every entry point the
+header declares, and rejects misuse on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "cpc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1609_05530_amd import _lib
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(L, name), name
+    from paper_1609_05530_amd._lib import SIGNATURES
+    assert set(SIGNATURES) == set(names)
+
+
+def test_struct_sizes_match_header():
+    from paper_1609_05530_amd._lib import Options
+    assert ctypes.sizeof(Options) == 40
+
+
+def test_defaults_and_workspace(L):
+    from paper_1609_05530_amd._lib import Options
+    o = Options()
+    L.cpc_default_options(ctypes.byref(o))
+    assert (o.prec, o.ties, o.var, o.max_iter, o.n_min, o.schedule) == (0, 0, 0, 60, 2, -1)
+    a = L.cpc_workspace_bytes(1000, 10, 1, 0, ctypes.byref(o))
+    b = L.cpc_workspace_bytes(2000, 10, 1, 0, ctypes.byref(o))
+    assert 0 < a < b
+    assert L.cpc_workspace_bytes(-1, 10, 1, 0, ctypes.byref(o)) == 0
+
+
+def test_errors_before_any_device_call(L):
+    import numpy as np
+    from paper_1609_05530_amd._lib import Options
+    o = Options()
+    L.cpc_default_options(ctypes.byref(o))
+    off = np.array([0, 5, 10], dtype=np.int64)
+    rc = L.cpc_fit(None, 1, 1, 0, 10, off.ctypes.data, 2, 0, ctypes.byref(o), 1, 1 << 20, 1, 1, None)
+    assert rc == -7  # CPC_E_HANDLE
+    assert b"handle" in L.cpc_last_error()
+    for code in range(-9, 1):
+        assert len(L.cpc_strerror(code)) > 0
+    h = ctypes.c_void_p()
+    assert L.cpc_create(0, None) == -1  # CPC_E_NULL
