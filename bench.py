@@ -1,0 +1,201 @@
+"""Benchmark of the partition-and-combine MPL copula estimator (arXiv:1609.05530)
+on one MI355X.
+
+One step = one cpc_fit_batched over the whole workload: ranks (eq. 12), the
+maximisation of eq. (13) for every subset, the Sec. 2.3 variances and the
+eq. (15)/(16) combination per group. Inputs are resident in HBM before the
+timed region. Prints one JSON line.
+
+Default workload (the shape the headline metric is quoted on, n = 1e7 per
+setting): Frank theta in {-10, -1, 0.01, 1, 10, 30} and Gaussian rho in
+{-0.95, 0, 0.95}, each n = 10,000,000 FP32 pairs in K = 1000 subsets with
+sizes ~ U[5000, 15000] renormalised; 9 groups, 9000 subset fits per step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# VALU issue slots per row of one Newton pass (per score + Hessian row
+# evaluation), counted from the FP32 row formulas: transcendentals (exp, log,
+# reciprocal) issue at a quarter of the full rate and count 4 slots each.
+#   Frank (|theta| >= 2):  exp x2, rcp x2 (1/b, 1/D)  -> 16 + 30 FMA/mul/add
+#   Frank (|theta| <  2):  expm1 x2, rcp x1           -> 12 + 34
+#   Gumbel:                exp x2, log x1, rcp x2      -> 20 + 40
+#   Gaussian (one pass):   AS 241 x2 (rcp + ~10 FMA)  -> 8 + 23
+SLOTS_PER_ROW_PASS = {"frank": 46.0, "gumbel": 60.0, "gaussian": 31.0}
+PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock (non-packed FP32 VALU)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="fp32c", choices=["fp32c", "fp64"])
+    ap.add_argument("--n", type=int, default=10_000_000, help="rows per setting")
+    ap.add_argument("--K", type=int, default=1000, help="subsets per setting")
+    ap.add_argument("--settings", default="all", help="'all' or a comma list of indices into the 9 settings")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=3, help="subsets per setting in the CPU-baseline sample")
+    ap.add_argument("--profile", action="store_true", help="short run for a profiler (no oracle, no checks)")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build targets a single MI355X "
+              "(subsets are independent; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1609_05530_amd as cpc
+    import synth
+
+    settings = synth.CONFIG5 if a.settings == "all" else [synth.CONFIG5[int(i)] for i in a.settings.split(",")]
+    t0 = time.time()
+    w = synth.config5(settings=settings, n=a.n, K=a.K)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(w.x).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    fams = w.families
+    K, G, n = w.K, w.G, w.n
+    ws = torch.empty(cpc.workspace_bytes(n, K, G, dtype=x.dtype, prec=a.prec), dtype=torch.uint8, device=dev)
+    out = cpc.FitResult(torch.empty((K, 6), dtype=torch.float64, device=dev),
+                        torch.empty((G, 5), dtype=torch.float64, device=dev))
+    opt = dict(prec=a.prec)
+
+    def step(**kw):
+        cpc.fit_batched(x, y, w.offsets, w.group_offsets, fams, workspace=ws, out=out, **opt, **kw)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(a.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = ev0.elapsed_time(ev1) / a.steps
+
+    # per-phase durations (HIP events recorded by the library on the launch stream)
+    phases = np.zeros(4)
+    nph = max(3, min(a.steps, 10))
+    for _ in range(nph):
+        step(phase_times=True)
+        phases += np.array(cpc.phase_times(0))
+    phases /= nph
+
+    theta = out.theta.cpu().numpy()
+    iters = out.iters.cpu().numpy()
+    status = out.status.cpu().numpy()
+    nsub = out.n.cpu().numpy()
+    fam_of = np.empty(K, dtype=object)
+    for g in range(G):
+        fam_of[w.group_offsets[g]:w.group_offsets[g + 1]] = fams[g]
+
+    # algorithmic work of the fit kernels: rows x Newton passes x slots per row-pass
+    slots = 0.0
+    obs_evals = 0.0
+    for fam in set(fams):
+        sel = fam_of == fam
+        passes = iters[sel].astype(np.float64)
+        slots += float(np.sum(nsub[sel] * passes)) * SLOTS_PER_ROW_PASS[fam]
+        obs_evals += float(np.sum(nsub[sel] * (passes + 1.0)))  # + the variance pass
+    fit_s = phases[1] / 1e3
+    achieved = slots / fit_s if fit_s > 0 else 0.0
+
+    line = {
+        "metric": "subset-fits/sec (batched MPL copula fits, n=1e7 per setting)",
+        "value": K / (ms_step / 1e3),
+        "unit": "subset-fits/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.prec == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{G} settings x n={a.n} FP32 pairs, K={a.K} subsets each, sizes U[5000,15000] renormalised",
+            "settings": [f"{f} {t:g}" for f, t in settings],
+            "subset_fits_per_step": K,
+            "rows_per_step": n,
+            "precision": a.prec,
+        },
+        "obs_evals_per_s": obs_evals / (ms_step / 1e3),
+        "phase_ms": {"rank": phases[0], "fit": phases[1], "variance": phases[2], "combine": phases[3]},
+        "newton_passes_mean": float(np.mean(iters[status == 0])) if np.any(status == 0) else None,
+        "status_counts": {str(int(s)): int(np.sum(status == s)) for s in np.unique(status)},
+        "wall_s_timed": wall,
+        "gen_s": gen_s,
+        "roofline": {
+            "kernel": "k_fit_wg (Newton passes of eq. 13)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_SLOTS / 1e12,
+            "unit": "T VALU lane-slots/s",
+            "frac": achieved / PEAK_LANE_SLOTS,
+            "traffic": None,
+        },
+    }
+
+    if not a.profile:
+        import oracle.oracle as O
+        # error vs the FP64 oracle and the oracle's own rate on a bounded sample
+        pick = []
+        for g in range(G):
+            m0 = int(w.group_offsets[g])
+            pick.extend(range(m0, m0 + a.cpu_sample))
+        xs = [w.x[w.offsets[m]:w.offsets[m + 1]].astype(np.float64) for m in pick]
+        ys = [w.y[w.offsets[m]:w.offsets[m + 1]].astype(np.float64) for m in pick]
+        sizes = np.array([len(v) for v in xs])
+        off = synth.offsets_from_sizes(sizes)
+        gofs = np.arange(0, len(pick) + 1, a.cpu_sample, dtype=np.int64)
+        nt = O.num_threads(0)
+        t0 = time.perf_counter()
+        sub, _ = O.fit(np.concatenate(xs), np.concatenate(ys), off, fams, gofs, nthreads=nt)
+        cpu_s = time.perf_counter() - t0
+        ref = sub["theta"]
+        got = theta[pick]
+        ok = (sub["status"] == 0) & (status[pick] == 0)
+        floor = np.array([0.1 if fam_of[m] == "frank" else 1e-3 for m in pick])
+        rel = np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), floor[ok])
+        vrel = np.abs(out.var.cpu().numpy()[pick][ok] / sub["var"][ok] - 1.0)
+        line["err_vs_oracle"] = {
+            "subsets_checked": int(ok.sum()),
+            "theta_max_rel": float(rel.max(initial=0)),
+            "theta_median_rel": float(np.median(rel)) if rel.size else None,
+            "var_max_rel": float(vrel.max(initial=0)),
+            "status_match": bool(np.array_equal(sub["status"], status[pick])),
+        }
+        line["cpu_baseline"] = {
+            "value": len(pick) / cpu_s,
+            "unit": "subset-fits/s",
+            "cores": nt,
+            "kind": "oracle",
+            "sample": f"{len(pick)} subsets ({a.cpu_sample} per setting, {int(sizes.sum())} rows), FP64 oracle, "
+                      f"OpenMP over subsets, {cpu_s:.1f} s",
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

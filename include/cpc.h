@@ -104,6 +104,7 @@ typedef struct {
 } cpc_options_t;
 
 #define CPC_FLAG_GRAPH 1
+#define CPC_FLAG_PHASE_TIMES 2 /* record hipEvents between the phases of a fit */
 
 /* 48 bytes, natural alignment. */
 typedef struct {
@@ -183,6 +184,13 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
                  const int64_t* offsets, int64_t K, int32_t family, const double* theta,
                  const cpc_options_t* opt, void* workspace, size_t ws_bytes, double* var,
                  void* stream);
+
+/* Durations (milliseconds) of the phases of the handle's last cpc_fit /
+ * cpc_fit_batched call made with CPC_FLAG_PHASE_TIMES: ms[0] ranks (eq. 12),
+ * ms[1] maximisation of eq. (13), ms[2] variance (Sec. 2.3), ms[3] combine
+ * (eq. 15). Measured with hipEvents on the call's stream; blocks until the
+ * last phase has completed. CPC_E_OPTIONS if no such call was made. */
+int cpc_phase_times(cpc_handle_t h, float* ms);
 
 /* Message for an error code, and the thread-local detail of the last error. */
 const char* cpc_strerror(int code);

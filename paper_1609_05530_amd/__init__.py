@@ -34,7 +34,8 @@ def _code(table, v):
     return table[v] if isinstance(v, str) else int(v)
 
 
-def _options(prec="fp64", ties="average", var="ggr", max_iter=60, tol=0.0, n_min=2, graph=False) -> Options:
+def _options(prec="fp64", ties="average", var="ggr", max_iter=60, tol=0.0, n_min=2, graph=False,
+             phase_times=False) -> Options:
     o = Options()
     lib().cpc_default_options(ctypes.byref(o))
     o.prec = _code(PRECISIONS, prec)
@@ -43,8 +44,17 @@ def _options(prec="fp64", ties="average", var="ggr", max_iter=60, tol=0.0, n_min
     o.max_iter = int(max_iter)
     o.tol = float(tol)
     o.n_min = int(n_min)
-    o.flags = 1 if graph else 0
+    o.flags = (1 if graph else 0) | (2 if phase_times else 0)
     return o
+
+
+def phase_times(device=None):
+    """Milliseconds of (rank, fit, variance, combine) of the last fit made with
+    phase_times=True on this device (HIP events on the fit's stream)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    ms = (ctypes.c_float * 4)()
+    check(lib().cpc_phase_times(_handle(dev), ms))
+    return [float(v) for v in ms]
 
 
 _handles: Dict[int, ctypes.c_void_p] = {}
@@ -114,21 +124,21 @@ class FitResult:
     @property
     def score(self): return self.raw[:, 3]
     @property
-    def n(self): return self.raw[:, 4].contiguous().view(torch.int64)
+    def n(self): return self.raw.view(torch.int64)[:, 4]
     @property
-    def iters(self): return self.raw[:, 5].contiguous().view(torch.int32)[0::2]
+    def iters(self): return self.raw.view(torch.int32)[:, 10]
     @property
-    def status(self): return self.raw[:, 5].contiguous().view(torch.int32)[1::2]
+    def status(self): return self.raw.view(torch.int32)[:, 11]
     @property
     def combined_theta(self): return self.raw_comb[:, 0]
     @property
     def combined_var(self): return self.raw_comb[:, 1]
     @property
-    def n_used(self): return self.raw_comb[:, 2].contiguous().view(torch.int64)
+    def n_used(self): return self.raw_comb.view(torch.int64)[:, 2]
     @property
-    def n_excluded(self): return self.raw_comb[:, 3].contiguous().view(torch.int64)
+    def n_excluded(self): return self.raw_comb.view(torch.int64)[:, 3]
     @property
-    def combined_status(self): return self.raw_comb[:, 4].contiguous().view(torch.int32)[0::2]
+    def combined_status(self): return self.raw_comb.view(torch.int32)[:, 8]
 
 
 def fit(x: torch.Tensor, y: torch.Tensor, offsets, family, *, workspace: Optional[torch.Tensor] = None,
@@ -223,23 +233,22 @@ def variance(R1: torch.Tensor, R2: torch.Tensor, offsets, family, theta: torch.T
 
 
 class LogLik(torch.autograd.Function):
-    """theta (K,) -> per-subset pseudo log-likelihood eq. (13); gradient from
-    the hand-written adjoint kernel (sum of dl/dtheta)."""
+    """theta (K,) -> per-subset pseudo log-likelihood eq. (13); its gradient is
+    the score from the hand-written adjoint kernel (twice differentiable:
+    the score's own gradient is the Hessian from the same kernel)."""
 
     @staticmethod
     def forward(ctx, theta, R1, R2, offsets, family, prec="fp32c"):
         out = eval_subsets(R1, R2, offsets, family, theta.detach(), prec=prec)
-        ctx.save_for_backward(out[:, 1].clone(), out[:, 2].clone())
-        ctx.meta = (R1, R2, offsets, family, prec, theta.detach())
+        ctx.save_for_backward(theta)
+        ctx.meta = (R1, R2, offsets, family, prec)
         return out[:, 0].clone()
 
     @staticmethod
     def backward(ctx, g):
-        score, _ = ctx.saved_tensors
-        R1, R2, offsets, family, prec, theta = ctx.meta
-        if ctx.needs_input_grad[0] and torch.is_grad_enabled():
-            return g * Score.apply(theta, R1, R2, offsets, family, prec), None, None, None, None, None
-        return g * score, None, None, None, None, None
+        (theta,) = ctx.saved_tensors
+        R1, R2, offsets, family, prec = ctx.meta
+        return g * Score.apply(theta, R1, R2, offsets, family, prec), None, None, None, None, None
 
 
 class Score(torch.autograd.Function):

@@ -43,6 +43,7 @@ SIGNATURES = {
     "cpc_rank": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, ctypes.POINTER(Options), _P, _SZ, _P, _P, _P]),
     "cpc_eval": (_I32, [_P, _P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P]),
     "cpc_variance": (_I32, [_P, _P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P]),
+    "cpc_phase_times": (_I32, [_P, ctypes.POINTER(ctypes.c_float)]),
     "cpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cpc_last_error": (ctypes.c_char_p, []),
 }

@@ -22,7 +22,9 @@ using namespace cpc;
 struct cpc_context {
   int device;
   int magic;
-  void* plan;  // host copy of the last call's launch tables, kept alive past the call
+  void* plan;               // host copy of the last call's launch tables, kept alive past the call
+  hipEvent_t ev[5];         // phase boundaries of the last fit (CPC_FLAG_PHASE_TIMES)
+  int have_times;
 };
 
 static constexpr int kMagic = 0x43504331;
@@ -239,6 +241,8 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   if (rc) return rc;
   HIP_OK(hipSetDevice(h->device));
   const Carved c = carve(ws, L);
+  const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
+  h->have_times = 0;
   P.gofs.assign(gofs, gofs + G + 1);
   rc = upload_tables(h, P, c, P.gofs.data(), G, s);
   if (rc) return rc;
@@ -256,10 +260,12 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   rp.n_min = o.n_min;
   rp.rows = c.rows;
   rp.state = c.state;
+  if (timed) HIP_OK(hipEventRecord(h->ev[0], s));
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
     HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
   }
+  if (timed) HIP_OK(hipEventRecord(h->ev[1], s));
   FitParams fp;
   std::memset(&fp, 0, sizeof(fp));
   fp.subs = c.subs;
@@ -271,6 +277,7 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
     fp.order = c.order_fit + b.first;
     HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
   }
+  if (timed) HIP_OK(hipEventRecord(h->ev[2], s));
   VarParams vp;
   std::memset(&vp, 0, sizeof(vp));
   vp.subs = c.subs;
@@ -283,7 +290,12 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
     vp.order = c.order_fit + b.first;
     HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
   }
+  if (timed) HIP_OK(hipEventRecord(h->ev[3], s));
   HIP_OK(launch_combine((const ResultOut*)out, c.gofs, G, (CombinedOut*)comb, s));
+  if (timed) {
+    HIP_OK(hipEventRecord(h->ev[4], s));
+    h->have_times = 1;
+  }
   return CPC_SUCCESS;
 }
 
@@ -314,6 +326,15 @@ int cpc_create(int device, cpc_handle_t* out) {
   h->device = device;
   h->magic = kMagic;
   h->plan = new Plan();
+  h->have_times = 0;
+  for (int i = 0; i < 5; ++i) {
+    if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->ev[j]);
+      delete (Plan*)h->plan;
+      delete h;
+      return fail(CPC_E_HIP, "hipEventCreate failed");
+    }
+  }
   *out = h;
   return CPC_SUCCESS;
 }
@@ -321,6 +342,7 @@ int cpc_create(int device, cpc_handle_t* out) {
 int cpc_destroy(cpc_handle_t h) {
   if (int rc = check_handle(h)) return rc;
   h->magic = 0;
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(h->ev[i]);
   delete (Plan*)h->plan;
   delete h;
   return CPC_SUCCESS;
@@ -499,6 +521,15 @@ int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, 
   const Carved c = carve(workspace, L);
   HIP_OK(hipMemcpyAsync(c.subs, subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
   HIP_OK(launch_eval_wg(R1, R2, c.subs, K, family, o.prec == CPC_PREC_FP64 ? 1 : 0, theta, out, s));
+  return CPC_SUCCESS;
+}
+
+int cpc_phase_times(cpc_handle_t h, float* ms) {
+  if (int rc = check_handle(h)) return rc;
+  if (!ms) return fail(CPC_E_NULL, "ms is NULL");
+  if (!h->have_times) return fail(CPC_E_OPTIONS, "no fit with CPC_FLAG_PHASE_TIMES on this handle");
+  HIP_OK(hipEventSynchronize(h->ev[4]));
+  for (int i = 0; i < 4; ++i) HIP_OK(hipEventElapsedTime(&ms[i], h->ev[i], h->ev[i + 1]));
   return CPC_SUCCESS;
 }
 

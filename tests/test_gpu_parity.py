@@ -61,9 +61,11 @@ def compare(g, sub, comb, prec, fam, label):
     use = (st == 0) | (st == 1)
     vt = 1e-6 if prec == "fp64" else 1e-4
     dvar = np.abs(g["var"][use] / sub["var"][use] - 1.0)
-    n = np.maximum(sub["n"][ok], 1)
+    # log-likelihoods of fitted subsets (at a box edge the oracle's per-row
+    # quadratic form cancels to ~1e-7 and is not a reference there)
+    n = np.maximum(sub["n"][use], 1)
     lt = 1e-9 if prec == "fp64" else 2e-5
-    dll = np.abs(g["loglik"][ok] - sub["loglik"][ok]) / n
+    dll = np.abs(g["loglik"][use] - sub["loglik"][use]) / n
     ct = 1e-6 if prec == "fp64" else 1e-5
     dc = np.abs(g["combined_theta"] - comb["theta"]) / np.maximum(np.abs(comb["theta"]), floor)
     print(f"[parity] {label}: max dtheta {dth.max(initial=0):.2e} dvar {dvar.max(initial=0):.2e} "
