@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libcpc.so")
 HOSTMATH = os.path.join(HERE, "libcpc_hostmath.so")
 
 ARCH = "gfx950"
-SOURCES = ["cpc_api.cpp", "k_rank.hip", "k_fit.hip", "k_var.hip", "k_eval.hip", "k_combine.hip"]
+SOURCES = ["cpc_api.cpp", "k_rank.hip", "k_fit.hip", "k_var.hip", "k_big.hip", "k_eval.hip", "k_combine.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -25,6 +25,7 @@ struct cpc_context {
   void* plan;               // host copy of the last call's launch tables, kept alive past the call
   hipEvent_t ev[5];         // phase boundaries of the last fit (CPC_FLAG_PHASE_TIMES)
   int have_times;
+  int* pending_host;        // pinned: subsets of the streaming path still iterating
 };
 
 static constexpr int kMagic = 0x43504331;
@@ -96,8 +97,13 @@ int size_class(int64_t rows) {
 
 // Workspace layout shared by all entry points.
 struct Layout {
-  size_t subs, order_rank, order_fit, state, gofs, r1, r2, e1, e2, l1, l2, s, total;
+  size_t subs, order_rank, order_fit, state, gofs, r1, r2, e1, e2, l1, l2, s;
+  // streaming path (subsets above kResidentMaxRows)
+  size_t bsegs, btiles, bflags, bgsum, bst, bpending, bhist, bpart, btsum, brow32[12], brow64[5];
+  size_t total;
 };
+
+int64_t max_tiles(int64_t n, int64_t K) { return n / kBigTile + K + 1; }
 
 Layout layout(int64_t n, int64_t K, int64_t G) {
   Layout L;
@@ -119,6 +125,18 @@ Layout layout(int64_t n, int64_t K, int64_t G) {
   L.l1 = take(2 * (size_t)n);
   L.l2 = take(2 * (size_t)n);
   L.s = take(8 * (size_t)n);
+  const int64_t T = max_tiles(n, K);
+  L.bsegs = take(sizeof(BigSeg) * (size_t)K);
+  L.btiles = take(sizeof(BigTile) * (size_t)T);
+  L.bflags = take(sizeof(int32_t) * (size_t)K);
+  L.bgsum = take(2 * sizeof(double) * (size_t)K);
+  L.bst = take(sizeof(NewtonState) * (size_t)K);
+  L.bpending = take(sizeof(int));
+  L.bhist = take(256 * sizeof(uint32_t) * (size_t)T);
+  L.bpart = take(5 * sizeof(double) * (size_t)T);
+  L.btsum = take(2 * sizeof(double) * (size_t)T);
+  for (int i = 0; i < 12; ++i) L.brow32[i] = take(4 * (size_t)n);
+  for (int i = 0; i < 5; ++i) L.brow64[i] = take(8 * (size_t)n);
   L.total = off;
   return L;
 }
@@ -134,11 +152,16 @@ struct Plan {
   std::vector<int32_t> order_rank, order_fit;
   std::vector<Bucket> rank_buckets, fit_buckets;
   std::vector<int64_t> gofs;
+  std::vector<BigSeg> bsegs;
+  std::vector<BigTile> btiles;
 };
 
 int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, Plan& P) {
   P.subs.resize((size_t)K);
+  P.bsegs.clear();
+  P.btiles.clear();
   std::vector<int> cls((size_t)K);
+  int64_t roff = 0;
   for (int64_t m = 0; m < K; ++m) {
     const int64_t rows = offsets[m + 1] - offsets[m];
     P.subs[m].begin = offsets[m];
@@ -146,12 +169,33 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
     P.subs[m].family = (int16_t)fam_of_subset[m];
     P.subs[m].group = 0;
     cls[m] = size_class(rows);
-    if (cls[m] < 0)
-      return fail(CPC_E_UNSUPPORTED, "subset %lld has %lld rows; this build fits subsets of up to %d rows",
-                  (long long)m, (long long)rows, kResidentMaxRows);
+    if (cls[m] < 0) {  // streaming path
+      BigSeg b;
+      b.begin = offsets[m];
+      b.n = rows;
+      b.roff = roff;
+      b.tile0 = (int64_t)P.btiles.size();
+      b.ntiles = (int32_t)((rows + kBigTile - 1) / kBigTile);
+      b.sid = (int32_t)m;
+      b.family = fam_of_subset[m];
+      b.pad = 0;
+      const int32_t g = (int32_t)P.bsegs.size();
+      for (int64_t st = 0; st < rows; st += kBigTile) {
+        BigTile t;
+        t.seg = g;
+        t.start = st;
+        t.count = (int32_t)std::min<int64_t>(kBigTile, rows - st);
+        P.btiles.push_back(t);
+      }
+      P.bsegs.push_back(b);
+      roff += rows;
+    }
   }
-  std::vector<int32_t> ids((size_t)K);
-  for (int64_t m = 0; m < K; ++m) ids[m] = (int32_t)m;
+  std::vector<int32_t> ids;
+  ids.reserve((size_t)K);
+  for (int64_t m = 0; m < K; ++m)
+    if (cls[m] >= 0) ids.push_back((int32_t)m);
+  const int64_t KR = (int64_t)ids.size();
   // rank lists: by class, largest first
   std::stable_sort(ids.begin(), ids.end(), [&](int32_t a, int32_t b) {
     if (cls[a] != cls[b]) return cls[a] > cls[b];
@@ -159,9 +203,9 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
   });
   P.order_rank = ids;
   P.rank_buckets.clear();
-  for (int64_t i = 0; i < K;) {
+  for (int64_t i = 0; i < KR;) {
     int64_t j = i;
-    while (j < K && cls[ids[j]] == cls[ids[i]]) ++j;
+    while (j < KR && cls[ids[j]] == cls[ids[i]]) ++j;
     P.rank_buckets.push_back({cls[ids[i]], 0, (int32_t)i, (int32_t)(j - i)});
     i = j;
   }
@@ -173,9 +217,9 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
   });
   P.order_fit = ids;
   P.fit_buckets.clear();
-  for (int64_t i = 0; i < K;) {
+  for (int64_t i = 0; i < KR;) {
     int64_t j = i;
-    while (j < K && cls[ids[j]] == cls[ids[i]] && P.subs[ids[j]].family == P.subs[ids[i]].family) ++j;
+    while (j < KR && cls[ids[j]] == cls[ids[i]] && P.subs[ids[j]].family == P.subs[ids[i]].family) ++j;
     P.fit_buckets.push_back({cls[ids[i]], P.subs[ids[i]].family, (int32_t)i, (int32_t)(j - i)});
     i = j;
   }
@@ -188,6 +232,8 @@ struct Carved {
   SubState* state;
   int64_t* gofs;
   RowArrays rows;
+  BigParams big;
+  BigBuffers bb;
 };
 
 Carved carve(void* ws, const Layout& L) {
@@ -205,6 +251,21 @@ Carved carve(void* ws, const Layout& L) {
   c.rows.L1 = (uint16_t*)(b + L.l1);
   c.rows.L2 = (uint16_t*)(b + L.l2);
   c.rows.S = (void*)(b + L.s);
+  std::memset(&c.big, 0, sizeof(c.big));
+  c.big.segs = (const BigSeg*)(b + L.bsegs);
+  c.big.tiles = (const BigTile*)(b + L.btiles);
+  c.big.flags = (int32_t*)(b + L.bflags);
+  c.big.gsum = (double*)(b + L.bgsum);
+  uint32_t** r32[12] = {&c.bb.ka, &c.bb.kb, &c.bb.kc, &c.bb.kd, &c.bb.va, &c.bb.vb,
+                        &c.bb.R1, &c.bb.R2, &c.bb.E1, &c.bb.E2, &c.bb.L1, &c.bb.L2};
+  for (int i = 0; i < 12; ++i) *r32[i] = (uint32_t*)(b + L.brow32[i]);
+  void** r64[5] = {&c.bb.LX, &c.bb.LY, &c.bb.A1, &c.bb.A2, &c.bb.S};
+  for (int i = 0; i < 5; ++i) *r64[i] = (void*)(b + L.brow64[i]);
+  c.bb.hist = (uint32_t*)(b + L.bhist);
+  c.bb.part = (double*)(b + L.bpart);
+  c.bb.tsum = (double*)(b + L.btsum);
+  c.bb.st = (NewtonState*)(b + L.bst);
+  c.bb.pending = (int*)(b + L.bpending);
   return c;
 }
 
@@ -215,9 +276,21 @@ int upload_tables(cpc_context* h, const Plan& P, const Carved& c, const int64_t*
   HIP_OK(hipMemcpyAsync(c.order_rank, P.order_rank.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(c.order_fit, P.order_fit.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
   if (gofs) HIP_OK(hipMemcpyAsync(c.gofs, gofs, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+  if (!P.bsegs.empty()) {
+    HIP_OK(hipMemcpyAsync((void*)c.big.segs, P.bsegs.data(), sizeof(BigSeg) * P.bsegs.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(hipMemcpyAsync((void*)c.big.tiles, P.btiles.data(), sizeof(BigTile) * P.btiles.size(),
+                          hipMemcpyHostToDevice, s));
+  }
   (void)h;
   (void)G;
   return CPC_SUCCESS;
+}
+
+// Fills the counts of the streaming-path parameter block from the plan.
+void set_big(Carved& c, const Plan& P, int64_t n_min) {
+  c.big.nsegs = (int32_t)P.bsegs.size();
+  c.big.ntiles = (int64_t)P.btiles.size();
+  c.big.n_min = n_min;
 }
 
 Plan& plan_of(cpc_handle_t h) { return *(Plan*)h->plan; }
@@ -240,7 +313,7 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   int rc = make_plan(offsets, K, fam_of_subset.data(), P);
   if (rc) return rc;
   HIP_OK(hipSetDevice(h->device));
-  const Carved c = carve(ws, L);
+  Carved c = carve(ws, L);
   const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
   h->have_times = 0;
   P.gofs.assign(gofs, gofs + G + 1);
@@ -260,11 +333,13 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   rp.n_min = o.n_min;
   rp.rows = c.rows;
   rp.state = c.state;
+  set_big(c, P, o.n_min);
   if (timed) HIP_OK(hipEventRecord(h->ev[0], s));
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
     HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
   }
+  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, nullptr, nullptr, s));
   if (timed) HIP_OK(hipEventRecord(h->ev[1], s));
   FitParams fp;
   std::memset(&fp, 0, sizeof(fp));
@@ -277,6 +352,7 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
     fp.order = c.order_fit + b.first;
     HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
   }
+  HIP_OK(big_solve(c.big, c.bb, o.tol, o.max_iter, fp64, h->pending_host, s));
   if (timed) HIP_OK(hipEventRecord(h->ev[2], s));
   VarParams vp;
   std::memset(&vp, 0, sizeof(vp));
@@ -290,6 +366,7 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
     vp.order = c.order_fit + b.first;
     HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
   }
+  HIP_OK(big_variance(c.big, c.bb, fp64, nullptr, o.var, MODE_FIT, nullptr, (ResultOut*)out, s));
   if (timed) HIP_OK(hipEventRecord(h->ev[3], s));
   HIP_OK(launch_combine((const ResultOut*)out, c.gofs, G, (CombinedOut*)comb, s));
   if (timed) {
@@ -327,9 +404,16 @@ int cpc_create(int device, cpc_handle_t* out) {
   h->magic = kMagic;
   h->plan = new Plan();
   h->have_times = 0;
+  h->pending_host = nullptr;
+  if (hipHostMalloc((void**)&h->pending_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete (Plan*)h->plan;
+    delete h;
+    return fail(CPC_E_HIP, "hipHostMalloc failed");
+  }
   for (int i = 0; i < 5; ++i) {
     if (hipEventCreate(&h->ev[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->ev[j]);
+      (void)hipHostFree(h->pending_host);
       delete (Plan*)h->plan;
       delete h;
       return fail(CPC_E_HIP, "hipEventCreate failed");
@@ -343,6 +427,7 @@ int cpc_destroy(cpc_handle_t h) {
   if (int rc = check_handle(h)) return rc;
   h->magic = 0;
   for (int i = 0; i < 5; ++i) (void)hipEventDestroy(h->ev[i]);
+  (void)hipHostFree(h->pending_host);
   delete (Plan*)h->plan;
   delete h;
   return CPC_SUCCESS;
@@ -419,7 +504,7 @@ int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_
   if (int rc = make_plan(offsets, K, fam.data(), P)) return rc;
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
-  const Carved c = carve(workspace, L);
+  Carved c = carve(workspace, L);
   if (int rc = upload_tables(h, P, c, nullptr, 0, s)) return rc;
   RankParams rp;
   std::memset(&rp, 0, sizeof(rp));
@@ -438,6 +523,8 @@ int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_
     rp.order = c.order_rank + b.first;
     HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
   }
+  set_big(c, P, o.n_min);
+  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s));
   return CPC_SUCCESS;
 }
 
@@ -460,7 +547,7 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
   if (int rc = make_plan(offsets, K, fam.data(), P)) return rc;
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
-  const Carved c = carve(workspace, L);
+  Carved c = carve(workspace, L);
   if (int rc = upload_tables(h, P, c, nullptr, 0, s)) return rc;
   // re-rank from the given ranks (integer keys): sorted positions and tie groups
   RankParams rp;
@@ -478,6 +565,8 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
     rp.order = c.order_rank + b.first;
     HIP_OK(launch_rank_wg(b.cls, 1, rp, b.count, s));
   }
+  set_big(c, P, o.n_min);
+  HIP_OK(big_rank(c.big, c.bb, R1, R2, 1, 1, o.ties, nullptr, nullptr, s));
   VarParams vp;
   std::memset(&vp, 0, sizeof(vp));
   vp.subs = c.subs;
@@ -492,6 +581,7 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
     vp.order = c.order_fit + b.first;
     HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
   }
+  HIP_OK(big_variance(c.big, c.bb, fp64, theta, o.var, MODE_VARIANCE, var, nullptr, s));
   return CPC_SUCCESS;
 }
 
@@ -518,7 +608,7 @@ int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, 
   }
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
-  const Carved c = carve(workspace, L);
+  Carved c = carve(workspace, L);
   HIP_OK(hipMemcpyAsync(c.subs, subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
   HIP_OK(launch_eval_wg(R1, R2, c.subs, K, family, o.prec == CPC_PREC_FP64 ? 1 : 0, theta, out, s));
   return CPC_SUCCESS;

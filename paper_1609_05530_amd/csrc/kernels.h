@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "cpc_device.h"
+#include "solver.h"
 
 namespace cpc {
 
@@ -70,6 +71,52 @@ struct VarParams {
 hipError_t launch_rank_wg(int cls, int kw, const RankParams& p, int grid, hipStream_t s);
 hipError_t launch_fit_wg(int cls, int fam, int fp64, const FitParams& p, int grid, hipStream_t s);
 hipError_t launch_var_wg(int cls, int fam, int fp64, const VarParams& p, int grid, hipStream_t s);
+
+// Streaming path for subsets of more than kResidentMaxRows rows: tiles of
+// 4096 rows over all such subsets; per-row arrays at compact indices
+// (roff + row within the subset).
+struct BigSeg {
+  int64_t begin;   // first row in x / y
+  int64_t n;       // rows
+  int64_t roff;    // first compact index
+  int64_t tile0;   // first tile
+  int32_t ntiles;
+  int32_t sid;     // subset id (result index)
+  int32_t family;
+  int32_t pad;
+};
+struct BigTile {
+  int32_t seg;
+  int32_t count;
+  int64_t start;  // first row of the tile within its subset
+};
+struct BigParams {
+  const BigSeg* segs;
+  const BigTile* tiles;
+  int32_t nsegs;
+  int32_t pad;
+  int64_t ntiles;
+  int64_t n_min;
+  int32_t* flags;  // per subset: bit 0 non-finite data, bit 1 a margin with one value
+  double* gsum;    // per subset: Gaussian S+, S-
+};
+struct BigBuffers {
+  uint32_t *ka, *kb, *kc, *kd, *va, *vb;  // sort keys / payloads (ping-pong)
+  uint32_t *R1, *R2, *E1, *E2, *L1, *L2;  // doubled ranks, sorted positions, tie-group starts
+  void *LX, *LY, *A1, *A2, *S;            // Gumbel logs, suffix-sum arrays, scores (row arithmetic type)
+  uint32_t* hist;                         // 256 per tile
+  double* part;                           // 5 per tile
+  double* tsum;                           // 2 per tile
+  NewtonState* st;                        // per subset
+  int* pending;                           // subsets still iterating
+};
+hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, const void* y, int dtype_kw,
+                    int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s);
+hipError_t big_solve(const BigParams& P, const BigBuffers& B, double tol, int max_iter, int fp64, int* pending_host,
+                     hipStream_t s);
+hipError_t big_variance(const BigParams& P, const BigBuffers& B, int fp64, const double* theta_in, int var_method,
+                        int mode, double* var_out, ResultOut* out, hipStream_t s);
+constexpr int kBigTile = 4096;
 
 // Adjoint of eq. (13): per-subset sums of l, dl/dtheta, d2l/dtheta2.
 hipError_t launch_eval_wg(const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t K, int fam,

@@ -32,25 +32,96 @@ __device__ __forceinline__ int group_ub(const uint32_t* heads, int e, int n, int
   return ub < n ? ub : n;
 }
 
-// Stable LSD radix sort of up to CAP = T*E keys held in registers in
-// wave-striped order (element e = (w*E + j)*64 + lane lives in wave w, slot
-// j). Only e < n take part. The payload (the element's original index) does
-// not occupy registers: it moves between two LDS buffers, starting as the
-// identity in vb[0]. Returns which of the two buffers holds the final payload
-// (vb[k][e] = original index of sorted position e). 8-bit digits; each pass
-// ranks elements within their wave with a ballot multisplit, then combines
-// per-wave digit counts in a digit-major scan (stable by construction).
-// A pass in which every element has the same digit moves nothing and is
-// skipped (uniformly).
-template <int T, int E, int KW>
-__device__ __forceinline__ int lds_radix_sort(uint32_t (&klo)[E], uint32_t (&khi)[E], int n,
-                                              uint32_t* buf, uint16_t* vb0, uint16_t* vb1,
-                                              uint16_t* cnt, uint32_t* dtot) {
+// One stable counting pass over the digits d[j] of the elements held in
+// wave-striped order (element e = (w*E + j)*64 + lane; only e < n take
+// part): each wave ranks its elements among its own earlier elements with the
+// same digit by a ballot multisplit, then per-wave digit counts are combined
+// in a digit-major exclusive scan. On return dst[j] is the element's position
+// in the stably sorted order of the workgroup's n elements, dtot[0..255] the
+// first position of each digit, and dtot[256 + (pass & 1)] is nonzero when
+// one digit holds all n elements (the pass is the identity). cnt: W*256 u16.
+template <int T, int E>
+__device__ __forceinline__ void lds_multisplit(const uint32_t (&d)[E], int n, int pass, uint16_t* cnt,
+                                               uint32_t* dtot, uint32_t (&dst)[E]) {
   constexpr int W = T / WAVE;
   constexpr int NT = (T < 256) ? T : 256;  // threads that scan digits
   constexpr int DPT = 256 / NT;            // digits per scanning thread
   const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   const uint64_t lt = lanemask_lt();
+  for (int i = lane; i < 256; i += WAVE) cnt[w * 256 + i] = 0;
+  // the identity flag alternates between two slots so that resetting it for
+  // this pass cannot race with reads of the previous pass's flag
+  if (tid == 0) dtot[256 + (pass & 1)] = 0u;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = (w * E + j) * WAVE + lane;
+    const bool valid = e < n;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d[j] >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const uint32_t lower = (uint32_t)__popcll(m & lt);
+    const uint32_t old = cnt[w * 256 + d[j]];
+    dst[j] = old + lower;
+    if (valid && lower == 0u) cnt[w * 256 + d[j]] = (uint16_t)(old + (uint32_t)__popcll(m));
+    // keep the slots' ballot chains from being interleaved (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();
+  uint32_t colsum[DPT];
+  uint32_t local = 0;
+  if (tid < NT) {
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      const int dg = tid * DPT + q;
+      uint32_t run = 0;
+      for (int k = 0; k < W; ++k) {
+        const uint32_t c = cnt[k * 256 + dg];
+        cnt[k * 256 + dg] = (uint16_t)run;
+        run += c;
+      }
+      colsum[q] = run;
+      local += run;
+      if (run == (uint32_t)n) dtot[256 + (pass & 1)] = 1u;
+    }
+  }
+  uint32_t incl = local;
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const uint32_t t = __shfl_up(incl, off, WAVE);
+    if (lane >= off) incl += t;
+  }
+  if (tid < NT && lane == WAVE - 1) dtot[258 + w] = incl;
+  __syncthreads();
+  if (tid < NT) {
+    uint32_t base = incl - local;
+    for (int k = 0; k < w; ++k) base += dtot[258 + k];
+#pragma unroll
+    for (int q = 0; q < DPT; ++q) {
+      dtot[tid * DPT + q] = base;
+      base += colsum[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < E; ++j) dst[j] += dtot[d[j]] + cnt[w * 256 + d[j]];
+}
+
+// Stable LSD radix sort of up to CAP = T*E keys held in registers in
+// wave-striped order. Only e < n take part. The payload (the element's
+// original index) does not occupy registers: it moves between two LDS
+// buffers, starting as the identity in vb0. Returns which of the two buffers
+// holds the final payload (vb[k][e] = original index of sorted position e).
+// 8-bit digits, least significant first; a pass in which every element has
+// the same digit moves nothing and is skipped (uniformly).
+template <int T, int E, int KW>
+__device__ __forceinline__ int lds_radix_sort(uint32_t (&klo)[E], uint32_t (&khi)[E], int n,
+                                              uint32_t* buf, uint16_t* vb0, uint16_t* vb1,
+                                              uint16_t* cnt, uint32_t* dtot) {
+  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
   for (int e = tid; e < n; e += T) vb0[e] = (uint16_t)e;
   int cur = 0;
   uint32_t dst[E];
@@ -58,77 +129,16 @@ __device__ __forceinline__ int lds_radix_sort(uint32_t (&klo)[E], uint32_t (&khi
   for (int pass = 0; pass < 4 * KW; ++pass) {
     const int word = pass >> 2;
     const int shift = (pass & 3) * 8;
-    for (int i = lane; i < 256; i += WAVE) cnt[w * 256 + i] = 0;
-    // the identity flag alternates between two slots so that resetting it for
-    // this pass cannot race with reads of the previous pass's flag
-    if (tid == 0) dtot[256 + (pass & 1)] = 0u;
-    // wave-level multisplit: rank of each element among the wave's earlier
-    // elements with the same digit (this wave's counters carry across slots)
+    uint32_t d[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int e = (w * E + j) * WAVE + lane;
-      const bool valid = e < n;
-      const uint32_t kw = (KW == 2 && word) ? khi[j] : klo[j];
-      const uint32_t d = (kw >> shift) & 0xFFu;
-      uint64_t m = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
-      }
-      const uint32_t lower = (uint32_t)__popcll(m & lt);
-      const uint32_t old = cnt[w * 256 + d];
-      dst[j] = (old + lower) | (d << 16);  // local rank, and the digit for the scatter
-      if (valid && lower == 0u) cnt[w * 256 + d] = (uint16_t)(old + (uint32_t)__popcll(m));
-      // keep the slots' ballot chains from being interleaved (register pressure)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    __syncthreads();
-    // digit-major exclusive scan: over waves per digit, then over digits
-    uint32_t colsum[DPT];
-    uint32_t local = 0;
-    if (tid < NT) {
-#pragma unroll
-      for (int q = 0; q < DPT; ++q) {
-        const int d = tid * DPT + q;
-        uint32_t run = 0;
-        for (int k = 0; k < W; ++k) {
-          const uint32_t c = cnt[k * 256 + d];
-          cnt[k * 256 + d] = (uint16_t)run;
-          run += c;
-        }
-        colsum[q] = run;
-        local += run;
-        if (run == (uint32_t)n) dtot[256 + (pass & 1)] = 1u;  // every element has this digit
-      }
-    }
-    uint32_t incl = local;
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-      const uint32_t t = __shfl_up(incl, off, WAVE);
-      if (lane >= off) incl += t;
-    }
-    if (tid < NT && lane == WAVE - 1) dtot[258 + w] = incl;
-    __syncthreads();
-    if (tid < NT) {
-      uint32_t base = incl - local;
-      for (int k = 0; k < w; ++k) base += dtot[258 + k];
-#pragma unroll
-      for (int q = 0; q < DPT; ++q) {
-        dtot[tid * DPT + q] = base;
-        base += colsum[q];
-      }
-    }
-    __syncthreads();
+    for (int j = 0; j < E; ++j) d[j] = (((KW == 2 && word) ? khi[j] : klo[j]) >> shift) & 0xFFu;
+    lds_multisplit<T, E>(d, n, pass, cnt, dtot, dst);
     if (dtot[256 + (pass & 1)] != 0u) continue;  // identity permutation: nothing moves
     const uint16_t* vs = cur ? vb1 : vb0;
     uint16_t* vd = cur ? vb0 : vb1;
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int e = (w * E + j) * WAVE + lane;
-      const uint32_t d = dst[j] >> 16;
-      dst[j] = (dst[j] & 0xFFFFu) + dtot[d] + cnt[w * 256 + d];
       if (e < n) {
         buf[dst[j]] = klo[j];
         vd[dst[j]] = vs[e];

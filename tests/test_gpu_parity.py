@@ -282,3 +282,95 @@ def test_bitwise_deterministic():
                                 fams, prec="fp32c"))
     for k in a:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+# ---------------------------------------------------------------------------
+# Streaming path (subsets of more than 16384 rows)
+
+BIG_SIZES = [16385, 20000, 3000, 45000]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("ties", ["average", "first"])
+def test_big_ranks_bit_exact(dtype, ties):
+    rng = np.random.default_rng(23)
+    n = int(sum(BIG_SIZES))
+    x = rng.standard_normal(n)
+    y = np.round(rng.standard_normal(n) * 16) / 16  # heavy ties
+    y[:100] = -0.0
+    if dtype == torch.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    off = synth.offsets_from_sizes(np.array(BIG_SIZES))
+    R1, R2 = cpc().rank(dev(x, dtype), dev(y, dtype), off, ties=ties)
+    R1 = R1.cpu().numpy().astype(np.int64); R2 = R2.cpu().numpy().astype(np.int64)
+    for m in range(len(BIG_SIZES)):
+        a, b = off[m], off[m + 1]
+        assert np.array_equal(R1[a:b], O.ranks(x[a:b], ties)), m
+        assert np.array_equal(R2[a:b], O.ranks(y[a:b], ties)), m
+
+
+@pytest.mark.parametrize("fam,th", [("gaussian", 0.6), ("frank", 5.0), ("frank", -2.0), ("gumbel", 2.0)])
+@pytest.mark.parametrize("prec,storage", [("fp64", "f64"), ("fp32c", "f32")])
+def test_big_fit_parity(fam, th, prec, storage):
+    n = int(sum(BIG_SIZES))
+    x, y = synth.copula_pairs(fam, th, n, 400 + FAM_CODE[fam])
+    if storage == "f32":
+        x = x.astype(np.float32).astype(np.float64); y = y.astype(np.float32).astype(np.float64)
+    off = synth.offsets_from_sizes(np.array(BIG_SIZES))
+    sub, comb = O.fit(x, y, off, fam, nthreads=0)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    res = to_np(cpc().fit(dev(x, dt), dev(y, dt), off, fam, prec=prec))
+    compare(res, sub, comb, prec, fam, f"big {fam} {th} {prec} {storage}")
+
+
+def test_big_statuses():
+    z = np.arange(20000, dtype=np.float64)
+    rng = np.random.default_rng(4)
+    x = np.concatenate([z, rng.standard_normal(20000), np.full(20000, 2.0)])
+    y = np.concatenate([z, rng.standard_normal(20000), rng.standard_normal(20000)])
+    x[25000] = np.inf
+    off = np.array([0, 20000, 40000, 60000])
+    for fam in ("gaussian", "frank", "gumbel"):
+        sub, _ = O.fit(x, y, off, fam)
+        res = to_np(cpc().fit(dev(x, torch.float64), dev(y, torch.float64), off, fam, prec="fp64"))
+        assert np.array_equal(res["status"], sub["status"]), (fam, res["status"], sub["status"])
+        assert res["theta"][0] == sub["theta"][0]
+
+
+@pytest.mark.parametrize("fam", ["gaussian", "frank", "gumbel"])
+def test_config2_full_size(fam):
+    """n = 1e6 per family, FP64, K in {1, 10, 100}: ranks of sampled rows by
+    brute force, the estimate as the root of the oracle's score, and oracle
+    parity on sampled subsets."""
+    w1 = synth.config2(fam, 1)
+    x, y = w1.x, w1.y
+    n = x.shape[0]
+    rng = np.random.default_rng(9)
+    for K in (1, 10, 100):
+        off = synth.equal_offsets(n, K)
+        res = to_np(cpc().fit(dev(x, torch.float64), dev(y, torch.float64), off, fam, prec="fp64"))
+        assert np.all(res["status"] == 0), (fam, K, res["status"])
+        R1, R2 = cpc().rank(dev(x, torch.float64), dev(y, torch.float64), off)
+        r1 = R1.cpu().numpy().astype(np.int64); r2 = R2.cpu().numpy().astype(np.int64)
+        m = 0
+        a, b = off[m], off[m + 1]
+        for i in rng.integers(a, b, 20):
+            assert r1[i] == 2 * np.sum(x[a:b] < x[i]) + np.sum(x[a:b] == x[i]) + 1
+            assert r2[i] == 2 * np.sum(y[a:b] < y[i]) + np.sum(y[a:b] == y[i]) + 1
+        # the estimate is the root of the score (the oracle's own derivatives)
+        nm = b - a
+        u, omu = O.pobs_from_ranks(r1[a:b], nm); v, omv = O.pobs_from_ranks(r2[a:b], nm)
+        d = O.logc_derivs(fam, float(res["theta"][m]), u, omu, v, omv)
+        assert abs(d[:, 1].sum()) <= 1e-6 * np.abs(d[:, 1]).sum(), (fam, K)
+        assert d[:, 2].sum() < 0
+        step = abs(d[:, 1].sum() / d[:, 2].sum())
+        assert step <= 1e-6 * max(abs(res["theta"][m]), 1e-3), (fam, K, step)
+        print(f"[config2] {fam} K={K}: theta[0]={res['theta'][0]:.10f} newton residual step {step:.2e} "
+              f"combined {res['combined_theta'][0]:.10f}", flush=True)
+        if K == 100:
+            pick = [0, 57]
+            xs = np.concatenate([x[off[j]:off[j + 1]] for j in pick]); ys = np.concatenate([y[off[j]:off[j + 1]] for j in pick])
+            sub, _ = O.fit(xs, ys, synth.offsets_from_sizes(np.diff(off)[pick]), fam)
+            rt = np.abs(res["theta"][pick] - sub["theta"]) / np.abs(sub["theta"])
+            rv = np.abs(res["var"][pick] / sub["var"] - 1.0)
+            assert rt.max() <= 1e-6 and rv.max() <= 1e-6, (fam, rt, rv)
