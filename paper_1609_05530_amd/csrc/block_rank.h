@@ -1,0 +1,142 @@
+// block_rank.h — workgroup-local stable radix ranking, the sorting step
+// behind the ranks of eq. (12) of arXiv:1609.05530.
+//
+// Elements live in registers in blocked arrangement: thread t holds the
+// elements at positions t*E .. t*E+E-1 of the current order. One counting
+// pass over a B-bit digit gives every thread a private 16-bit counter per
+// digit value in LDS, two digit values per 32-bit word: digit d of thread t
+// lives in word (d mod C)*T + t, half d / C, with C = 2^(B-1). The lanes of a
+// wave therefore always touch 64 consecutive words (no bank conflicts).
+//   1. each thread counts its own elements in order with LDS atomic adds; the
+//      returned old value is the element's offset among the thread's earlier
+//      elements with the same digit;
+//   2. the counter words are exclusive-scanned in (d mod C, t) order, packed:
+//      each half accumulates separately because no half can exceed the
+//      element count (< 2^16), and the upper halves then take the total of
+//      the lower ones, which gives the digit-major, thread-minor prefix;
+//   3. an element's position in the stable order is its counter's prefix
+//      plus its offset.
+// No cross-lane matching is needed: a pass costs a few LDS operations and
+// about a dozen VALU instructions per element.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cpc_device.h"
+
+namespace cpc {
+
+// Inclusive prefix sum over the lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const uint32_t t = __shfl_up(v, off, WAVE);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+template <int T, int E, int B>
+struct BlockDigitRank {
+  static_assert(T % WAVE == 0, "whole waves");
+  static_assert(B >= 2 && B <= 8, "digit width");
+  static_assert(T * E <= 65535, "16-bit counters");
+  static constexpr int W = T / WAVE;
+  static constexpr int C = 1 << (B - 1);  // counter words per thread
+  static constexpr int kCounterWords = C * T;
+  static constexpr int kScratchWords = W;
+  static constexpr uint32_t kMask = (1u << B) - 1u;
+
+  // The digit of item j is bits [off, off + B) of its key (klo[j], and
+  // khi[j] above bit 31 when KW == 2); it is computed twice rather than kept
+  // live across the barriers. All items of a wave take part when `active`
+  // (wave-uniform) is set, none otherwise; on return pos[j] is the item's
+  // position in the stable digit order (undefined for an inactive wave).
+  // cnt: kCounterWords u32 of LDS, red: kScratchWords u32 of LDS. Contains
+  // three workgroup barriers; between calls a thread touches no counter word
+  // but its own.
+  template <int KW>
+  __device__ static __forceinline__ uint32_t digit_of(uint32_t lo, uint32_t hi, int off) {
+    if constexpr (KW == 2) return (uint32_t)((((uint64_t)hi << 32) | lo) >> off) & kMask;
+    return (lo >> off) & kMask;
+  }
+  template <int KW>
+  __device__ static __forceinline__ void rank(const uint32_t (&klo)[E], const uint32_t (&khi)[E], int off, bool active,
+                                              uint32_t* cnt, uint32_t* red, uint32_t (&pos)[E]) {
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    // 1. private counters: clear, then count in order (pos[j] holds the
+    //    counter word before the item's increment)
+#pragma unroll
+    for (int c = 0; c < C; ++c) cnt[c * T + t] = 0u;
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const uint32_t d = digit_of<KW>(klo[j], khi[j], off);
+        pos[j] = atomicAdd(&cnt[(d & (C - 1)) * T + t], 1u << ((d >> (B - 1)) << 4));
+      }
+    }
+    __syncthreads();
+    // 2. exclusive scan of the words in linear order; thread t owns words
+    //    [t*C, t*C + C)
+    uint32_t v[C];
+    if constexpr (C % 4 == 0) {
+      const uint4* src = reinterpret_cast<const uint4*>(cnt + t * C);
+#pragma unroll
+      for (int q = 0; q < C / 4; ++q) {
+        const uint4 x = src[q];
+        v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) v[c] = cnt[t * C + c];
+    }
+    uint32_t run = 0u;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const uint32_t x = v[c];
+      v[c] = run;
+      run += x;
+    }
+    const uint32_t incl = wave_incl_sum_u32(run);
+    if (lane == WAVE - 1) red[w] = incl;
+    __syncthreads();
+    uint32_t base = incl - run, grand = 0u;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+      const uint32_t r = red[k];
+      if (k < w) base += r;
+      grand += r;
+    }
+    if constexpr (C % 4 == 0) {
+      uint4* dst = reinterpret_cast<uint4*>(cnt + t * C);
+#pragma unroll
+      for (int q = 0; q < C / 4; ++q)
+        dst[q] = make_uint4(v[4 * q] + base, v[4 * q + 1] + base, v[4 * q + 2] + base, v[4 * q + 3] + base);
+    } else {
+#pragma unroll
+      for (int c = 0; c < C; ++c) cnt[t * C + c] = v[c] + base;
+    }
+    __syncthreads();
+    // 3. positions (the shift and column index are laundered so that the
+    //    counting phase's digits and addresses are recomputed, not kept live
+    //    across the scan)
+    const uint32_t lowtot = grand & 0xFFFFu;
+    int tl = t, offl = off;
+    asm volatile("" : "+v"(tl));
+    asm volatile("" : "+s"(offl));
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const uint32_t d = digit_of<KW>(klo[j], khi[j], offl);
+        const uint32_t word = cnt[(d & (C - 1)) * T + tl];
+        const uint32_t sh = (d >> (B - 1)) << 4;
+        const uint32_t base = (d >> (B - 1)) ? (word >> 16) + lowtot : (word & 0xFFFFu);
+        pos[j] = base + ((pos[j] >> sh) & 0xFFFFu);
+      }
+    }
+  }
+};
+
+}  // namespace cpc

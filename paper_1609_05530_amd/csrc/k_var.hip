@@ -11,14 +11,21 @@
 // are scattered to sorted position in LDS and suffix-summed there.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "solver.h"
 
 namespace cpc {
 
-// In-place inclusive suffix sums of A[0..n): A[i] <- sum_{q >= i} A[q];
-// per-thread chunks of E consecutive entries, chunk sums and the workgroup
-// scan in double.
+// LDS index of sorted position q: one pad word after every 16 entries, so
+// that threads walking their own 16 consecutive entries hit distinct banks.
+__device__ __forceinline__ int pidx(int q) { return q + (q >> 4); }
+constexpr int padded(int cap) { return cap + cap / 16; }
+
+// In-place inclusive suffix sums over sorted positions [0, n) of the padded
+// array A: A[q] <- sum_{q' >= q} A[q']. Per-thread chunks of E consecutive
+// positions, chunk sums and the workgroup scan in double.
 template <int T, int E, typename CT>
 __device__ __forceinline__ void lds_suffix_sum(CT* A, int n, double* scratch) {
   constexpr int W = T / WAVE;
@@ -26,13 +33,13 @@ __device__ __forceinline__ void lds_suffix_sum(CT* A, int n, double* scratch) {
   double cs = 0.0;
 #pragma unroll
   for (int i = 0; i < E; ++i)
-    if (c0 + i < n) cs += (double)A[c0 + i];
+    if (c0 + i < n) cs += (double)A[pidx(c0 + i)];
   double run = block_excl_suffix<W>(cs, scratch);
 #pragma unroll
   for (int i = E - 1; i >= 0; --i) {
     if (c0 + i < n) {
-      run += (double)A[c0 + i];
-      A[c0 + i] = (CT)run;
+      run += (double)A[pidx(c0 + i)];
+      A[pidx(c0 + i)] = (CT)run;
     }
   }
   __syncthreads();
@@ -42,9 +49,9 @@ template <int T, int CAP, typename CT, int FAM>
 __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
   constexpr int W = T / WAVE;
   constexpr int E = CAP / T;
-  constexpr bool TWO = 2 * sizeof(CT) * CAP <= 144 * 1024;
-  __shared__ CT A1[CAP];
-  __shared__ CT A2[TWO ? CAP : 1];
+  constexpr bool TWO = 2 * sizeof(CT) * padded(CAP) <= 144 * 1024;
+  __shared__ CT A1[padded(CAP)];
+  __shared__ CT A2[TWO ? padded(CAP) : 1];
   __shared__ double red[W * 5];
   const int tid = threadIdx.x;
   const int sid = P.order[blockIdx.x];
@@ -75,7 +82,6 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
   const uint16_t *R1 = P.rows.R1 + o, *R2 = P.rows.R2 + o;
   const uint16_t *E1 = P.rows.E1 + o, *E2 = P.rows.E2 + o;
   const uint16_t *L1 = P.rows.L1 + o, *L2 = P.rows.L2 + o;
-  CT* S = (CT*)P.rows.S + o;
   const uint32_t twon1 = 2u * (uint32_t)(n + 1);
   const CT inv = (CT)1 / (CT)twon1;
   const double dn = (double)n;
@@ -83,82 +89,83 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
   const bool rd = sizeof(CT) == 4 && c.use_d;  // FP64 rows near the family boundaries
   const Consts<double> cd = make_consts<double>(FAM, theta);
 
-  auto row_eval = [&](int i, CT& l, CT& s, CT& g1, CT& g2) {
+  // Row arithmetic in RT (CT, or double near the family boundaries), results
+  // in CT. The choice is uniform over the workgroup and made once, outside
+  // the row loops.
+  auto row_eval_t = [&](auto rt_tag, int i, CT& l, CT& s, CT& g1, CT& g2) {
+    using RT = decltype(rt_tag);
     const uint32_t a = R1[i], b = R2[i];
-    if (rd) {
-      const double invd = 1.0 / (double)twon1;
-      double ld, sdd, g1d, g2d;
-      if constexpr (FAM == FAM_FRANK) {
-        frank_rfull<double>(cd, a, b, twon1, invd, ld, sdd, g1d, g2d);
-      } else if constexpr (FAM == FAM_GUMBEL) {
-        double lx, ly;
-        gumbel_lxy<double>(a, b, twon1, invd, lx, ly);
-        gumbel_rfull<double>(cd, a, b, twon1, invd, lx, ly, ld, sdd, g1d, g2d);
-      } else {
-        double z1, z2;
-        gauss_z<double>(a, b, twon1, z1, z2);
-        gauss_rfull<double>(cd, z1, z2, ld, sdd, g1d, g2d);
-      }
-      l = (CT)ld; s = (CT)sdd; g1 = (CT)g1d; g2 = (CT)g2d;
+    const RT invr = (RT)1 / (RT)twon1;
+    const Consts<RT>& cc = [&]() -> const Consts<RT>& {
+      if constexpr (std::is_same<RT, double>::value) return cd; else return c;
+    }();
+    RT lr, sr, g1r, g2r;
+    if constexpr (FAM == FAM_FRANK) {
+      frank_rfull<RT>(cc, a, b, twon1, invr, lr, sr, g1r, g2r);
+    } else if constexpr (FAM == FAM_GUMBEL) {
+      RT lx, ly;
+      gumbel_lxy<RT>(a, b, twon1, invr, lx, ly);
+      gumbel_rfull<RT>(cc, a, b, twon1, invr, lx, ly, lr, sr, g1r, g2r);
     } else {
-      if constexpr (FAM == FAM_FRANK) {
-        frank_rfull<CT>(c, a, b, twon1, inv, l, s, g1, g2);
-      } else if constexpr (FAM == FAM_GUMBEL) {
-        CT lx, ly;
-        gumbel_lxy<CT>(a, b, twon1, inv, lx, ly);
-        gumbel_rfull<CT>(c, a, b, twon1, inv, lx, ly, l, s, g1, g2);
-      } else {
-        CT z1, z2;
-        gauss_z<CT>(a, b, twon1, z1, z2);
-        gauss_rfull<CT>(c, z1, z2, l, s, g1, g2);
-      }
+      RT z1, z2;
+      gauss_z<RT>(a, b, twon1, z1, z2);
+      gauss_rfull<RT>(cc, z1, z2, lr, sr, g1r, g2r);
     }
+    l = (CT)lr; s = (CT)sr; g1 = (CT)g1r; g2 = (CT)g2r;
   };
 
   KSum<CT> kl, ksc, ks2;
   double psum = 0.0, psq = 0.0;
-  if constexpr (TWO) {
-    for (int i = tid; i < n; i += T) {
-      CT l, s, g1, g2;
-      row_eval(i, l, s, g1, g2);
-      kl.add(l); ksc.add(s); ks2.add(s * s);
-      A1[E1[i]] = g1;
-      A2[E2[i]] = g2;
-      S[i] = s;
+  CT* S = (CT*)P.rows.S + o;  // per-row score (workspace), then s + W1 (one-array variant)
+  auto rows = [&](auto rt_tag) {
+    using RT = decltype(rt_tag);
+    if constexpr (TWO) {
+      for (int i = tid; i < n; i += T) {
+        CT l, s, g1, g2;
+        row_eval_t(RT{}, i, l, s, g1, g2);
+        kl.add(l); ksc.add(s); ks2.add(s * s);
+        A1[pidx(E1[i])] = g1;
+        A2[pidx(E2[i])] = g2;
+        S[i] = s;
+      }
+      __syncthreads();
+      lds_suffix_sum<T, E, CT>(A1, n, red);
+      lds_suffix_sum<T, E, CT>(A2, n, red);
+      for (int i = tid; i < n; i += T) {
+        const double psi = (double)S[i] + ((double)A1[pidx(L1[i])] + (double)A2[pidx(L2[i])]) / dn;
+        psum += psi;
+        psq += psi * psi;
+      }
+    } else {
+      for (int i = tid; i < n; i += T) {
+        CT l, s, g1, g2;
+        row_eval_t(RT{}, i, l, s, g1, g2);
+        kl.add(l); ksc.add(s); ks2.add(s * s);
+        A1[pidx(E1[i])] = g1;
+        S[i] = s;
+      }
+      __syncthreads();
+      lds_suffix_sum<T, E, CT>(A1, n, red);
+      for (int i = tid; i < n; i += T) S[i] = (CT)((double)S[i] + (double)A1[pidx(L1[i])] / dn);
+      __syncthreads();
+      for (int i = tid; i < n; i += T) {
+        CT l, s, g1, g2;
+        row_eval_t(RT{}, i, l, s, g1, g2);
+        A1[pidx(E2[i])] = g2;
+      }
+      __syncthreads();
+      lds_suffix_sum<T, E, CT>(A1, n, red);
+      for (int i = tid; i < n; i += T) {
+        const double psi = (double)S[i] + (double)A1[pidx(L2[i])] / dn;
+        psum += psi;
+        psq += psi * psi;
+      }
     }
-    __syncthreads();
-    lds_suffix_sum<T, E, CT>(A1, n, red);
-    lds_suffix_sum<T, E, CT>(A2, n, red);
-    for (int i = tid; i < n; i += T) {
-      const double psi = (double)S[i] + ((double)A1[L1[i]] + (double)A2[L2[i]]) / dn;
-      psum += psi;
-      psq += psi * psi;
-    }
-  } else {
-    for (int i = tid; i < n; i += T) {
-      CT l, s, g1, g2;
-      row_eval(i, l, s, g1, g2);
-      kl.add(l); ksc.add(s); ks2.add(s * s);
-      A1[E1[i]] = g1;
-      S[i] = s;
-    }
-    __syncthreads();
-    lds_suffix_sum<T, E, CT>(A1, n, red);
-    for (int i = tid; i < n; i += T) S[i] = (CT)((double)S[i] + (double)A1[L1[i]] / dn);
-    __syncthreads();
-    for (int i = tid; i < n; i += T) {
-      CT l, s, g1, g2;
-      row_eval(i, l, s, g1, g2);
-      A1[E2[i]] = g2;
-    }
-    __syncthreads();
-    lds_suffix_sum<T, E, CT>(A1, n, red);
-    for (int i = tid; i < n; i += T) {
-      const double psi = (double)S[i] + (double)A1[L2[i]] / dn;
-      psum += psi;
-      psq += psi * psi;
-    }
-  }
+  };
+  if (rd)
+    rows(double{});
+  else
+    rows(CT{});
   double v[5] = {kl.value(), ksc.value(), ks2.value(), psum, psq};
   block_sum<W, 5>(v, red);
   if (tid == 0) {

@@ -1,0 +1,354 @@
+// rank_wg.h — the workgroup-per-subset rank kernel: ranks of eq. (12) of
+// arXiv:1609.05530 within each subset of the partition (eq. 14), for subsets
+// of up to T*E rows. Each margin is read once from HBM into registers
+// (blocked arrangement), stably radix-sorted by its order-preserving key
+// with the row index as payload (block_rank.h), and tie groups are found in
+// sorted order by two workgroup scans. Outputs per row: the doubled rank
+// R = 2 r (average ranks for ties: R = 2 #{less} + #{equal} + 1, or ties
+// broken by row order), the sorted position and the start of the row's tie
+// group (the last two feed the variance kernel's suffix sums).
+//
+// Only the key bits that vary within the subset are sorted on: the AND and
+// OR of all keys give the varying range, and B-bit digit passes cover it
+// from its lowest bit; a digit that is constant over the subset is skipped.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <type_traits>
+
+#include "block_rank.h"
+#include "kernels.h"
+
+namespace cpc {
+
+// LDS of the rank kernel. ALIAS: the digit counters share memory with the
+// exchange buffer (less LDS, two more barriers per pass). PK (32-bit keys
+// only): key and payload move together as one 64-bit word per element
+// (one scatter per element and pass instead of two).
+template <int T, int E, int B, int KW, bool ALIAS, bool PK>
+struct RankLds {
+  static_assert(!PK || KW == 1, "packed exchange holds 32-bit keys");
+  static constexpr int W = T / WAVE;
+  static constexpr int CAP = T * E;
+  static constexpr int CNT = BlockDigitRank<T, E, B>::kCounterWords;
+  static constexpr int XW = PK ? 2 * CAP : CAP + CAP / 2;  // (u32 key, u32 payload) or u32 keys + u16 payloads
+  static constexpr int MAIN = ALIAS ? (CNT > XW ? CNT : XW) : CNT + XW;
+  alignas(16) uint32_t main[MAIN];  // 16-byte vector reads of keys, payloads, counters
+  uint32_t red[W];
+  uint32_t wl[W * KW];  // last key of each wave
+  int32_t wmax[W], wmin[W];
+  uint32_t andor[4];
+  __device__ __forceinline__ uint32_t* cnt() { return main; }
+  __device__ __forceinline__ uint32_t* xk() { return ALIAS ? main : main + CNT; }
+  __device__ __forceinline__ uint16_t* xv() { return reinterpret_cast<uint16_t*>(xk() + CAP); }
+  __device__ __forceinline__ uint64_t* x64() { return reinterpret_cast<uint64_t*>(xk()); }
+};
+
+template <typename U>
+__device__ __forceinline__ U wave_and(U v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v &= __shfl_xor(v, off, WAVE);
+  return v;
+}
+template <typename U>
+__device__ __forceinline__ U wave_or(U v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Ranks one margin and writes, per row of the subset, R (and the sorted
+// position e and tie-group start lb). Returns true if the margin holds a
+// non-finite value; sets all_tied if every value is equal.
+template <int T, int E, int B, int KW, bool ALIAS, bool PK, typename DT>
+__device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
+                                                RankLds<T, E, B, KW, ALIAS, PK>& sm, uint16_t* Rg, uint16_t* Eg,
+                                                uint16_t* Lg, uint32_t* R32, bool& all_tied) {
+  using Rank = BlockDigitRank<T, E, B>;
+  constexpr int W = T / WAVE;
+  constexpr uint32_t MASK = Rank::kMask;
+  const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+  const int p0 = t * E;
+  const int nv = min(max(n - p0, 0), E);
+  uint32_t* cnt = sm.cnt();
+  uint32_t* xk = sm.xk();
+  uint16_t* xv = sm.xv();
+  all_tied = false;
+  if (n <= 0) return false;
+
+  // load, keys, non-finite flag, AND / OR of the keys. 32-bit keys are read
+  // coalesced and transposed to the blocked arrangement through LDS; 64-bit
+  // keys are read blocked. An item past the end takes the largest key: the
+  // stable sort keeps it behind every valid element, at a position >= n.
+  uint32_t klo[E], khi[E], pay[E];
+  uint64_t kand = ~0ull, kor = 0ull;
+  bool bad = false;
+  if (t == 0) {
+    sm.andor[0] = sm.andor[1] = ~0u;
+    sm.andor[2] = sm.andor[3] = 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < E; ++j) pay[j] = (uint32_t)(p0 + j);
+  if constexpr (KW == 1) {
+    auto load = [&](auto ik) {
+      constexpr bool IK = decltype(ik)::value;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int e = j * T + t;
+        const bool valid = e < n;
+        uint32_t k;
+        if constexpr (IK) {
+          k = ((const uint32_t*)data)[min(e, n - 1)];
+        } else {
+          const DT v = data[min(e, n - 1)];
+          bad |= valid && !isfinite(v);
+          k = key_of((float)v);
+        }
+        kand &= valid ? (uint64_t)k : ~0ull;
+        kor |= valid ? (uint64_t)k : 0ull;
+        xk[e] = valid ? k : ~0u;
+      }
+    };
+    if (int_keys)
+      load(std::true_type{});
+    else
+      load(std::false_type{});
+  } else {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const bool valid = j < nv;
+      const DT v = data[min(p0 + j, n - 1)];
+      bad |= valid && !isfinite(v);
+      uint64_t k = key_of((double)v);
+      kand &= valid ? k : ~0ull;
+      kor |= valid ? k : 0ull;
+      k = valid ? k : ~0ull;
+      klo[j] = (uint32_t)k;
+      khi[j] = (uint32_t)(k >> 32);
+    }
+  }
+  kand = wave_and(kand);
+  kor = wave_or(kor);
+  __syncthreads();  // andor initialised; previous margin's LDS use finished
+  if (lane == 0) {
+    atomicAnd(&sm.andor[0], (uint32_t)kand);
+    atomicAnd(&sm.andor[1], (uint32_t)(kand >> 32));
+    atomicOr(&sm.andor[2], (uint32_t)kor);
+    atomicOr(&sm.andor[3], (uint32_t)(kor >> 32));
+  }
+  __syncthreads();
+  if constexpr (KW == 1) {
+    const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+#pragma unroll
+    for (int q = 0; q < E / 4; ++q) {
+      const uint4 a = sk[q];
+      klo[4 * q] = a.x; klo[4 * q + 1] = a.y; klo[4 * q + 2] = a.z; klo[4 * q + 3] = a.w;
+      khi[4 * q] = khi[4 * q + 1] = khi[4 * q + 2] = khi[4 * q + 3] = 0u;
+    }
+    if (ALIAS) __syncthreads();  // the first pass clears counters over these keys
+  }
+  const uint64_t var = ((((uint64_t)sm.andor[1]) << 32) | sm.andor[0]) ^ ((((uint64_t)sm.andor[3]) << 32) | sm.andor[2]);
+
+  // radix passes over the varying bits; waves wholly past the end sit out
+  // (their items keep their own positions >= n and their payloads)
+  const bool active = w * WAVE * E < n;
+  if (var != 0ull && n > 1) {
+    const int lo = __builtin_ctzll(var);
+    const int hi = 63 - __builtin_clzll(var);
+    const int npass = (hi - lo) / B + 1;
+#pragma unroll 1
+    for (int ps = 0; ps < npass; ++ps) {
+      const int off = lo + ps * B;
+      if (((var >> off) & MASK) == 0ull) continue;  // constant digit: identity pass
+      uint32_t pos[E];
+      Rank::template rank<KW>(klo, khi, off, active, cnt, sm.red, pos);
+      if (ALIAS) __syncthreads();  // counters are read until here
+      if (active) {
+        if constexpr (PK) {
+          uint64_t* x64 = sm.x64();
+#pragma unroll
+          for (int j = 0; j < E; ++j) x64[pos[j]] = ((uint64_t)pay[j] << 32) | klo[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            xk[pos[j]] = klo[j];
+            xv[pos[j]] = (uint16_t)pay[j];
+          }
+        }
+      }
+      __syncthreads();
+      if (active) {
+        if constexpr (PK) {
+          const uint4* sk = reinterpret_cast<const uint4*>(sm.x64() + p0);
+#pragma unroll
+          for (int q = 0; q < E / 2; ++q) {
+            const uint4 a = sk[q];
+            klo[2 * q] = a.x; pay[2 * q] = a.y; klo[2 * q + 1] = a.z; pay[2 * q + 1] = a.w;
+          }
+        } else {
+          const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+          const uint4* sv = reinterpret_cast<const uint4*>(xv + p0);
+#pragma unroll
+          for (int q = 0; q < E / 4; ++q) {
+            const uint4 a = sk[q];
+            klo[4 * q] = a.x; klo[4 * q + 1] = a.y; klo[4 * q + 2] = a.z; klo[4 * q + 3] = a.w;
+          }
+#pragma unroll
+          for (int q = 0; q < E / 8; ++q) {
+            const uint4 a = sv[q];
+            pay[8 * q] = a.x & 0xFFFFu; pay[8 * q + 1] = a.x >> 16;
+            pay[8 * q + 2] = a.y & 0xFFFFu; pay[8 * q + 3] = a.y >> 16;
+            pay[8 * q + 4] = a.z & 0xFFFFu; pay[8 * q + 5] = a.z >> 16;
+            pay[8 * q + 6] = a.w & 0xFFFFu; pay[8 * q + 7] = a.w >> 16;
+          }
+        }
+      }
+      if constexpr (KW == 2) {
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int j = 0; j < E; ++j) xk[pos[j]] = khi[j];
+        }
+        __syncthreads();
+        if (active) {
+          const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+#pragma unroll
+          for (int q = 0; q < E / 4; ++q) {
+            const uint4 a = sk[q];
+            khi[4 * q] = a.x; khi[4 * q + 1] = a.y; khi[4 * q + 2] = a.z; khi[4 * q + 3] = a.w;
+          }
+        }
+      }
+      if (ALIAS) __syncthreads();  // exchange buffer is read until here
+    }
+  }
+
+  // tie groups: a sorted position starts a group unless its key equals its
+  // predecessor's
+  if (lane == WAVE - 1) {
+    sm.wl[w * KW] = klo[E - 1];
+    if (KW == 2) sm.wl[w * KW + KW - 1] = khi[E - 1];
+  }
+  uint32_t plo = __shfl_up(klo[E - 1], 1, WAVE);
+  uint32_t phi = (KW == 2) ? __shfl_up(khi[E - 1], 1, WAVE) : 0u;
+  __syncthreads();
+  if (lane == 0 && w > 0) {
+    plo = sm.wl[(w - 1) * KW];
+    if (KW == 2) phi = sm.wl[(w - 1) * KW + KW - 1];
+  }
+  uint32_t headm = 0u;  // bit j: item j starts a group
+  int hmax = -1, hmin = INT_MAX;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t ql = j ? klo[j - 1] : plo;
+    const uint32_t qh = j ? khi[j - 1] : phi;
+    const bool head = (j < nv) && ((p0 + j == 0) || ql != klo[j] || (KW == 2 && qh != khi[j]));
+    headm |= head ? (1u << j) : 0u;
+    hmax = head ? p0 + j : hmax;
+    hmin = head ? min(hmin, p0 + j) : hmin;
+  }
+  // exclusive max-scan from the left and min-scan from the right
+  int imax = hmax, imin = hmin;
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const int a = __shfl_up(imax, off, WAVE);
+    const int b = __shfl_down(imin, off, WAVE);
+    if (lane >= off) imax = max(imax, a);
+    if (lane + off < WAVE) imin = min(imin, b);
+  }
+  if (lane == WAVE - 1) sm.wmax[w] = imax;
+  if (lane == 0) sm.wmin[w] = imin;
+  int cl = __shfl_up(imax, 1, WAVE);
+  int cr = __shfl_down(imin, 1, WAVE);
+  if (lane == 0) cl = -1;
+  if (lane == WAVE - 1) cr = INT_MAX;
+  __syncthreads();
+  for (int k = 0; k < w; ++k) cl = max(cl, sm.wmax[k]);
+  for (int k = w + 1; k < W; ++k) cr = min(cr, sm.wmin[k]);
+  cr = min(cr, n);
+  uint32_t lb[E], ub[E];
+  {
+    int cur = cl;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((headm >> j) & 1u) cur = p0 + j;
+      lb[j] = (uint32_t)cur;
+    }
+    cur = cr;
+#pragma unroll
+    for (int j = E - 1; j >= 0; --j) {
+      ub[j] = (uint32_t)cur;
+      if ((headm >> j) & 1u) cur = p0 + j;
+    }
+  }
+  all_tied = (n >= 1) && (t == 0) && (ub[0] >= (uint32_t)n);
+  // R, sorted position and group start, scattered to row order in LDS
+  uint16_t* xl = xv;
+  // (an item past the end carries a payload >= n)
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const uint32_t e = (uint32_t)(p0 + j);
+    const uint32_t R = (ties == 1) ? 2u * (e + 1u) : lb[j] + ub[j] + 1u;
+    const uint32_t l = (ties == 1) ? e : lb[j];
+    xk[pay[j]] = R | (e << 16);
+    xl[pay[j]] = (uint16_t)l;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += T) {
+    const uint32_t v = xk[i];
+    if (R32) {
+      R32[i] = v & 0xFFFFu;
+    } else {
+      Rg[i] = (uint16_t)(v & 0xFFFFu);
+      Eg[i] = (uint16_t)(v >> 16);
+      Lg[i] = xl[i];
+    }
+  }
+  __syncthreads();
+  return bad;
+}
+
+template <int T, int E, int B, int KW, bool ALIAS, bool PK>
+__global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
+  __shared__ RankLds<T, E, B, KW, ALIAS, PK> sm;
+  const int sid = P.order[blockIdx.x];
+  const SubDesc sd = P.subs[sid];
+  const int n = sd.n;
+  if (P.mode != MODE_RANK && (int64_t)n < P.n_min) {
+    if (threadIdx.x == 0) {
+      P.state[sid].status = ST_DEGENERATE;
+      P.state[sid].iters = 0;
+      P.state[sid].theta = NAN;
+    }
+    return;
+  }
+  const bool rk = P.mode == MODE_RANK;
+  bool t1, t2, b1, b2;
+  const int64_t o = sd.begin;
+  if constexpr (KW == 2) {
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, PK, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
+                                                     P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, PK, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
+                                                     P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
+  } else {
+    const bool ik = P.int_keys != 0;
+    const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
+    const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, PK, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
+                                                    P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, PK, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
+                                                    P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
+  }
+  if (rk) return;
+  const bool bad = __syncthreads_or((int)(b1 || b2)) != 0;
+  // all_tied is known to thread 0 only
+  if (threadIdx.x == 0) {
+    P.state[sid].status = bad ? ST_NONFINITE : ((t1 || t2) ? ST_DEGENERATE : ST_OK);
+    P.state[sid].iters = 0;
+    P.state[sid].theta = NAN;
+  }
+}
+
+}  // namespace cpc
