@@ -3,8 +3,8 @@ on one MI355X.
 
 One step = one cpc_fit_batched over the whole workload: ranks (eq. 12), the
 maximisation of eq. (13) for every subset, the Sec. 2.3 variances and the
-eq. (15)/(16) combination per group. Inputs are resident in HBM before the
-timed region. Prints one JSON line.
+eq. (15)/(16) combination per group, replayed as one captured hipGraph.
+Inputs are resident in HBM before the timed region. Prints one JSON line.
 
 Default workload (the shape the headline metric is quoted on, n = 1e7 per
 setting): Frank theta in {-10, -1, 0.01, 1, 10, 30} and Gaussian rho in
@@ -14,8 +14,11 @@ sizes ~ U[5000, 15000] renormalised; 9 groups, 9000 subset fits per step.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,6 +37,12 @@ if ROOT not in sys.path:
 #   Gaussian (one pass):   AS 241 x2 (rcp + ~10 FMA)  -> 8 + 23
 SLOTS_PER_ROW_PASS = {"frank": 46.0, "gumbel": 60.0, "gaussian": 31.0}
 PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock (non-packed FP32 VALU)
+PEAK_HBM = 8.0e12                       # bytes/s
+# Algorithmic HBM bytes per row of the rank step: read x, y (FP32) and write
+# the two u16 doubled ranks.
+RANK_BYTES_PER_ROW = 4 + 4 + 2 + 2
+RANK_SOURCES = ["paper_1609_05530_amd/csrc/rank_wg.h", "paper_1609_05530_amd/csrc/block_rank.h",
+                "paper_1609_05530_amd/csrc/k_rank.hip"]
 
 
 def parse():
@@ -45,10 +54,33 @@ def parse():
     ap.add_argument("--n", type=int, default=10_000_000, help="rows per setting")
     ap.add_argument("--K", type=int, default=1000, help="subsets per setting")
     ap.add_argument("--settings", default="all", help="'all' or a comma list of indices into the 9 settings")
+    ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3, help="subsets per setting in the CPU-baseline sample")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler (no oracle, no checks)")
     return ap.parse_args()
+
+
+def rank_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in RANK_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_rank_traffic():
+    """HBM bytes per step of the rank kernels from the committed rocprofv3 PMC
+    summary, if it was taken on the current rank sources (else None)."""
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*rank*pmc*.md")):
+        with open(path) as f:
+            text = f.read()
+        m_hash = re.search(r"rank_source_sha256_16:\s*([0-9a-f]+)", text)
+        m_bytes = re.search(r"rank_hbm_bytes_per_step:\s*([0-9.eE+]+)", text)
+        if m_hash and m_bytes and m_hash.group(1) == rank_source_hash():
+            return float(m_bytes.group(1))
+    return None
 
 
 def main():
@@ -71,27 +103,35 @@ def main():
     y = torch.from_numpy(w.y).to(dev)
     fams = w.families
     K, G, n = w.K, w.G, w.n
-    ws = torch.empty(cpc.workspace_bytes(n, K, G, dtype=x.dtype, prec=a.prec), dtype=torch.uint8, device=dev)
-    out = cpc.FitResult(torch.empty((K, 6), dtype=torch.float64, device=dev),
-                        torch.empty((G, 5), dtype=torch.float64, device=dev))
-    opt = dict(prec=a.prec)
+    graph = not a.no_graph
 
-    def step(**kw):
-        cpc.fit_batched(x, y, w.offsets, w.group_offsets, fams, workspace=ws, out=out, **opt, **kw)
+    def make_step(prec):
+        ws = torch.empty(cpc.workspace_bytes(n, K, G, dtype=x.dtype, prec=prec), dtype=torch.uint8, device=dev)
+        out = cpc.FitResult(torch.empty((K, 6), dtype=torch.float64, device=dev),
+                            torch.empty((G, 5), dtype=torch.float64, device=dev))
 
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(a.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_step = ev0.elapsed_time(ev1) / a.steps
+        def step(**kw):
+            g = graph and not kw.get("phase_times", False)
+            cpc.fit_batched(x, y, w.offsets, w.group_offsets, fams, workspace=ws, out=out, prec=prec, graph=g, **kw)
+        return step, out
+
+    def timed(step, steps, warmup):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t_start = time.perf_counter()
+        evs[0].record()
+        for i in range(steps):
+            step()
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(steps)])
+        return float(evs[0].elapsed_time(evs[-1]) / steps), float(np.median(per)), wall
+
+    step, out = make_step(a.prec)
+    ms_step, ms_median, wall = timed(step, a.steps, a.warmup)
 
     if a.profile:
         # a plain device copy of known size (x: 4 bytes x rows) to scale the
@@ -125,7 +165,11 @@ def main():
         slots += float(np.sum(nsub[sel] * passes)) * SLOTS_PER_ROW_PASS[fam]
         obs_evals += float(np.sum(nsub[sel] * (passes + 1.0)))  # + the variance pass
     fit_s = phases[1] / 1e3
-    achieved = slots / fit_s if fit_s > 0 else 0.0
+    achieved_fit = slots / fit_s if fit_s > 0 else 0.0
+    rank_s = phases[0] / 1e3
+    rank_bytes = float(n) * RANK_BYTES_PER_ROW
+    achieved_rank = rank_bytes / rank_s if rank_s > 0 else 0.0
+    traffic = measured_rank_traffic()
 
     line = {
         "metric": "subset-fits/sec (batched MPL copula fits, n=1e7 per setting)",
@@ -135,6 +179,7 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": ms_median,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -146,23 +191,44 @@ def main():
             "subset_fits_per_step": K,
             "rows_per_step": n,
             "precision": a.prec,
+            "launch": "hipGraph replay" if graph else "eager",
         },
         "obs_evals_per_s": obs_evals / (ms_step / 1e3),
+        "obs_evals_per_s_eval_kernels": obs_evals / ((phases[1] + phases[2]) / 1e3),
         "phase_ms": {"rank": phases[0], "fit": phases[1], "variance": phases[2], "combine": phases[3]},
         "newton_passes_mean": float(np.mean(iters[status == 0])) if np.any(status == 0) else None,
         "status_counts": {str(int(s)): int(np.sum(status == s)) for s in np.unique(status)},
         "wall_s_timed": wall,
         "gen_s": gen_s,
         "roofline": {
+            "kernel": "k_rank_wg (ranks of eq. 12; all its launches in one step)",
+            "bound": "hbm",
+            "achieved": achieved_rank / 1e9,
+            "peak": PEAK_HBM / 1e9,
+            "unit": "GB/s",
+            "frac": achieved_rank / PEAK_HBM,
+            "traffic": traffic,
+            "algorithmic_bytes": rank_bytes,
+        },
+        "roofline_fit": {
             "kernel": "k_fit_wg (Newton passes of eq. 13)",
             "bound": "alu",
-            "achieved": achieved / 1e12,
+            "achieved": achieved_fit / 1e12,
             "peak": PEAK_LANE_SLOTS / 1e12,
             "unit": "T VALU lane-slots/s",
-            "frac": achieved / PEAK_LANE_SLOTS,
+            "frac": achieved_fit / PEAK_LANE_SLOTS,
             "traffic": None,
         },
     }
+
+    if not a.profile and not a.no_fp64_compare and a.prec == "fp32c":
+        step64, out64 = make_step("fp64")
+        ms64, med64, _ = timed(step64, max(3, a.steps // 4), 1)
+        line["fp64_path"] = {"ms_per_step": ms64, "ms_per_step_median": med64,
+                             "speedup_fp32c_over_fp64": ms64 / ms_step}
+        theta64 = out64.theta.cpu().numpy()
+    else:
+        theta64 = None
 
     if not a.profile:
         import oracle.oracle as O
@@ -181,10 +247,13 @@ def main():
         sub, _ = O.fit(np.concatenate(xs), np.concatenate(ys), off, fams, gofs, nthreads=nt)
         cpu_s = time.perf_counter() - t0
         ref = sub["theta"]
-        got = theta[pick]
         ok = (sub["status"] == 0) & (status[pick] == 0)
         floor = np.array([0.1 if fam_of[m] == "frank" else 1e-3 for m in pick])
-        rel = np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), floor[ok])
+
+        def rel_err(th):
+            got = th[pick]
+            return np.abs(got[ok] - ref[ok]) / np.maximum(np.abs(ref[ok]), floor[ok])
+        rel = rel_err(theta)
         vrel = np.abs(out.var.cpu().numpy()[pick][ok] / sub["var"][ok] - 1.0)
         line["err_vs_oracle"] = {
             "subsets_checked": int(ok.sum()),
@@ -193,6 +262,9 @@ def main():
             "var_max_rel": float(vrel.max(initial=0)),
             "status_match": bool(np.array_equal(sub["status"], status[pick])),
         }
+        if theta64 is not None:
+            rel64 = rel_err(theta64)
+            line["fp64_path"]["theta_max_rel_vs_oracle"] = float(rel64.max(initial=0))
         line["cpu_baseline"] = {
             "value": len(pick) / cpu_s,
             "unit": "subset-fits/s",

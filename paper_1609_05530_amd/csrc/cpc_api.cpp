@@ -26,6 +26,8 @@ struct cpc_context {
   hipEvent_t ev[5];         // phase boundaries of the last fit (CPC_FLAG_PHASE_TIMES)
   int have_times;
   int* pending_host;        // pinned: subsets of the streaming path still iterating
+  hipStream_t cap_stream;   // the fit is captured here in graph mode (default priority)
+  void* graph;              // GraphCache: the instantiated graph of the last graph-mode call
 };
 
 static constexpr int kMagic = 0x43504331;
@@ -300,6 +302,53 @@ int check_handle(cpc_handle_t h) {
   return CPC_SUCCESS;
 }
 
+// Graph mode (CPC_FLAG_GRAPH): the kernels of a fit are captured once into a
+// hipGraph and replayed while the call's arguments stay the same. The launch
+// tables are uploaded before capture, so the graph holds kernels only. The
+// key is every pointer, size and option of the call plus the offsets, group
+// offsets and families; a replay also requires that the workspace still
+// holds the tables of the capture, so any other call through this handle
+// with the same workspace drops the cached graph.
+struct GraphCache {
+  bool valid = false;
+  const void *x = nullptr, *y = nullptr;
+  int32_t dtype = 0;
+  int64_t n = 0, K = 0, G = 0;
+  std::vector<int64_t> offsets, gofs;
+  std::vector<int32_t> fam;
+  Options o{};
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void *out = nullptr, *comb = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  void drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    valid = false;
+  }
+  bool same(const void* x_, const void* y_, int32_t dtype_, int64_t n_, const int64_t* off_, int64_t K_,
+            const int64_t* gofs_, int64_t G_, const std::vector<int32_t>& fam_, const Options& o_, void* ws_,
+            size_t ws_bytes_, void* out_, void* comb_) const {
+    return valid && x == x_ && y == y_ && dtype == dtype_ && n == n_ && K == K_ && G == G_ && ws == ws_ &&
+           ws_bytes == ws_bytes_ && out == out_ && comb == comb_ && o.prec == o_.prec && o.ties == o_.ties &&
+           o.var == o_.var && o.max_iter == o_.max_iter && o.tol == o_.tol && o.n_min == o_.n_min &&
+           o.flags == o_.flags && std::equal(offsets.begin(), offsets.end(), off_) &&
+           std::equal(gofs.begin(), gofs.end(), gofs_) && fam == fam_;
+  }
+};
+
+GraphCache& graph_of(cpc_handle_t h) { return *(GraphCache*)h->graph; }
+
+// Any call that writes into `ws` invalidates a graph captured over it.
+void touch_workspace(cpc_handle_t h, const void* ws) {
+  GraphCache& gc = graph_of(h);
+  if (gc.valid && gc.ws == ws) gc.drop();
+}
+
+int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
+                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph, hipStream_t s);
+
 // The full fit path for validated arguments.
 int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
             int64_t K, const int64_t* gofs, int64_t G, const std::vector<int32_t>& fam_of_subset,
@@ -309,16 +358,62 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   if (!ws) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < L.total)
     return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
+  const bool graph = (o.flags & CPC_FLAG_GRAPH) != 0;
+  if (graph && (o.flags & CPC_FLAG_PHASE_TIMES))
+    return fail(CPC_E_OPTIONS, "phase times are not recorded in graph mode");
+  GraphCache& gc = graph_of(h);
+  HIP_OK(hipSetDevice(h->device));
+  if (graph && gc.same(x, y, dtype, n, offsets, K, gofs, G, fam_of_subset, o, ws, ws_bytes, out, comb)) {
+    h->have_times = 0;
+    HIP_OK(hipGraphLaunch(gc.exec, s));
+    return CPC_SUCCESS;
+  }
+  touch_workspace(h, ws);
   Plan& P = plan_of(h);
   int rc = make_plan(offsets, K, fam_of_subset.data(), P);
   if (rc) return rc;
-  HIP_OK(hipSetDevice(h->device));
   Carved c = carve(ws, L);
-  const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
   h->have_times = 0;
   P.gofs.assign(gofs, gofs + G + 1);
   rc = upload_tables(h, P, c, P.gofs.data(), G, s);
   if (rc) return rc;
+  set_big(c, P, o.n_min);
+  if (!graph) return enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, false, s);
+
+  // capture on the handle's stream once the uploads on `s` are done
+  HIP_OK(hipStreamSynchronize(s));
+  HIP_OK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, true, h->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (ec != hipSuccess) return fail(CPC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return fail(CPC_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  gc.drop();
+  gc.x = x; gc.y = y; gc.dtype = dtype; gc.n = n; gc.K = K; gc.G = G;
+  gc.offsets.assign(offsets, offsets + K + 1);
+  gc.gofs.assign(gofs, gofs + G + 1);
+  gc.fam = fam_of_subset;
+  gc.o = o; gc.ws = ws; gc.ws_bytes = ws_bytes; gc.out = out; gc.comb = comb;
+  gc.exec = ex;
+  gc.valid = true;
+  HIP_OK(hipGraphLaunch(ex, s));
+  return CPC_SUCCESS;
+}
+
+// The launch sequence of a fit (tables already in the workspace):
+// rank -> fit -> variance -> combine. In graph mode nothing here waits on
+// the host: the streaming path's Newton loop runs its full pass budget, its
+// kernels returning at once when every subset is done.
+int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
+                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph, hipStream_t s) {
+  const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
   const int kw = (dtype == CPC_F64) ? 2 : 1;
   const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
 
@@ -333,7 +428,6 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   rp.n_min = o.n_min;
   rp.rows = c.rows;
   rp.state = c.state;
-  set_big(c, P, o.n_min);
   if (timed) HIP_OK(hipEventRecord(h->ev[0], s));
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
@@ -352,7 +446,7 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
     fp.order = c.order_fit + b.first;
     HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
   }
-  HIP_OK(big_solve(c.big, c.bb, o.tol, o.max_iter, fp64, h->pending_host, s));
+  HIP_OK(big_solve(c.big, c.bb, o.tol, o.max_iter, fp64, graph ? nullptr : h->pending_host, s));
   if (timed) HIP_OK(hipEventRecord(h->ev[2], s));
   VarParams vp;
   std::memset(&vp, 0, sizeof(vp));
@@ -405,15 +499,26 @@ int cpc_create(int device, cpc_handle_t* out) {
   h->plan = new Plan();
   h->have_times = 0;
   h->pending_host = nullptr;
+  h->graph = new GraphCache();
   if (hipHostMalloc((void**)&h->pending_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete (GraphCache*)h->graph;
     delete (Plan*)h->plan;
     delete h;
     return fail(CPC_E_HIP, "hipHostMalloc failed");
   }
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipHostFree(h->pending_host);
+    delete (GraphCache*)h->graph;
+    delete (Plan*)h->plan;
+    delete h;
+    return fail(CPC_E_HIP, "hipStreamCreateWithFlags failed");
+  }
   for (int i = 0; i < 5; ++i) {
     if (hipEventCreate(&h->ev[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->ev[j]);
+      (void)hipStreamDestroy(h->cap_stream);
       (void)hipHostFree(h->pending_host);
+      delete (GraphCache*)h->graph;
       delete (Plan*)h->plan;
       delete h;
       return fail(CPC_E_HIP, "hipEventCreate failed");
@@ -426,6 +531,10 @@ int cpc_create(int device, cpc_handle_t* out) {
 int cpc_destroy(cpc_handle_t h) {
   if (int rc = check_handle(h)) return rc;
   h->magic = 0;
+  (void)hipSetDevice(h->device);
+  graph_of(h).drop();
+  delete (GraphCache*)h->graph;
+  (void)hipStreamDestroy(h->cap_stream);
   for (int i = 0; i < 5; ++i) (void)hipEventDestroy(h->ev[i]);
   (void)hipHostFree(h->pending_host);
   delete (Plan*)h->plan;
@@ -504,6 +613,7 @@ int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_
   if (int rc = make_plan(offsets, K, fam.data(), P)) return rc;
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
+  touch_workspace(h, workspace);
   Carved c = carve(workspace, L);
   if (int rc = upload_tables(h, P, c, nullptr, 0, s)) return rc;
   RankParams rp;
@@ -547,6 +657,7 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
   if (int rc = make_plan(offsets, K, fam.data(), P)) return rc;
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
+  touch_workspace(h, workspace);
   Carved c = carve(workspace, L);
   if (int rc = upload_tables(h, P, c, nullptr, 0, s)) return rc;
   // re-rank from the given ranks (integer keys): sorted positions and tie groups
@@ -608,6 +719,7 @@ int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, 
   }
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
+  touch_workspace(h, workspace);
   Carved c = carve(workspace, L);
   HIP_OK(hipMemcpyAsync(c.subs, subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
   HIP_OK(launch_eval_wg(R1, R2, c.subs, K, family, o.prec == CPC_PREC_FP64 ? 1 : 0, theta, out, s));

@@ -72,6 +72,11 @@ struct KSum {
   __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
+// Per-thread sum of per-row terms, compensated in the row arithmetic type
+// (Kahan); the workgroup then combines the per-thread values in FP64.
+template <typename T>
+using RowSum = KSum<T>;
+
 // ---------------------------------------------------------------------------
 // Reductions with a fixed tree: wave butterfly, then wave partials summed in
 // wave order by thread 0. Results are returned to thread 0 only.

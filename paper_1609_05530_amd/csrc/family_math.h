@@ -23,7 +23,27 @@
 
 namespace cpc {
 
-CPC_HD float m_exp(float x) { return expf(x); }
+// FP32 exp and reciprocal of the row paths. In GPU code they go straight to
+// the transcendental units: exp(x) = 2^t 2^e with t = fl(x log2 e) and the
+// rounding error e = x log2 e - t recovered by two FMAs (log2 e split into a
+// float head and tail), 2^t by v_exp_f32 and 2^e by 1 + e ln 2 (|e| <= 2^-17
+// for the bounded arguments the rows pass); 1/x by v_rcp_f32. Both are within
+// a few ulp, far inside what the FP32 rows tolerate, at a third of the
+// instructions of the correctly rounded library routines. The host build
+// (used only by unit tests of the formulas) calls libm.
+CPC_HD float m_exp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  constexpr float kL2E = 1.44269502162933349609375f;  // float(log2 e)
+  constexpr float kL2ELo = 1.925963033500011e-08f;     // log2 e - kL2E
+  constexpr float kLn2 = 0.693147182464599609375f;
+  const float t = x * kL2E;
+  const float e = fmaf(x, kL2ELo, fmaf(x, kL2E, -t));
+  const float r = __builtin_amdgcn_exp2f(t);
+  return fmaf(r, e * kLn2, r);
+#else
+  return expf(x);
+#endif
+}
 CPC_HD double m_exp(double x) { return exp(x); }
 CPC_HD float m_log(float x) { return logf(x); }
 CPC_HD double m_log(double x) { return log(x); }
@@ -33,7 +53,13 @@ CPC_HD float m_expm1(float x) { return expm1f(x); }
 CPC_HD double m_expm1(double x) { return expm1(x); }
 CPC_HD float m_sqrt(float x) { return sqrtf(x); }
 CPC_HD double m_sqrt(double x) { return sqrt(x); }
-CPC_HD float m_rcp(float x) { return 1.0f / x; }
+CPC_HD float m_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
 CPC_HD double m_rcp(double x) { return 1.0 / x; }
 CPC_HD float m_abs(float x) { return fabsf(x); }
 CPC_HD double m_abs(double x) { return fabs(x); }
@@ -108,20 +134,20 @@ CPC_HD float qnorm_ppnd7(int64_t R, int64_t twon1) {
   const float q = (float)(2 * R - twon1) * 0.5f * inv;
   if (fabsf(q) <= 0.425f) {
     const float r = 0.180625f - q * q;
-    return q * (((59.109374720f * r + 159.29113202f) * r + 50.434271938f) * r + 3.3871327179f) /
-           (((67.187563600f * r + 78.757757664f) * r + 17.895169469f) * r + 1.0f);
+    return q * (((59.109374720f * r + 159.29113202f) * r + 50.434271938f) * r + 3.3871327179f) *
+           m_rcp(((67.187563600f * r + 78.757757664f) * r + 17.895169469f) * r + 1.0f);
   }
   const int64_t m = (2 * R < twon1) ? R : (twon1 - R);
   float r = sqrtf(-logf((float)m * inv));
   float z;
   if (r <= 5.0f) {
     r -= 1.6f;
-    z = (((0.17023821103f * r + 1.3067284816f) * r + 2.7568153900f) * r + 1.4234372777f) /
-        ((0.12021132975f * r + 0.73700164250f) * r + 1.0f);
+    z = (((0.17023821103f * r + 1.3067284816f) * r + 2.7568153900f) * r + 1.4234372777f) *
+        m_rcp((0.12021132975f * r + 0.73700164250f) * r + 1.0f);
   } else {
     r -= 5.0f;
-    z = (((0.017337203997f * r + 0.42868294337f) * r + 3.0812263860f) * r + 6.6579051150f) /
-        ((0.012258202635f * r + 0.24197894225f) * r + 1.0f);
+    z = (((0.017337203997f * r + 0.42868294337f) * r + 3.0812263860f) * r + 6.6579051150f) *
+        m_rcp((0.012258202635f * r + 0.24197894225f) * r + 1.0f);
   }
   return (q < 0.0f) ? -z : z;
 }
@@ -209,6 +235,7 @@ template <typename T>
 struct FrankConst {
   T th, e, C1, C2;  // theta (> 0), e^{-theta}, 1/theta + e/E, -1/theta^2 - e/E - (e/E)^2
   T Eh, iEh, psi;   // E/theta, theta/E, (E/theta - e)/theta (scaled form, small theta)
+  T ith;            // 1/theta
   double logthE;    // log(theta E)
   double logth;     // log(theta)
 };
@@ -223,6 +250,7 @@ CPC_HD FrankConst<T> frank_const(double th) {
   k.Eh = (T)(E / th);
   k.iEh = (T)(th / E);
   k.psi = (T)((E - th * e) / (th * th));
+  k.ith = (T)(1.0 / th);
   k.logthE = log(th * E);
   k.logth = log(th);
   return k;
@@ -265,17 +293,19 @@ CPC_HD FrankTerms<T> frank_terms(const FrankConst<T>& k, T u, T v, T omv) {
   t.r1 = t.Dp * t.iD;
   return t;
 }
-// Newton pass: score and Hessian per row.
-template <typename T>
+// Newton pass: score and Hessian per row. FORM: 1 the scaled form (FP32,
+// theta below FRANK_SCALED_BELOW), 0 the direct form, -1 chosen here.
+template <typename T, int FORM = -1>
 CPC_HD void frank_sh(const FrankConst<T>& k, T u, T v, T omv, T& s, T& h) {
-  if (sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW) {
+  const bool scaled = FORM == 1 || (FORM == -1 && sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW);
+  if (scaled) {
     const T th = k.th;
-    const T Ah = -m_expm1(-th * u) / th, Bh = -m_expm1(-th * v) / th;
+    const T Ah = -m_expm1(-th * u) * k.ith, Bh = -m_expm1(-th * v) * k.ith;
     const T a = (T)1 - th * Ah, b = (T)1 - th * Bh;
     const T iDh = m_rcp(k.Eh - th * Ah * Bh);
     const T P = u * a * Bh + v * b * Ah;
     s = (k.Eh * k.psi - Ah * Bh * (k.Eh + k.e)) * k.iEh * iDh - (u + v) + (T)2 * P * iDh;
-    const T ith = (T)1 / th;
+    const T ith = k.ith;
     const T r1 = (k.e - th * P) * iDh * ith;
     const T r2 = (-k.e + th * (u * u * a * Bh + v * v * b * Ah) - (T)2 * u * v * a * b) * iDh * ith;
     h = k.C2 - (T)2 * r2 + (T)2 * r1 * r1;
@@ -288,11 +318,12 @@ CPC_HD void frank_sh(const FrankConst<T>& k, T u, T v, T omv, T& s, T& h) {
   h = k.C2 - (T)2 * r2 + (T)2 * t.r1 * t.r1;
 }
 // Variance pass: l (without log(theta E)), score, d2l/dtheta du, d2l/dtheta dv.
-template <typename T>
+template <typename T, int FORM = -1>
 CPC_HD void frank_full(const FrankConst<T>& k, T u, T v, T omv, T& l, T& s, T& g1, T& g2) {
   const T th = k.th;
-  if (sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW) {
-    const T Ah = -m_expm1(-th * u) / th, Bh = -m_expm1(-th * v) / th;
+  const bool scaled = FORM == 1 || (FORM == -1 && sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW);
+  if (scaled) {
+    const T Ah = -m_expm1(-th * u) * k.ith, Bh = -m_expm1(-th * v) * k.ith;
     const T a = (T)1 - th * Ah, b = (T)1 - th * Bh;
     const T Dh = k.Eh - th * Ah * Bh;
     const T iDh = m_rcp(Dh);

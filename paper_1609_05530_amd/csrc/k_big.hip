@@ -260,8 +260,10 @@ __global__ void __launch_bounds__(256) k_big_start_update(BigParams P, const dou
 // One Newton pass: per-tile sums of the score, Hessian and squared score.
 template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1, const uint32_t* R2, const CT* LX,
-                                                 const CT* LY, const NewtonState* st, double* part) {
+                                                 const CT* LY, const NewtonState* st, double* part,
+                                                 const int* pending) {
   __shared__ double red[(BT / WAVE) * 3];
+  if (*pending == 0) return;  // every subset has converged
   const BigTile t = P.tiles[blockIdx.x];
   const BigSeg s = P.segs[t.seg];
   if (st[t.seg].done) return;  // uniform per tile
@@ -283,7 +285,7 @@ __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1
     }
     v[0] = ks.value(); v[1] = kh.value(); v[2] = s2;
   } else {
-    KSum<CT> ks, kh;
+    RowSum<CT> ks, kh;
     CT s2 = (CT)0;
     for (int i = threadIdx.x; i < t.count; i += BT) {
       const int64_t q = s.roff + t.start + i;
@@ -300,6 +302,7 @@ __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1
 __global__ void __launch_bounds__(256) k_big_update(BigParams P, const double* part, NewtonState* st, double tol,
                                                     int max_iter, int fp64, int* pending) {
   __shared__ int cnt;
+  if (*pending == 0) return;  // every subset has converged (the count stays 0)
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
   int mine = 0;
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(BT) k_big_var_rows(BigParams P, const uint32_t
   const Consts<CT> c = make_consts<CT>(fam, th);
   const Consts<double> cd = make_consts<double>(fam, th);
   const bool rd = sizeof(CT) == 4 && c.use_d;
-  KSum<CT> kl, ks, k2;
+  RowSum<CT> kl, ks, k2;
   for (int i = threadIdx.x; i < t.count && !skip; i += BT) {
     const int64_t q = s.roff + t.start + i;
     const uint32_t a = R1[q], b = R2[q];
@@ -552,12 +555,15 @@ static hipError_t big_solve_t(const BigParams& P, const BigBuffers& B, double to
   hipLaunchKernelGGL((k_big_start<CT>), dim3(nt), dim3(BT), 0, s, P, B.R1, B.R2, (CT*)B.LX, (CT*)B.LY, B.part);
   hipLaunchKernelGGL(k_big_start_update, dim3(1), dim3(256), 0, s, P, B.part, B.st, tol, B.pending);
   // Newton passes in blocks of 4; the host stops once every subset is done.
+  // Without a host flag (graph capture) every pass of the budget is enqueued
+  // and the passes after convergence return at once on the device counter.
   for (int it = 0; it < max_iter; it += 4) {
     for (int k = 0; k < 4 && it + k < max_iter; ++k) {
       hipLaunchKernelGGL((k_big_eval<CT>), dim3(nt), dim3(BT), 0, s, P, B.R1, B.R2, (const CT*)B.LX, (const CT*)B.LY,
-                         B.st, B.part);
+                         B.st, B.part, B.pending);
       hipLaunchKernelGGL(k_big_update, dim3(1), dim3(256), 0, s, P, B.part, B.st, tol, max_iter, fp64, B.pending);
     }
+    if (!pending_host) continue;
     hipError_t e = hipMemcpyAsync(pending_host, B.pending, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);

@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(T) k_eval_wg(const uint32_t* R1, const uint32_
   }
   const Consts<CT> c = make_consts<CT>(fam, th);
   const uint32_t twon1 = 2u * (uint32_t)(n + 1);
-  KSum<CT> kl, ks, kh;
+  RowSum<CT> kl, ks, kh;
   for (int i = threadIdx.x; i < n; i += T) {
     CT l, s, h, g1, g2;
     row_lshf<CT>(c, R1[sd.begin + i], R2[sd.begin + i], twon1, l, s, h, g1, g2);

@@ -13,6 +13,8 @@
 //     Newton step.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "solver.h"
 
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(T) k_fit_wg(FitParams P) {
       v[0] = kp.value();
       v[1] = km.value();
     } else {
-      KSum<CT> kp, km;
+      RowSum<CT> kp, km;
       for (int i = tid; i < n; i += T) {
         const uint32_t r = sm.rr[i];
         CT z1, z2;
@@ -127,28 +129,40 @@ __global__ void __launch_bounds__(T) k_fit_wg(FitParams P) {
         v[2] = s2;
         noise = 16.0 * 1.1102230246251565e-16;
       } else {
-        KSum<CT> ks, kh;
-        CT s2 = (CT)0;
-        for (int i = tid; i < n; i += T) {
-          CT s, h;
-          if constexpr (FAM == FAM_FRANK) {
-            const uint32_t r = sm.rr[i];
-            frank_rsh<CT>(c, r & 0xFFFFu, r >> 16, twon1, inv, s, h);
-          } else if constexpr (SM::GC) {
-            gumbel_sh(c.gk, sm.lx[i], sm.ly[i], s, h);
-          } else {
-            const uint32_t r = sm.rr[i];
-            CT lx, ly;
-            gumbel_lxy<CT>(r & 0xFFFFu, r >> 16, twon1, inv, lx, ly);
-            gumbel_sh(c.gk, lx, ly, s, h);
+        // the Frank form (scaled / direct) is fixed per pass, outside the row loop
+        auto pass = [&](auto form_tag) {
+          constexpr int FORM = decltype(form_tag)::value;
+          RowSum<CT> ks, kh;
+          CT s2 = (CT)0;
+#pragma unroll 2
+          for (int i = tid; i < n; i += T) {
+            CT s, h;
+            if constexpr (FAM == FAM_FRANK) {
+              const uint32_t r = sm.rr[i];
+              frank_rsh<CT, FORM>(c, r & 0xFFFFu, r >> 16, twon1, inv, s, h);
+            } else if constexpr (SM::GC) {
+              gumbel_sh(c.gk, sm.lx[i], sm.ly[i], s, h);
+            } else {
+              const uint32_t r = sm.rr[i];
+              CT lx, ly;
+              gumbel_lxy<CT>(r & 0xFFFFu, r >> 16, twon1, inv, lx, ly);
+              gumbel_sh(c.gk, lx, ly, s, h);
+            }
+            ks.add(s);
+            kh.add(h);
+            s2 += s * s;
           }
-          ks.add(s);
-          kh.add(h);
-          s2 += s * s;
-        }
-        v[0] = ks.value();
-        v[1] = kh.value();
-        v[2] = (double)s2;
+          v[0] = ks.value();
+          v[1] = kh.value();
+          v[2] = (double)s2;
+        };
+        const bool scaled = FAM == FAM_FRANK && sizeof(CT) == 4 && c.fk.th < (CT)FRANK_SCALED_BELOW;
+        if (FAM != FAM_FRANK || sizeof(CT) == 8)
+          pass(std::integral_constant<int, -1>{});
+        else if (scaled)
+          pass(std::integral_constant<int, 1>{});
+        else
+          pass(std::integral_constant<int, 0>{});
         noise = 16.0 * (sizeof(CT) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
       }
       block_sum<W, 3>(v, red);

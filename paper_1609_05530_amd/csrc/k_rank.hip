@@ -7,16 +7,15 @@
 namespace cpc {
 
 // Launch shapes per size class: (threads, items per thread, digit bits,
-// counters sharing LDS with the exchange buffer, packed key + payload
-// exchange for 32-bit keys). The class capacity threads * items must match
-// kClassThreads * kClassItems.
-template <int T, int E, int B, bool ALIAS, bool PK>
+// counters sharing LDS with the exchange buffer, 32-bit payloads). The class
+// capacity threads * items must match kClassThreads * kClassItems.
+template <int T, int E, int B, bool ALIAS, bool P32>
 static hipError_t launch_t(int kw, const RankParams& p, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (kw == 2)
-    hipLaunchKernelGGL((k_rank_wg<T, E, B, 2, ALIAS, false>), dim3(grid), dim3(T), 0, s, p);
+    hipLaunchKernelGGL((k_rank_wg<T, E, B, 2, ALIAS, P32>), dim3(grid), dim3(T), 0, s, p);
   else
-    hipLaunchKernelGGL((k_rank_wg<T, E, B, 1, ALIAS, PK>), dim3(grid), dim3(T), 0, s, p);
+    hipLaunchKernelGGL((k_rank_wg<T, E, B, 1, ALIAS, P32>), dim3(grid), dim3(T), 0, s, p);
   return hipGetLastError();
 }
 

@@ -92,8 +92,9 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
   // Row arithmetic in RT (CT, or double near the family boundaries), results
   // in CT. The choice is uniform over the workgroup and made once, outside
   // the row loops.
-  auto row_eval_t = [&](auto rt_tag, int i, CT& l, CT& s, CT& g1, CT& g2) {
+  auto row_eval_t = [&](auto rt_tag, auto form_tag, int i, CT& l, CT& s, CT& g1, CT& g2) {
     using RT = decltype(rt_tag);
+    constexpr int FORM = decltype(form_tag)::value;
     const uint32_t a = R1[i], b = R2[i];
     const RT invr = (RT)1 / (RT)twon1;
     const Consts<RT>& cc = [&]() -> const Consts<RT>& {
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
     }();
     RT lr, sr, g1r, g2r;
     if constexpr (FAM == FAM_FRANK) {
-      frank_rfull<RT>(cc, a, b, twon1, invr, lr, sr, g1r, g2r);
+      frank_rfull<RT, FORM>(cc, a, b, twon1, invr, lr, sr, g1r, g2r);
     } else if constexpr (FAM == FAM_GUMBEL) {
       RT lx, ly;
       gumbel_lxy<RT>(a, b, twon1, invr, lx, ly);
@@ -114,15 +115,16 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
     l = (CT)lr; s = (CT)sr; g1 = (CT)g1r; g2 = (CT)g2r;
   };
 
-  KSum<CT> kl, ksc, ks2;
+  RowSum<CT> kl, ksc, ks2;
   double psum = 0.0, psq = 0.0;
   CT* S = (CT*)P.rows.S + o;  // per-row score (workspace), then s + W1 (one-array variant)
-  auto rows = [&](auto rt_tag) {
+  auto rows = [&](auto rt_tag, auto form_tag) {
     using RT = decltype(rt_tag);
+    using FT = decltype(form_tag);
     if constexpr (TWO) {
       for (int i = tid; i < n; i += T) {
         CT l, s, g1, g2;
-        row_eval_t(RT{}, i, l, s, g1, g2);
+        row_eval_t(RT{}, FT{}, i, l, s, g1, g2);
         kl.add(l); ksc.add(s); ks2.add(s * s);
         A1[pidx(E1[i])] = g1;
         A2[pidx(E2[i])] = g2;
@@ -139,7 +141,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
     } else {
       for (int i = tid; i < n; i += T) {
         CT l, s, g1, g2;
-        row_eval_t(RT{}, i, l, s, g1, g2);
+        row_eval_t(RT{}, FT{}, i, l, s, g1, g2);
         kl.add(l); ksc.add(s); ks2.add(s * s);
         A1[pidx(E1[i])] = g1;
         S[i] = s;
@@ -150,7 +152,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
       __syncthreads();
       for (int i = tid; i < n; i += T) {
         CT l, s, g1, g2;
-        row_eval_t(RT{}, i, l, s, g1, g2);
+        row_eval_t(RT{}, FT{}, i, l, s, g1, g2);
         A1[pidx(E2[i])] = g2;
       }
       __syncthreads();
@@ -162,10 +164,15 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
       }
     }
   };
-  if (rd)
-    rows(double{});
+  // the Frank form (FP32: scaled below FRANK_SCALED_BELOW, else direct) is
+  // fixed per subset, outside the row loops
+  using Auto = std::integral_constant<int, -1>;
+  if (rd || sizeof(CT) == 8 || FAM != FAM_FRANK)
+    rd ? rows(double{}, Auto{}) : rows(CT{}, Auto{});
+  else if (c.fk.th < (CT)FRANK_SCALED_BELOW)
+    rows(CT{}, std::integral_constant<int, 1>{});
   else
-    rows(CT{});
+    rows(CT{}, std::integral_constant<int, 0>{});
   double v[5] = {kl.value(), ksc.value(), ks2.value(), psum, psq};
   block_sum<W, 5>(v, red);
   if (tid == 0) {

@@ -23,28 +23,37 @@
 
 namespace cpc {
 
-// LDS of the rank kernel. ALIAS: the digit counters share memory with the
-// exchange buffer (less LDS, two more barriers per pass). PK (32-bit keys
-// only): key and payload move together as one 64-bit word per element
-// (one scatter per element and pass instead of two).
-template <int T, int E, int B, int KW, bool ALIAS, bool PK>
+// LDS of the rank kernel: digit counters (CNT words), the exchange buffer
+// (CAP u32 keys, then CAP payloads of 16 or 32 bits) and a few small arrays.
+// ALIAS: counters share memory with the exchange buffer (less LDS, two more
+// barriers per pass). P32: 32-bit payloads (a scatter lane writes a whole
+// word instead of half of one). Without ALIAS the small arrays live in memory
+// that is idle while they are in use: the counter-scan scratch `red` in the
+// exchange keys (between a pass's gather and its next scatter), the AND / OR
+// of the keys in the payload area (load phase), the tie-phase arrays in the
+// counters (after the last pass).
+template <int T, int E, int B, int KW, bool ALIAS, bool P32>
 struct RankLds {
-  static_assert(!PK || KW == 1, "packed exchange holds 32-bit keys");
   static constexpr int W = T / WAVE;
   static constexpr int CAP = T * E;
   static constexpr int CNT = BlockDigitRank<T, E, B>::kCounterWords;
-  static constexpr int XW = PK ? 2 * CAP : CAP + CAP / 2;  // (u32 key, u32 payload) or u32 keys + u16 payloads
-  static constexpr int MAIN = ALIAS ? (CNT > XW ? CNT : XW) : CNT + XW;
+  static constexpr int XW = CAP + (P32 ? CAP : CAP / 2);
+  static constexpr int SMALL = 3 * W + W * KW + 8;  // red, wmax, wmin, wl, andor (+ non-finite flag)
+  static constexpr int MAIN = ALIAS ? (CNT > XW ? CNT : XW) + SMALL : CNT + XW;
+  static_assert(ALIAS || CNT >= 2 * W + W * KW, "tie-phase arrays fit in the counters");
   alignas(16) uint32_t main[MAIN];  // 16-byte vector reads of keys, payloads, counters
-  uint32_t red[W];
-  uint32_t wl[W * KW];  // last key of each wave
-  int32_t wmax[W], wmin[W];
-  uint32_t andor[4];
   __device__ __forceinline__ uint32_t* cnt() { return main; }
   __device__ __forceinline__ uint32_t* xk() { return ALIAS ? main : main + CNT; }
-  __device__ __forceinline__ uint16_t* xv() { return reinterpret_cast<uint16_t*>(xk() + CAP); }
-  __device__ __forceinline__ uint64_t* x64() { return reinterpret_cast<uint64_t*>(xk()); }
+  __device__ __forceinline__ uint32_t* xv32() { return xk() + CAP; }
+  __device__ __forceinline__ uint16_t* xv16() { return reinterpret_cast<uint16_t*>(xk() + CAP); }
+  __device__ __forceinline__ uint32_t* small() { return main + (MAIN - SMALL); }
+  __device__ __forceinline__ uint32_t* red() { return ALIAS ? small() : xk(); }
+  __device__ __forceinline__ int32_t* wmax() { return (int32_t*)(ALIAS ? small() + W : cnt()); }
+  __device__ __forceinline__ int32_t* wmin() { return wmax() + W; }
+  __device__ __forceinline__ uint32_t* wl() { return (uint32_t*)(wmax() + 2 * W); }
+  __device__ __forceinline__ uint32_t* andor() { return ALIAS ? small() + 3 * W + W * KW : xv32(); }
 };
+static_assert(sizeof(RankLds<1024, 16, 4, 1, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
 
 template <typename U>
 __device__ __forceinline__ U wave_and(U v) {
@@ -60,11 +69,12 @@ __device__ __forceinline__ U wave_or(U v) {
 }
 
 // Ranks one margin and writes, per row of the subset, R (and the sorted
-// position e and tie-group start lb). Returns true if the margin holds a
-// non-finite value; sets all_tied if every value is equal.
-template <int T, int E, int B, int KW, bool ALIAS, bool PK, typename DT>
+// position e and tie-group start lb). Returns true (in every thread) if the
+// margin holds a non-finite value; sets all_tied (in thread 0) if every value
+// is equal.
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
-                                                RankLds<T, E, B, KW, ALIAS, PK>& sm, uint16_t* Rg, uint16_t* Eg,
+                                                RankLds<T, E, B, KW, ALIAS, P32>& sm, uint16_t* Rg, uint16_t* Eg,
                                                 uint16_t* Lg, uint32_t* R32, bool& all_tied) {
   using Rank = BlockDigitRank<T, E, B>;
   constexpr int W = T / WAVE;
@@ -74,7 +84,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   const int nv = min(max(n - p0, 0), E);
   uint32_t* cnt = sm.cnt();
   uint32_t* xk = sm.xk();
-  uint16_t* xv = sm.xv();
+  uint32_t* andor = sm.andor();
   all_tied = false;
   if (n <= 0) return false;
 
@@ -86,8 +96,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   uint64_t kand = ~0ull, kor = 0ull;
   bool bad = false;
   if (t == 0) {
-    sm.andor[0] = sm.andor[1] = ~0u;
-    sm.andor[2] = sm.andor[3] = 0u;
+    andor[0] = andor[1] = ~0u;
+    andor[2] = andor[3] = andor[4] = 0u;
   }
 #pragma unroll
   for (int j = 0; j < E; ++j) pay[j] = (uint32_t)(p0 + j);
@@ -133,11 +143,13 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   kor = wave_or(kor);
   __syncthreads();  // andor initialised; previous margin's LDS use finished
   if (lane == 0) {
-    atomicAnd(&sm.andor[0], (uint32_t)kand);
-    atomicAnd(&sm.andor[1], (uint32_t)(kand >> 32));
-    atomicOr(&sm.andor[2], (uint32_t)kor);
-    atomicOr(&sm.andor[3], (uint32_t)(kor >> 32));
+    atomicAnd(&andor[0], (uint32_t)kand);
+    atomicAnd(&andor[1], (uint32_t)(kand >> 32));
+    atomicOr(&andor[2], (uint32_t)kor);
+    atomicOr(&andor[3], (uint32_t)(kor >> 32));
   }
+  const uint64_t badw = __ballot(bad);
+  if (lane == 0 && badw != 0ull) atomicOr(&andor[4], 1u);
   __syncthreads();
   if constexpr (KW == 1) {
     const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
@@ -149,7 +161,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     }
     if (ALIAS) __syncthreads();  // the first pass clears counters over these keys
   }
-  const uint64_t var = ((((uint64_t)sm.andor[1]) << 32) | sm.andor[0]) ^ ((((uint64_t)sm.andor[3]) << 32) | sm.andor[2]);
+  const uint64_t var = ((((uint64_t)andor[1]) << 32) | andor[0]) ^ ((((uint64_t)andor[3]) << 32) | andor[2]);
+  bad = andor[4] != 0u;  // workgroup-uniform from here on
 
   // radix passes over the varying bits; waves wholly past the end sit out
   // (their items keep their own positions >= n and their payloads)
@@ -163,38 +176,35 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
       const int off = lo + ps * B;
       if (((var >> off) & MASK) == 0ull) continue;  // constant digit: identity pass
       uint32_t pos[E];
-      Rank::template rank<KW>(klo, khi, off, active, cnt, sm.red, pos);
+      Rank::template rank<KW>(klo, khi, off, active, cnt, sm.red(), pos);
       if (ALIAS) __syncthreads();  // counters are read until here
       if (active) {
-        if constexpr (PK) {
-          uint64_t* x64 = sm.x64();
 #pragma unroll
-          for (int j = 0; j < E; ++j) x64[pos[j]] = ((uint64_t)pay[j] << 32) | klo[j];
-        } else {
-#pragma unroll
-          for (int j = 0; j < E; ++j) {
-            xk[pos[j]] = klo[j];
-            xv[pos[j]] = (uint16_t)pay[j];
-          }
+        for (int j = 0; j < E; ++j) {
+          xk[pos[j]] = klo[j];
+          if constexpr (P32)
+            sm.xv32()[pos[j]] = pay[j];
+          else
+            sm.xv16()[pos[j]] = (uint16_t)pay[j];
         }
       }
       __syncthreads();
       if (active) {
-        if constexpr (PK) {
-          const uint4* sk = reinterpret_cast<const uint4*>(sm.x64() + p0);
+        const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
 #pragma unroll
-          for (int q = 0; q < E / 2; ++q) {
-            const uint4 a = sk[q];
-            klo[2 * q] = a.x; pay[2 * q] = a.y; klo[2 * q + 1] = a.z; pay[2 * q + 1] = a.w;
-          }
-        } else {
-          const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
-          const uint4* sv = reinterpret_cast<const uint4*>(xv + p0);
+        for (int q = 0; q < E / 4; ++q) {
+          const uint4 a = sk[q];
+          klo[4 * q] = a.x; klo[4 * q + 1] = a.y; klo[4 * q + 2] = a.z; klo[4 * q + 3] = a.w;
+        }
+        if constexpr (P32) {
+          const uint4* sv = reinterpret_cast<const uint4*>(sm.xv32() + p0);
 #pragma unroll
           for (int q = 0; q < E / 4; ++q) {
-            const uint4 a = sk[q];
-            klo[4 * q] = a.x; klo[4 * q + 1] = a.y; klo[4 * q + 2] = a.z; klo[4 * q + 3] = a.w;
+            const uint4 a = sv[q];
+            pay[4 * q] = a.x; pay[4 * q + 1] = a.y; pay[4 * q + 2] = a.z; pay[4 * q + 3] = a.w;
           }
+        } else {
+          const uint4* sv = reinterpret_cast<const uint4*>(sm.xv16() + p0);
 #pragma unroll
           for (int q = 0; q < E / 8; ++q) {
             const uint4 a = sv[q];
@@ -228,15 +238,15 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   // tie groups: a sorted position starts a group unless its key equals its
   // predecessor's
   if (lane == WAVE - 1) {
-    sm.wl[w * KW] = klo[E - 1];
-    if (KW == 2) sm.wl[w * KW + KW - 1] = khi[E - 1];
+    sm.wl()[w * KW] = klo[E - 1];
+    if (KW == 2) sm.wl()[w * KW + KW - 1] = khi[E - 1];
   }
   uint32_t plo = __shfl_up(klo[E - 1], 1, WAVE);
   uint32_t phi = (KW == 2) ? __shfl_up(khi[E - 1], 1, WAVE) : 0u;
   __syncthreads();
   if (lane == 0 && w > 0) {
-    plo = sm.wl[(w - 1) * KW];
-    if (KW == 2) phi = sm.wl[(w - 1) * KW + KW - 1];
+    plo = sm.wl()[(w - 1) * KW];
+    if (KW == 2) phi = sm.wl()[(w - 1) * KW + KW - 1];
   }
   uint32_t headm = 0u;  // bit j: item j starts a group
   int hmax = -1, hmin = INT_MAX;
@@ -258,15 +268,15 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     if (lane >= off) imax = max(imax, a);
     if (lane + off < WAVE) imin = min(imin, b);
   }
-  if (lane == WAVE - 1) sm.wmax[w] = imax;
-  if (lane == 0) sm.wmin[w] = imin;
+  if (lane == WAVE - 1) sm.wmax()[w] = imax;
+  if (lane == 0) sm.wmin()[w] = imin;
   int cl = __shfl_up(imax, 1, WAVE);
   int cr = __shfl_down(imin, 1, WAVE);
   if (lane == 0) cl = -1;
   if (lane == WAVE - 1) cr = INT_MAX;
   __syncthreads();
-  for (int k = 0; k < w; ++k) cl = max(cl, sm.wmax[k]);
-  for (int k = w + 1; k < W; ++k) cr = min(cr, sm.wmin[k]);
+  for (int k = 0; k < w; ++k) cl = max(cl, sm.wmax()[k]);
+  for (int k = w + 1; k < W; ++k) cr = min(cr, sm.wmin()[k]);
   cr = min(cr, n);
   uint32_t lb[E], ub[E];
   {
@@ -285,7 +295,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   }
   all_tied = (n >= 1) && (t == 0) && (ub[0] >= (uint32_t)n);
   // R, sorted position and group start, scattered to row order in LDS
-  uint16_t* xl = xv;
+  uint16_t* xl = sm.xv16();
   // (an item past the end carries a payload >= n)
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -310,9 +320,9 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   return bad;
 }
 
-template <int T, int E, int B, int KW, bool ALIAS, bool PK>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32>
 __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
-  __shared__ RankLds<T, E, B, KW, ALIAS, PK> sm;
+  __shared__ RankLds<T, E, B, KW, ALIAS, P32> sm;
   const int sid = P.order[blockIdx.x];
   const SubDesc sd = P.subs[sid];
   const int n = sd.n;
@@ -328,21 +338,21 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   bool t1, t2, b1, b2;
   const int64_t o = sd.begin;
   if constexpr (KW == 2) {
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, PK, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
                                                      P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, PK, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
                                                      P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
   } else {
     const bool ik = P.int_keys != 0;
     const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
     const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, PK, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
                                                     P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, PK, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
                                                     P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
   }
   if (rk) return;
-  const bool bad = __syncthreads_or((int)(b1 || b2)) != 0;
+  const bool bad = b1 || b2;
   // all_tied is known to thread 0 only
   if (threadIdx.x == 0) {
     P.state[sid].status = bad ? ST_NONFINITE : ((t1 || t2) ? ST_DEGENERATE : ST_OK);

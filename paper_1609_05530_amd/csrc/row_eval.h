@@ -61,7 +61,9 @@ CPC_HD Consts<CT> make_consts(int fam, double theta) {
 // ---------------------------------------------------------------------------
 // Frank rows. In double: reflection and series inside frank_row_d. In float:
 // the FP32 forms of family_math.h (|theta| within [0.05, 50]).
-template <typename CT>
+// FORM (FP32 only): 1 scaled form, 0 direct form, -1 chosen per call (the
+// kernels choose once per subset and pass it down).
+template <typename CT, int FORM = -1>
 CPC_HD void frank_rsh(const Consts<CT>& c, uint32_t R1, uint32_t R2, uint32_t twon1, CT inv, CT& s,
                       CT& h) {
   const PObs<CT> p = pobs<CT>(R1, twon1, inv), q = pobs<CT>(R2, twon1, inv);
@@ -71,11 +73,11 @@ CPC_HD void frank_rsh(const Consts<CT>& c, uint32_t R1, uint32_t R2, uint32_t tw
   } else {
     const CT v = c.neg ? q.omu : q.u, omv = c.neg ? q.u : q.omu;
     CT ss;
-    frank_sh(c.fk, p.u, v, omv, ss, h);
+    frank_sh<CT, FORM>(c.fk, p.u, v, omv, ss, h);
     s = c.neg ? -ss : ss;
   }
 }
-template <typename CT>
+template <typename CT, int FORM = -1>
 CPC_HD void frank_rfull(const Consts<CT>& c, uint32_t R1, uint32_t R2, uint32_t twon1, CT inv, CT& l,
                         CT& s, CT& g1, CT& g2) {
   const PObs<CT> p = pobs<CT>(R1, twon1, inv), q = pobs<CT>(R2, twon1, inv);
@@ -85,7 +87,7 @@ CPC_HD void frank_rfull(const Consts<CT>& c, uint32_t R1, uint32_t R2, uint32_t 
   } else {
     const CT v = c.neg ? q.omu : q.u, omv = c.neg ? q.u : q.omu;
     CT ll, ss, gg1, gg2;
-    frank_full(c.fk, p.u, v, omv, ll, ss, gg1, gg2);
+    frank_full<CT, FORM>(c.fk, p.u, v, omv, ll, ss, gg1, gg2);
     l = ll + (CT)c.fk.logthE;
     s = c.neg ? -ss : ss;
     g1 = c.neg ? -gg1 : gg1;

@@ -374,3 +374,76 @@ def test_config2_full_size(fam):
             rt = np.abs(res["theta"][pick] - sub["theta"]) / np.abs(sub["theta"])
             rv = np.abs(res["var"][pick] / sub["var"] - 1.0)
             assert rt.max() <= 1e-6 and rv.max() <= 1e-6, (fam, rt, rv)
+
+
+# ---------------------------------------------------------------------------
+# Graph mode: the launch sequence captured once and replayed
+
+
+def _graph_case():
+    rng = np.random.default_rng(71)
+    sizes = [1200, 3000, 9000, 16000, 20000, 500, 7000, 17000]
+    n = int(sum(sizes))
+    xs, ys = [], []
+    fams = ["frank", "gumbel"]
+    for g, (fam, th) in enumerate([("frank", 5.0), ("gumbel", 2.0)]):
+        m = sum(sizes[g * 4:(g + 1) * 4])
+        x, y = synth.copula_pairs(fam, th, m, seed=300 + g, dtype=np.float32)
+        xs.append(x)
+        ys.append(y)
+    x = np.concatenate(xs)
+    y = np.concatenate(ys)
+    off = synth.offsets_from_sizes(np.array(sizes))
+    gofs = np.array([0, 4, 8], dtype=np.int64)
+    assert off[-1] == n
+    return x, y, off, gofs, fams
+
+
+@pytest.mark.parametrize("prec", ["fp32c", "fp64"])
+def test_graph_replays_match_eager(prec):
+    m = cpc()
+    x, y, off, gofs, fams = _graph_case()
+    dx, dy = dev(x, torch.float32), dev(y, torch.float32)
+    eager = to_np(m.fit_batched(dx, dy, off, gofs, fams, prec=prec))
+    K, G = len(off) - 1, len(gofs) - 1
+    ws = torch.empty(m.workspace_bytes(len(x), K, G, dtype=torch.float32, prec=prec), dtype=torch.uint8,
+                     device="cuda")
+    out = m.FitResult(torch.empty((K, 6), dtype=torch.float64, device="cuda"),
+                      torch.empty((G, 5), dtype=torch.float64, device="cuda"))
+    for r in range(4):
+        out.raw.fill_(float("nan"))
+        out.raw_comb.fill_(float("nan"))
+        m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec=prec)
+        torch.cuda.synchronize()
+        got = to_np(out)
+        for k in eager:
+            assert np.array_equal(got[k], eager[k], equal_nan=True), (r, k)
+        # eager work of the program between replays, including another fit
+        z = torch.randn(4096, device="cuda")
+        assert torch.isfinite(z.sum()).item()
+        again = to_np(m.fit_batched(dx, dy, off, gofs, fams, prec=prec))
+        for k in eager:
+            assert np.array_equal(again[k], eager[k], equal_nan=True), (r, k)
+
+
+def test_graph_replay_reads_current_data():
+    m = cpc()
+    x, y, off, gofs, fams = _graph_case()
+    dx, dy = dev(x, torch.float32), dev(y, torch.float32)
+    K, G = len(off) - 1, len(gofs) - 1
+    ws = torch.empty(m.workspace_bytes(len(x), K, G, dtype=torch.float32, prec="fp32c"), dtype=torch.uint8,
+                     device="cuda")
+    out = m.FitResult(torch.empty((K, 6), dtype=torch.float64, device="cuda"),
+                      torch.empty((G, 5), dtype=torch.float64, device="cuda"))
+    m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec="fp32c")
+    torch.cuda.synchronize()
+    # new contents in the same buffers: the replay must see them
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(len(x))
+    dy.copy_(dev(y[perm], torch.float32))
+    m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec="fp32c")
+    torch.cuda.synchronize()
+    got = to_np(out)
+    ref = to_np(m.fit_batched(dx, dy, off, gofs, fams, prec="fp32c"))
+    for k in ref:
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
