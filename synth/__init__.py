@@ -17,8 +17,10 @@ splits with integer sizes by largest remainder.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 from typing import List, Sequence
 
 import numpy as np
@@ -219,17 +221,22 @@ def config2(family: str, K: int, n: int = 1_000_000) -> Workload:
 
 def config3(replicates: int = 1000, n: int = 100_000, K: int = 50, seed0: int = 3000) -> Workload:
     """Replicates of n pairs, family = r mod 3, Kendall tau ~ U[0.1, 0.8],
-    K Dirichlet(1) subsets per replicate; FP32 storage."""
+    K Dirichlet(1) subsets per replicate; FP32 storage. Replicates are drawn
+    on a thread pool; each has its own seeds, so the result does not depend on
+    the number of workers."""
     fams = ["gaussian", "frank", "gumbel"]
-    parts = []
-    for r in range(replicates):
+
+    def one(r):
         rng = np.random.default_rng(seed0 + r)
         fam = fams[r % 3]
         tau = rng.uniform(0.1, 0.8)
         th = theta_from_tau(fam, tau)
-        x, y = copula_pairs(fam, th, n, seed0 + 100_000 + r)
+        x, y = copula_pairs(fam, th, n, seed0 + 100_000 + r, dtype=np.float32)
         off = dirichlet_offsets(n, K, rng)
-        parts.append((x, y, off, fam, th, seed0 + r))
+        return (x, y, off, fam, th, seed0 + r)
+
+    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        parts = list(ex.map(one, range(replicates)))
     return _concat(f"{replicates} replicates x n={n}, K={K} Dirichlet(1) fp32", parts, np.float32)
 
 
@@ -260,13 +267,28 @@ def config5(settings: Sequence = CONFIG5, n: int = 10_000_000, K: int = 1000, lo
     return _concat(f"{len(settings)} settings x n={n}, K={K} U[{lo:g},{hi:g}] fp32", parts, np.float32)
 
 
-def _chunked_pairs(family: str, theta: float, n: int, seed: int, dtype, chunk: int = 1 << 22):
-    """Draw n pairs in chunks (bounded float64 temporaries), seeded per chunk."""
+def _chunked_pairs(family: str, theta: float, n: int, seed: int, dtype, chunk: int = 1 << 22,
+                   workers: int = 0):
+    """Draw n pairs in chunks (bounded float64 temporaries), seeded per chunk.
+    Chunks are drawn on a thread pool (numpy releases the GIL in its bulk
+    generators and ufuncs); every chunk has its own seed, so the result does
+    not depend on the number of workers."""
     x = np.empty(n, dtype=dtype)
     y = np.empty(n, dtype=dtype)
-    for c, start in enumerate(range(0, n, chunk)):
+    starts = list(range(0, n, chunk))
+
+    def one(c):
+        start = starts[c]
         m = min(chunk, n - start)
         xs, ys = copula_pairs(family, theta, m, seed * 1_000_003 + c)
         x[start:start + m] = xs
         y[start:start + m] = ys
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or len(starts) <= 1:
+        for c in range(len(starts)):
+            one(c)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(one, range(len(starts))))
     return x, y
