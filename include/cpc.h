@@ -99,7 +99,7 @@ typedef struct {
   int32_t max_iter;  /* Newton passes per subset, default 60 */
   double tol;        /* stop when |dtheta| <= tol (1 + |theta|); 0 = default (1e-12 FP64, 1e-9 FP32C) */
   int64_t n_min;     /* subsets with fewer rows are DEGENERATE; default (and minimum) 2 */
-  int32_t schedule;  /* -1 = autotuned; otherwise a fixed schedule id (see DESIGN) */
+  int32_t schedule;  /* -1 = rank-kernel launch shapes chosen by the autotuner (default); 0 = built-in shapes */
   int32_t flags;     /* bit 0: capture/replay the launch sequence as a hipGraph */
 } cpc_options_t;
 

@@ -11,7 +11,11 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "cpc.h"
@@ -28,6 +32,7 @@ struct cpc_context {
   int* pending_host;        // pinned: subsets of the streaming path still iterating
   hipStream_t cap_stream;   // the fit is captured here in graph mode (default priority)
   void* graph;              // GraphCache: the instantiated graph of the last graph-mode call
+  void* tuner;              // Tuner: rank-kernel launch shapes chosen per workload signature
 };
 
 static constexpr int kMagic = 0x43504331;
@@ -56,6 +61,7 @@ struct Options {
   int prec, ties, var, max_iter;
   double tol;
   int64_t n_min;
+  int schedule;
   int flags;
 };
 
@@ -69,12 +75,14 @@ int read_options(const cpc_options_t* o, Options& r) {
   if (o->max_iter < 1) return fail(CPC_E_OPTIONS, "max_iter must be >= 1 (got %d)", o->max_iter);
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(CPC_E_OPTIONS, "tol must be finite and >= 0");
   if (o->n_min < 0) return fail(CPC_E_OPTIONS, "n_min must be >= 0");
+  if (o->schedule != -1 && o->schedule != 0) return fail(CPC_E_OPTIONS, "schedule must be -1 or 0 (got %d)", o->schedule);
   r.prec = o->prec;
   r.ties = o->ties;
   r.var = o->var;
   r.max_iter = o->max_iter;
   r.tol = o->tol > 0.0 ? o->tol : (o->prec == CPC_PREC_FP64 ? 1e-12 : 1e-9);
   r.n_min = o->n_min < 2 ? 2 : o->n_min;
+  r.schedule = o->schedule;
   r.flags = o->flags;
   return CPC_SUCCESS;
 }
@@ -147,6 +155,7 @@ Layout layout(int64_t n, int64_t K, int64_t G) {
 struct Bucket {
   int cls, fam;
   int32_t first, count;  // range in the order array
+  int shape;             // rank buckets: launch shape (-1 = the class default)
 };
 
 struct Plan {
@@ -208,7 +217,7 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
   for (int64_t i = 0; i < KR;) {
     int64_t j = i;
     while (j < KR && cls[ids[j]] == cls[ids[i]]) ++j;
-    P.rank_buckets.push_back({cls[ids[i]], 0, (int32_t)i, (int32_t)(j - i)});
+    P.rank_buckets.push_back({cls[ids[i]], 0, (int32_t)i, (int32_t)(j - i), -1});
     i = j;
   }
   // fit / variance lists: by (class, family), largest first
@@ -222,7 +231,7 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
   for (int64_t i = 0; i < KR;) {
     int64_t j = i;
     while (j < KR && cls[ids[j]] == cls[ids[i]] && P.subs[ids[j]].family == P.subs[ids[i]].family) ++j;
-    P.fit_buckets.push_back({cls[ids[i]], P.subs[ids[i]].family, (int32_t)i, (int32_t)(j - i)});
+    P.fit_buckets.push_back({cls[ids[i]], P.subs[ids[i]].family, (int32_t)i, (int32_t)(j - i), -1});
     i = j;
   }
   return CPC_SUCCESS;
@@ -349,6 +358,103 @@ void touch_workspace(cpc_handle_t h, const void* ws) {
 int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
                 const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph, hipStream_t s);
 
+// Autotuner: the rank kernel's launch shape per size class, chosen by timing
+// each candidate shape on the call's own subsets (the rank kernel is exact
+// and idempotent, so trial launches leave nothing behind that the real run
+// does not rewrite). A decision is keyed by (class, key width, log2 of the
+// bucket's subset count, mean fill of the class capacity in eighths), kept
+// in the handle and, when CPC_AUTOTUNE_CACHE names a file, appended there and
+// read back by later handles. Tuning synchronises the stream once per new
+// key; it runs before any graph capture.
+struct Tuner {
+  std::map<std::tuple<int, int, int, int>, int> choice;
+  std::string path;
+  std::string arch;
+};
+Tuner& tuner_of(cpc_handle_t h) { return *(Tuner*)h->tuner; }
+
+void tuner_load(Tuner& t, int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) t.arch = prop.gcnArchName;
+  const size_t colon = t.arch.find(':');
+  if (colon != std::string::npos) t.arch.resize(colon);
+  const char* p = std::getenv("CPC_AUTOTUNE_CACHE");
+  if (!p || !*p) return;
+  t.path = p;
+  FILE* f = std::fopen(p, "r");
+  if (!f) return;
+  char arch[64];
+  int cls, kw, cb, fb, shape;
+  while (std::fscanf(f, "%63s %d %d %d %d %d", arch, &cls, &kw, &cb, &fb, &shape) == 6) {
+    if (t.arch == arch && cls >= 0 && cls < kNumClasses && shape >= 0 && shape < kNumRankShapes &&
+        kRankShapes[shape].cap >= (int)(kClassThreads[cls] * kClassItems[cls]))
+      t.choice[{cls, kw, cb, fb}] = shape;
+  }
+  std::fclose(f);
+}
+
+RankParams rank_params(const Carved& c, const void* x, const void* y, const Options& o) {
+  RankParams rp;
+  std::memset(&rp, 0, sizeof(rp));
+  rp.x = x;
+  rp.y = y;
+  rp.subs = c.subs;
+  rp.mode = MODE_FIT;
+  rp.ties = o.ties;
+  rp.int_keys = 0;
+  rp.n_min = o.n_min;
+  rp.rows = c.rows;
+  rp.state = c.state;
+  return rp;
+}
+
+int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, const void* y, int kw,
+                       const Options& o, hipStream_t s) {
+  Tuner& t = tuner_of(h);
+  for (Bucket& b : P.rank_buckets) {
+    b.shape = kRankDefaultShape[b.cls];
+    if (o.schedule == 0 || kw != 1 || b.count <= 0) continue;
+    double mean = 0.0;
+    for (int32_t i = 0; i < b.count; ++i) mean += P.subs[P.order_rank[b.first + i]].n;
+    mean /= b.count;
+    const int cap = kClassThreads[b.cls] * kClassItems[b.cls];
+    const int cb = (int)std::floor(std::log2((double)b.count));
+    const int fb = std::min(7, (int)(8.0 * mean / cap));
+    const auto key = std::make_tuple(b.cls, kw, cb, fb);
+    auto it = t.choice.find(key);
+    if (it != t.choice.end()) {
+      b.shape = it->second;
+      continue;
+    }
+    RankParams rp = rank_params(c, x, y, o);
+    rp.order = c.order_rank + b.first;
+    float best = 0.0f;
+    for (int k = 0; k < 3 && kRankCandidates[b.cls][k] >= 0; ++k) {
+      const int shape = kRankCandidates[b.cls][k];
+      HIP_OK(launch_rank_shape(shape, kw, rp, b.count, s));  // warm-up
+      HIP_OK(hipEventRecord(h->ev[0], s));
+      HIP_OK(launch_rank_shape(shape, kw, rp, b.count, s));
+      HIP_OK(launch_rank_shape(shape, kw, rp, b.count, s));
+      HIP_OK(hipEventRecord(h->ev[1], s));
+      HIP_OK(hipEventSynchronize(h->ev[1]));
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+      if (k == 0 || ms < best) {
+        best = ms;
+        b.shape = shape;
+      }
+    }
+    t.choice[key] = b.shape;
+    if (!t.path.empty()) {
+      if (FILE* f = std::fopen(t.path.c_str(), "a")) {
+        std::fprintf(f, "%s %d %d %d %d %d\n", t.arch.c_str(), b.cls, kw, cb, fb, b.shape);
+        std::fclose(f);
+      }
+    }
+  }
+  return CPC_SUCCESS;
+}
+
 // The full fit path for validated arguments.
 int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
             int64_t K, const int64_t* gofs, int64_t G, const std::vector<int32_t>& fam_of_subset,
@@ -378,6 +484,8 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   rc = upload_tables(h, P, c, P.gofs.data(), G, s);
   if (rc) return rc;
   set_big(c, P, o.n_min);
+  rc = choose_rank_shapes(h, P, c, x, y, dtype == CPC_F64 ? 2 : 1, o, s);
+  if (rc) return rc;
   if (!graph) return enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, false, s);
 
   // capture on the handle's stream once the uploads on `s` are done
@@ -417,21 +525,11 @@ int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const v
   const int kw = (dtype == CPC_F64) ? 2 : 1;
   const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
 
-  RankParams rp;
-  std::memset(&rp, 0, sizeof(rp));
-  rp.x = x;
-  rp.y = y;
-  rp.subs = c.subs;
-  rp.mode = MODE_FIT;
-  rp.ties = o.ties;
-  rp.int_keys = 0;
-  rp.n_min = o.n_min;
-  rp.rows = c.rows;
-  rp.state = c.state;
+  RankParams rp = rank_params(c, x, y, o);
   if (timed) HIP_OK(hipEventRecord(h->ev[0], s));
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
-    HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
+    HIP_OK(launch_rank_shape(b.shape >= 0 ? b.shape : kRankDefaultShape[b.cls], kw, rp, b.count, s));
   }
   HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, nullptr, nullptr, s));
   if (timed) HIP_OK(hipEventRecord(h->ev[1], s));
@@ -500,7 +598,10 @@ int cpc_create(int device, cpc_handle_t* out) {
   h->have_times = 0;
   h->pending_host = nullptr;
   h->graph = new GraphCache();
+  h->tuner = new Tuner();
+  tuner_load(tuner_of(h), device);
   if (hipHostMalloc((void**)&h->pending_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete (Tuner*)h->tuner;
     delete (GraphCache*)h->graph;
     delete (Plan*)h->plan;
     delete h;
@@ -508,6 +609,7 @@ int cpc_create(int device, cpc_handle_t* out) {
   }
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipHostFree(h->pending_host);
+    delete (Tuner*)h->tuner;
     delete (GraphCache*)h->graph;
     delete (Plan*)h->plan;
     delete h;
@@ -518,6 +620,7 @@ int cpc_create(int device, cpc_handle_t* out) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->ev[j]);
       (void)hipStreamDestroy(h->cap_stream);
       (void)hipHostFree(h->pending_host);
+      delete (Tuner*)h->tuner;
       delete (GraphCache*)h->graph;
       delete (Plan*)h->plan;
       delete h;
@@ -534,6 +637,7 @@ int cpc_destroy(cpc_handle_t h) {
   (void)hipSetDevice(h->device);
   graph_of(h).drop();
   delete (GraphCache*)h->graph;
+  delete (Tuner*)h->tuner;
   (void)hipStreamDestroy(h->cap_stream);
   for (int i = 0; i < 5; ++i) (void)hipEventDestroy(h->ev[i]);
   (void)hipHostFree(h->pending_host);

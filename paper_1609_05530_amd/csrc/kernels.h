@@ -69,6 +69,24 @@ struct VarParams {
 };
 
 hipError_t launch_rank_wg(int cls, int kw, const RankParams& p, int grid, hipStream_t s);
+
+// Launch shapes of the rank kernel (threads, items per thread): a subset of
+// up to threads * items rows fits a shape. Ranks are exact integers under
+// every shape, so the choice (made by the autotuner per size class) only
+// affects speed. 64-bit keys always use the class's default shape.
+struct RankShape {
+  int threads, items, cap;
+};
+constexpr int kNumRankShapes = 7;
+constexpr RankShape kRankShapes[kNumRankShapes] = {{64, 8, 512},    {256, 8, 2048},  {128, 16, 2048},
+                                                   {512, 16, 8192}, {256, 32, 8192}, {1024, 16, 16384},
+                                                   {512, 32, 16384}};
+constexpr int kRankDefaultShape[kNumClasses] = {0, 1, 3, 5};
+// Candidate shapes per size class (-1 terminated): one wave or one larger
+// workgroup per subset for the smallest class, two thread / item splits for
+// the others.
+constexpr int kRankCandidates[kNumClasses][3] = {{0, 1, -1}, {1, 2, -1}, {3, 4, -1}, {5, 6, -1}};
+hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, hipStream_t s);
 hipError_t launch_fit_wg(int cls, int fam, int fp64, const FitParams& p, int grid, hipStream_t s);
 hipError_t launch_var_wg(int cls, int fam, int fp64, const VarParams& p, int grid, hipStream_t s);
 

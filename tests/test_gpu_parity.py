@@ -447,3 +447,71 @@ def test_graph_replay_reads_current_data():
     ref = to_np(m.fit_batched(dx, dy, off, gofs, fams, prec="fp32c"))
     for k in ref:
         assert np.array_equal(got[k], ref[k], equal_nan=True), k
+
+
+# ---------------------------------------------------------------------------
+# Autotuner: rank-kernel launch shapes (speed only; results are identical)
+
+
+def _fit_with_handle(h, x, y, off, gofs, fams, schedule, prec="fp32c"):
+    import ctypes
+    from paper_1609_05530_amd import _lib
+    m = cpc()
+    K, G = len(off) - 1, len(gofs) - 1
+    o = m._options(prec=prec)
+    o.schedule = schedule
+    ws = torch.empty(m.workspace_bytes(len(x), K, G, dtype=torch.float32, prec=prec), dtype=torch.uint8,
+                     device="cuda")
+    out = m.FitResult(torch.empty((K, 6), dtype=torch.float64, device="cuda"),
+                      torch.empty((G, 5), dtype=torch.float64, device="cuda"))
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    gofs = np.ascontiguousarray(gofs, dtype=np.int64)
+    codes = np.ascontiguousarray([FAM_CODE[f] for f in fams], dtype=np.int32)
+    _lib.check(_lib.lib().cpc_fit_batched(
+        h, x.data_ptr(), y.data_ptr(), 1, len(x), off.ctypes.data, K, gofs.ctypes.data, G, codes.ctypes.data,
+        ctypes.byref(o), ws.data_ptr(), ws.numel(), out.raw.data_ptr(), out.raw_comb.data_ptr(),
+        torch.cuda.current_stream().cuda_stream))
+    return to_np(out)
+
+
+def test_autotuned_shapes_give_identical_results(tmp_path, monkeypatch):
+    import ctypes
+    from paper_1609_05530_amd import _lib
+    rng = np.random.default_rng(41)
+    # subsets in every size class, two groups
+    sizes = np.array([300, 480, 1500, 2000, 5000, 8000, 12000, 16000, 100, 700, 3000, 9000])
+    xs, ys = [], []
+    for g, (fam, th) in enumerate([("frank", 4.0), ("gaussian", 0.4)]):
+        x, y = synth.copula_pairs(fam, th, int(sizes[g * 6:(g + 1) * 6].sum()), seed=500 + g, dtype=np.float32)
+        xs.append(x); ys.append(y)
+    x = dev(np.concatenate(xs), torch.float32)
+    y = dev(np.concatenate(ys), torch.float32)
+    off = synth.offsets_from_sizes(sizes)
+    gofs = np.array([0, 6, 12], dtype=np.int64)
+    fams = ["frank", "gaussian"]
+    cache = tmp_path / "autotune.txt"
+    monkeypatch.setenv("CPC_AUTOTUNE_CACHE", str(cache))
+    h = ctypes.c_void_p()
+    _lib.check(_lib.lib().cpc_create(0, ctypes.byref(h)))
+    try:
+        tuned = _fit_with_handle(h, x, y, off, gofs, fams, -1)
+        fixed = _fit_with_handle(h, x, y, off, gofs, fams, 0)
+    finally:
+        _lib.check(_lib.lib().cpc_destroy(h))
+    for k in tuned:
+        assert np.array_equal(tuned[k], fixed[k], equal_nan=True), k
+    lines = cache.read_text().split("\n")
+    lines = [l for l in lines if l.strip()]
+    classes = sorted({int(l.split()[1]) for l in lines})
+    assert classes == [0, 1, 2, 3], lines
+    print("[autotune] decisions:", lines, flush=True)
+    # a fresh handle reads the decisions back and adds none
+    h2 = ctypes.c_void_p()
+    _lib.check(_lib.lib().cpc_create(0, ctypes.byref(h2)))
+    try:
+        again = _fit_with_handle(h2, x, y, off, gofs, fams, -1)
+    finally:
+        _lib.check(_lib.lib().cpc_destroy(h2))
+    assert len([l for l in cache.read_text().split("\n") if l.strip()]) == len(lines)
+    for k in tuned:
+        assert np.array_equal(again[k], tuned[k], equal_nan=True), k
