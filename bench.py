@@ -86,8 +86,8 @@ def measured_rank_traffic():
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build targets a single MI355X "
-              "(subsets are independent; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only (subsets are independent: several GPUs would each take "
+              "whole subsets and all-reduce the per-group sums of eq. 15).", file=sys.stderr)
         sys.exit(2)
     import torch
 
