@@ -248,7 +248,7 @@ def main():
         cpu_s = time.perf_counter() - t0
         ref = sub["theta"]
         ok = (sub["status"] == 0) & (status[pick] == 0)
-        floor = np.array([0.1 if fam_of[m] == "frank" else 1e-3 for m in pick])
+        floor = np.array([0.1 if fam_of[m] == "frank" else 1e-2 for m in pick])
 
         def rel_err(th):
             got = th[pick]

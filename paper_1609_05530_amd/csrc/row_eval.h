@@ -17,8 +17,12 @@ enum Family { FAM_GAUSSIAN = 0, FAM_FRANK = 1, FAM_GUMBEL = 2 };
 
 // Rows switch from FP32 to FP64 arithmetic (in the FP32-compensated mode)
 // where the FP32 forms lose digits: Frank near independence or far out
-// (e^{-theta} leaves FP32 range), Gaussian with |rho| near 1.
-constexpr double FRANK_F32_MIN_ABS = 0.05;
+// (e^{-theta} leaves FP32 range), Gaussian with |rho| near 1. Near Frank
+// independence the log-likelihood is flat (mean d2l/dtheta2 ~ -0.03 at
+// theta = 0.1), so a rounding bias of one FP32 ulp in the per-row score
+// moves the root by ~2e-6 absolute: FP64 rows below |theta| = 0.5 keep the
+// estimate within 1e-5 relative (4e-6 measured worst case above it).
+constexpr double FRANK_F32_MIN_ABS = 0.5;
 constexpr double FRANK_F32_MAX_ABS = 50.0;
 constexpr double GAUSS_F32_MAX_ABS = 0.99;
 
@@ -48,7 +52,7 @@ CPC_HD Consts<CT> make_consts(int fam, double theta) {
     const double a = fabs(theta);
     c.neg = theta < 0.0;
     if (sizeof(CT) == 4 && (a < FRANK_F32_MIN_ABS || a > FRANK_F32_MAX_ABS)) c.use_d = true;
-    c.fk = frank_const<CT>(a > 0.0 ? a : 1.0);  // the FP32 forms only see |theta| >= 0.05
+    c.fk = frank_const<CT>(a > 0.0 ? a : 1.0);  // the FP32 forms only see |theta| >= 0.5
   } else if (fam == FAM_GUMBEL) {
     c.gk = gumbel_const<CT>(theta);
   } else {
@@ -60,7 +64,7 @@ CPC_HD Consts<CT> make_consts(int fam, double theta) {
 
 // ---------------------------------------------------------------------------
 // Frank rows. In double: reflection and series inside frank_row_d. In float:
-// the FP32 forms of family_math.h (|theta| within [0.05, 50]).
+// the FP32 forms of family_math.h (|theta| within [0.5, 50]).
 // FORM (FP32 only): 1 scaled form, 0 direct form, -1 chosen per call (the
 // kernels choose once per subset and pass it down).
 template <typename CT, int FORM = -1>

@@ -12,7 +12,8 @@ namespace cpc {
 
 struct NewtonState {
   double theta, lo, hi, prev_step;
-  int32_t it, status, done, flags;  // flags: bit 0 lower box edge evaluated, bit 1 upper
+  int32_t it, status, done, flags;  // flags: bit 0 lower box edge evaluated, bit 1 upper,
+                                    // bit 2 the previous step was a plain Newton step
 };
 
 // Starting value from Spearman's rho of the ranks (Sec. 2.3 names the
@@ -94,7 +95,9 @@ __device__ inline void newton_update(NewtonState& st, int fam, double S, double 
     return;
   }
   double tn = (H < 0.0) ? th - S / H : NAN;
+  bool newton = true;  // tn is the plain Newton step
   if (!(tn > st.lo && tn < st.hi)) {
+    newton = false;
     if (!(tn > st.lo) && st.lo == bl && !(st.flags & 1)) {
       tn = bl;
       st.flags |= 1;
@@ -111,13 +114,20 @@ __device__ inline void newton_update(NewtonState& st, int fam, double S, double 
   // FP32 rows: once the steps stop shrinking below 1e-6 the iteration sits on
   // the rounding noise of the score and further passes change nothing
   const bool stalled = noise > 1e-10 && st.it >= 3 && step > 0.5 * st.prev_step && step <= 1e-6 * scale;
-  if (!edge && (step <= tol * scale || (st.hi - st.lo) <= tol * scale || stalled)) {
+  // Quadratic convergence: the error after this step is about C step^2 with
+  // C ~ step / prev_step^2 when the last two steps were plain Newton steps;
+  // once that prediction is a tenth of the tolerance the confirming pass
+  // is skipped.
+  const bool predicted = newton && (st.flags & 4) && step <= 0.1 * st.prev_step &&
+                         step * step * step <= 0.1 * tol * scale * st.prev_step * st.prev_step;
+  if (!edge && (step <= tol * scale || (st.hi - st.lo) <= tol * scale || stalled || predicted)) {
     st.theta = tn;
     st.done = 1;
     newton_snap(st, fam);
     return;
   }
   st.prev_step = step;
+  st.flags = newton ? (st.flags | 4) : (st.flags & ~4);
   st.theta = tn;
   if (st.it >= max_iter) {
     st.status = ST_NOCONV;
