@@ -123,7 +123,7 @@ struct BlockDigitRank {
     //    counting phase's digits and addresses are recomputed, not kept live
     //    across the scan)
     const uint32_t lowtot = grand & 0xFFFFu;
-    int tl = t, offl = off;
+    int tl = t, offl = __builtin_amdgcn_readfirstlane(off);
     asm volatile("" : "+v"(tl));
     asm volatile("" : "+s"(offl));
     if (active) {

@@ -429,7 +429,7 @@ int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, 
     RankParams rp = rank_params(c, x, y, o);
     rp.order = c.order_rank + b.first;
     float best = 0.0f;
-    for (int k = 0; k < 3 && kRankCandidates[b.cls][k] >= 0; ++k) {
+    for (int k = 0; k < 5 && kRankCandidates[b.cls][k] >= 0; ++k) {
       const int shape = kRankCandidates[b.cls][k];
       HIP_OK(launch_rank_shape(shape, kw, rp, b.count, s));  // warm-up
       HIP_OK(hipEventRecord(h->ev[0], s));

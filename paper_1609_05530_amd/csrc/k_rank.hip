@@ -24,28 +24,35 @@ static_assert(kClassThreads[1] * kClassItems[1] == 256 * 8, "class 1 capacity");
 static_assert(kClassThreads[2] * kClassItems[2] == 512 * 16, "class 2 capacity");
 static_assert(kClassThreads[3] * kClassItems[3] == 1024 * 16, "class 3 capacity");
 
-template <int T, int E>
+template <int T, int E, bool PACK>
 static hipError_t launch_shape1(const RankParams& p, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rank_wg<T, E, 4, 1, false, false>), dim3(grid), dim3(T), 0, s, p);
+  hipLaunchKernelGGL((k_rank_wg<T, E, 4, 1, false, false, PACK>), dim3(grid), dim3(T), 0, s, p);
   return hipGetLastError();
 }
 
 hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, hipStream_t s) {
   if (shape < 0 || shape >= kNumRankShapes) return hipErrorInvalidValue;
-  if (kw == 2) {  // 64-bit keys: the default shape of the class the shape serves
+  if (kw == 2) {  // 64-bit keys: the unpacked default of the class the shape serves
     for (int c = 0; c < kNumClasses; ++c)
-      if (kRankShapes[shape].cap == kRankShapes[kRankDefaultShape[c]].cap) return launch_rank_wg(c, kw, p, grid, s);
+      if (kRankShapes[shape].cap == kClassThreads[c] * kClassItems[c]) return launch_rank_wg(c, kw, p, grid, s);
     return hipErrorInvalidValue;
   }
   switch (shape) {
-    case 0: return launch_shape1<64, 8>(p, grid, s);
-    case 1: return launch_shape1<256, 8>(p, grid, s);
-    case 2: return launch_shape1<128, 16>(p, grid, s);
-    case 3: return launch_shape1<512, 16>(p, grid, s);
-    case 4: return launch_shape1<256, 32>(p, grid, s);
-    case 5: return launch_shape1<1024, 16>(p, grid, s);
-    case 6: return launch_shape1<512, 32>(p, grid, s);
+    case 0: return launch_shape1<64, 8, false>(p, grid, s);
+    case 1: return launch_shape1<256, 8, false>(p, grid, s);
+    case 2: return launch_shape1<128, 16, false>(p, grid, s);
+    case 3: return launch_shape1<512, 16, false>(p, grid, s);
+    case 4: return launch_shape1<256, 32, false>(p, grid, s);
+    case 5: return launch_shape1<1024, 16, false>(p, grid, s);
+    case 6: return launch_shape1<512, 32, false>(p, grid, s);
+    case 7: return launch_shape1<64, 8, true>(p, grid, s);
+    case 8: return launch_shape1<256, 8, true>(p, grid, s);
+    case 9: return launch_shape1<128, 16, true>(p, grid, s);
+    case 10: return launch_shape1<512, 16, true>(p, grid, s);
+    case 11: return launch_shape1<256, 32, true>(p, grid, s);
+    case 12: return launch_shape1<1024, 16, true>(p, grid, s);
+    case 13: return launch_shape1<512, 32, true>(p, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -92,10 +92,9 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
   // Row arithmetic in RT (CT, or double near the family boundaries), results
   // in CT. The choice is uniform over the workgroup and made once, outside
   // the row loops.
-  auto row_eval_t = [&](auto rt_tag, auto form_tag, int i, CT& l, CT& s, CT& g1, CT& g2) {
+  auto row_eval_ab = [&](auto rt_tag, auto form_tag, uint32_t a, uint32_t b, CT& l, CT& s, CT& g1, CT& g2) {
     using RT = decltype(rt_tag);
     constexpr int FORM = decltype(form_tag)::value;
-    const uint32_t a = R1[i], b = R2[i];
     const RT invr = (RT)1 / (RT)twon1;
     const Consts<RT>& cc = [&]() -> const Consts<RT>& {
       if constexpr (std::is_same<RT, double>::value) return cd; else return c;
@@ -114,6 +113,9 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
     }
     l = (CT)lr; s = (CT)sr; g1 = (CT)g1r; g2 = (CT)g2r;
   };
+  auto row_eval_t = [&](auto rt_tag, auto form_tag, int i, CT& l, CT& s, CT& g1, CT& g2) {
+    row_eval_ab(rt_tag, form_tag, R1[i], R2[i], l, s, g1, g2);
+  };
 
   RowSum<CT> kl, ksc, ks2;
   double psum = 0.0, psq = 0.0;
@@ -122,21 +124,47 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
     using RT = decltype(rt_tag);
     using FT = decltype(form_tag);
     if constexpr (TWO) {
-      for (int i = tid; i < n; i += T) {
-        CT l, s, g1, g2;
-        row_eval_t(RT{}, FT{}, i, l, s, g1, g2);
-        kl.add(l); ksc.add(s); ks2.add(s * s);
-        A1[pidx(E1[i])] = g1;
-        A2[pidx(E2[i])] = g2;
-        S[i] = s;
+      // Rows i = tid, tid + T, ...; the loads of the next two rows are in
+      // flight while a row is evaluated (their latency dominates otherwise).
+      {
+        const int last = n - 1;
+        int i1 = min(tid + T, last), i2 = min(tid + 2 * T, last);
+        const int i0 = min(tid, last);
+        uint32_t r0 = (uint32_t)R1[i0] | ((uint32_t)R2[i0] << 16), q0 = (uint32_t)E1[i0] | ((uint32_t)E2[i0] << 16);
+        uint32_t r1 = (uint32_t)R1[i1] | ((uint32_t)R2[i1] << 16), q1 = (uint32_t)E1[i1] | ((uint32_t)E2[i1] << 16);
+#pragma unroll 1
+        for (int i = tid; i < n; i += T) {
+          i2 = min(i + 2 * T, last);
+          const uint32_t r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16);
+          const uint32_t q2 = (uint32_t)E1[i2] | ((uint32_t)E2[i2] << 16);
+          CT l, s, g1, g2;
+          row_eval_ab(RT{}, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
+          kl.add(l); ksc.add(s); ks2.add(s * s);
+          A1[pidx((int)(q0 & 0xFFFFu))] = g1;
+          A2[pidx((int)(q0 >> 16))] = g2;
+          S[i] = s;
+          r0 = r1; q0 = q1; r1 = r2; q1 = q2;
+        }
       }
       __syncthreads();
       lds_suffix_sum<T, E, CT>(A1, n, red);
       lds_suffix_sum<T, E, CT>(A2, n, red);
-      for (int i = tid; i < n; i += T) {
-        const double psi = (double)S[i] + ((double)A1[pidx(L1[i])] + (double)A2[pidx(L2[i])]) / dn;
-        psum += psi;
-        psq += psi * psi;
+      {
+        const int last = n - 1;
+        const int i0 = min(tid, last), i1 = min(tid + T, last);
+        CT s0 = S[i0], s1 = S[i1];
+        uint32_t l0 = (uint32_t)L1[i0] | ((uint32_t)L2[i0] << 16), l1 = (uint32_t)L1[i1] | ((uint32_t)L2[i1] << 16);
+#pragma unroll 1
+        for (int i = tid; i < n; i += T) {
+          const int i2 = min(i + 2 * T, last);
+          const CT s2 = S[i2];
+          const uint32_t l2 = (uint32_t)L1[i2] | ((uint32_t)L2[i2] << 16);
+          const double psi =
+              (double)s0 + ((double)A1[pidx((int)(l0 & 0xFFFFu))] + (double)A2[pidx((int)(l0 >> 16))]) / dn;
+          psum += psi;
+          psq += psi * psi;
+          s0 = s1; l0 = l1; s1 = s2; l1 = l2;
+        }
       }
     } else {
       for (int i = tid; i < n; i += T) {

@@ -72,7 +72,7 @@ __device__ __forceinline__ U wave_or(U v) {
 // position e and tie-group start lb). Returns true (in every thread) if the
 // margin holds a non-finite value; sets all_tied (in thread 0) if every value
 // is equal.
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, typename DT>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
                                                 RankLds<T, E, B, KW, ALIAS, P32>& sm, uint16_t* Rg, uint16_t* Eg,
                                                 uint16_t* Lg, uint32_t* R32, bool& all_tied) {
@@ -161,31 +161,60 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     }
     if (ALIAS) __syncthreads();  // the first pass clears counters over these keys
   }
-  const uint64_t var = ((((uint64_t)andor[1]) << 32) | andor[0]) ^ ((((uint64_t)andor[3]) << 32) | andor[2]);
-  bad = andor[4] != 0u;  // workgroup-uniform from here on
+  // workgroup-uniform from here on (read into scalar registers)
+  const uint32_t a0 = __builtin_amdgcn_readfirstlane(andor[0]), a1 = __builtin_amdgcn_readfirstlane(andor[1]);
+  const uint32_t o0 = __builtin_amdgcn_readfirstlane(andor[2]), o1 = __builtin_amdgcn_readfirstlane(andor[3]);
+  const uint64_t var = ((((uint64_t)a1) << 32) | a0) ^ ((((uint64_t)o1) << 32) | o0);
+  bad = __builtin_amdgcn_readfirstlane(andor[4]) != 0u;
 
   // radix passes over the varying bits; waves wholly past the end sit out
-  // (their items keep their own positions >= n and their payloads)
+  // (their items keep their own positions >= n and their payloads).
+  // Packed exchange (PACK, 32-bit keys): once the key bits that later passes
+  // still need fit beside the payload in one word, key and payload move
+  // together (one scatter per element instead of two); the word then holds
+  // key bits from `kbase` up at bit PB, and the payload in the low PB bits.
+  // The tie groups then need the full keys, read back from the margin by row.
+  constexpr int CAP = T * E;
+  constexpr bool CAN_PACK = PACK && (KW == 1) && !P32;
+  constexpr int PB = (CAP <= 512) ? 9 : (CAP <= 2048) ? 11 : (CAP <= 4096) ? 12 : (CAP <= 8192) ? 13 : 14;
+  static_assert(CAP <= (1 << PB), "payload field holds every position");
+  constexpr uint32_t PMASK = (1u << PB) - 1u;
+  bool packed = false;
+  int kbase = 0;
   const bool active = w * WAVE * E < n;
   if (var != 0ull && n > 1) {
     const int lo = __builtin_ctzll(var);
     const int hi = 63 - __builtin_clzll(var);
     const int npass = (hi - lo) / B + 1;
+    int ps = 0;
+    // passes with separate key and payload (the last of them may already
+    // write packed words)
 #pragma unroll 1
-    for (int ps = 0; ps < npass; ++ps) {
+    for (; ps < npass; ++ps) {
       const int off = lo + ps * B;
       if (((var >> off) & MASK) == 0ull) continue;  // constant digit: identity pass
       uint32_t pos[E];
       Rank::template rank<KW>(klo, khi, off, active, cnt, sm.red(), pos);
       if (ALIAS) __syncthreads();  // counters are read until here
+      bool pack_now = false;
+      if constexpr (CAN_PACK) {
+        const int rem = hi - (off + B) + 1;  // key bits that later passes need
+        pack_now = rem <= 0 || rem + PB <= 32;
+      }
       if (active) {
+        if (pack_now) {
+          const int sh = off + B;
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
-          xk[pos[j]] = klo[j];
-          if constexpr (P32)
-            sm.xv32()[pos[j]] = pay[j];
-          else
-            sm.xv16()[pos[j]] = (uint16_t)pay[j];
+          for (int j = 0; j < E; ++j) xk[pos[j]] = ((sh >= 32) ? 0u : (klo[j] >> sh) << PB) | pay[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            xk[pos[j]] = klo[j];
+            if constexpr (P32)
+              sm.xv32()[pos[j]] = pay[j];
+            else
+              sm.xv16()[pos[j]] = (uint16_t)pay[j];
+          }
         }
       }
       __syncthreads();
@@ -196,22 +225,24 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
           const uint4 a = sk[q];
           klo[4 * q] = a.x; klo[4 * q + 1] = a.y; klo[4 * q + 2] = a.z; klo[4 * q + 3] = a.w;
         }
-        if constexpr (P32) {
-          const uint4* sv = reinterpret_cast<const uint4*>(sm.xv32() + p0);
+        if (!pack_now) {
+          if constexpr (P32) {
+            const uint4* sv = reinterpret_cast<const uint4*>(sm.xv32() + p0);
 #pragma unroll
-          for (int q = 0; q < E / 4; ++q) {
-            const uint4 a = sv[q];
-            pay[4 * q] = a.x; pay[4 * q + 1] = a.y; pay[4 * q + 2] = a.z; pay[4 * q + 3] = a.w;
-          }
-        } else {
-          const uint4* sv = reinterpret_cast<const uint4*>(sm.xv16() + p0);
+            for (int q = 0; q < E / 4; ++q) {
+              const uint4 a = sv[q];
+              pay[4 * q] = a.x; pay[4 * q + 1] = a.y; pay[4 * q + 2] = a.z; pay[4 * q + 3] = a.w;
+            }
+          } else {
+            const uint4* sv = reinterpret_cast<const uint4*>(sm.xv16() + p0);
 #pragma unroll
-          for (int q = 0; q < E / 8; ++q) {
-            const uint4 a = sv[q];
-            pay[8 * q] = a.x & 0xFFFFu; pay[8 * q + 1] = a.x >> 16;
-            pay[8 * q + 2] = a.y & 0xFFFFu; pay[8 * q + 3] = a.y >> 16;
-            pay[8 * q + 4] = a.z & 0xFFFFu; pay[8 * q + 5] = a.z >> 16;
-            pay[8 * q + 6] = a.w & 0xFFFFu; pay[8 * q + 7] = a.w >> 16;
+            for (int q = 0; q < E / 8; ++q) {
+              const uint4 a = sv[q];
+              pay[8 * q] = a.x & 0xFFFFu; pay[8 * q + 1] = a.x >> 16;
+              pay[8 * q + 2] = a.y & 0xFFFFu; pay[8 * q + 3] = a.y >> 16;
+              pay[8 * q + 4] = a.z & 0xFFFFu; pay[8 * q + 5] = a.z >> 16;
+              pay[8 * q + 6] = a.w & 0xFFFFu; pay[8 * q + 7] = a.w >> 16;
+            }
           }
         }
       }
@@ -232,6 +263,56 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
         }
       }
       if (ALIAS) __syncthreads();  // exchange buffer is read until here
+      if (pack_now) {
+        packed = true;
+        kbase = off + B;
+        ++ps;
+        break;
+      }
+    }
+    // passes over packed words
+    if constexpr (CAN_PACK) {
+      if (packed) {
+#pragma unroll 1
+        for (; ps < npass; ++ps) {
+          const int off = lo + ps * B;
+          if (((var >> off) & MASK) == 0ull) continue;
+          uint32_t pos[E];
+          Rank::template rank<KW>(klo, khi, PB + off - kbase, active, cnt, sm.red(), pos);
+          if (ALIAS) __syncthreads();
+          if (active) {
+#pragma unroll
+            for (int j = 0; j < E; ++j) xk[pos[j]] = klo[j];
+          }
+          __syncthreads();
+          if (active) {
+            const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+#pragma unroll
+            for (int q = 0; q < E / 4; ++q) {
+              const uint4 a = sk[q];
+              klo[4 * q] = a.x; klo[4 * q + 1] = a.y; klo[4 * q + 2] = a.z; klo[4 * q + 3] = a.w;
+            }
+          }
+          if (ALIAS) __syncthreads();
+        }
+      }
+    }
+  }
+  if constexpr (CAN_PACK) {
+    if (packed) {
+      // payloads out of the packed words; the full keys (for the tie groups)
+      // are read back from the margin by row (an item past the end re-reads
+      // the last row: its key is not used)
+#pragma unroll
+      for (int j = 0; j < E; ++j) pay[j] = klo[j] & PMASK;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int r = min((int)pay[j], n - 1);
+        if (int_keys)
+          klo[j] = ((const uint32_t*)data)[r];
+        else
+          klo[j] = key_of((float)data[r]);
+      }
     }
   }
 
@@ -320,7 +401,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   return bad;
 }
 
-template <int T, int E, int B, int KW, bool ALIAS, bool P32>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false>
 __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   __shared__ RankLds<T, E, B, KW, ALIAS, P32> sm;
   const int sid = P.order[blockIdx.x];
@@ -338,17 +419,17 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   bool t1, t2, b1, b2;
   const int64_t o = sd.begin;
   if constexpr (KW == 2) {
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
                                                      P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
                                                      P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
   } else {
     const bool ik = P.int_keys != 0;
     const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
     const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
                                                     P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
                                                     P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
   }
   if (rk) return;
