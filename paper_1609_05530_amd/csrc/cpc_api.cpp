@@ -282,10 +282,15 @@ Carved carve(void* ws, const Layout& L) {
 
 int upload_tables(cpc_context* h, const Plan& P, const Carved& c, const int64_t* gofs, int64_t G,
                   hipStream_t s) {
-  const size_t K = P.subs.size();
-  HIP_OK(hipMemcpyAsync(c.subs, P.subs.data(), sizeof(SubDesc) * K, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(c.order_rank, P.order_rank.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(c.order_fit, P.order_fit.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice, s));
+  // the launch orders list only the subsets of the workgroup path (possibly none)
+  if (!P.subs.empty())
+    HIP_OK(hipMemcpyAsync(c.subs, P.subs.data(), sizeof(SubDesc) * P.subs.size(), hipMemcpyHostToDevice, s));
+  if (!P.order_rank.empty())
+    HIP_OK(hipMemcpyAsync(c.order_rank, P.order_rank.data(), sizeof(int32_t) * P.order_rank.size(),
+                          hipMemcpyHostToDevice, s));
+  if (!P.order_fit.empty())
+    HIP_OK(hipMemcpyAsync(c.order_fit, P.order_fit.data(), sizeof(int32_t) * P.order_fit.size(),
+                          hipMemcpyHostToDevice, s));
   if (gofs) HIP_OK(hipMemcpyAsync(c.gofs, gofs, sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
   if (!P.bsegs.empty()) {
     HIP_OK(hipMemcpyAsync((void*)c.big.segs, P.bsegs.data(), sizeof(BigSeg) * P.bsegs.size(), hipMemcpyHostToDevice, s));

@@ -543,3 +543,23 @@ def test_fp32c_matches_fp64_on_every_subset():
         print(f"[fp32c vs fp64] {fam} {th:g}: max rel dtheta {rel.max():.2e}, dvar {vrel.max():.2e}", flush=True)
         assert rel.max() <= rt, (fam, th, rel.max())
         assert vrel.max() <= 1e-4, (fam, th, vrel.max())
+
+
+def test_fresh_handle_only_streaming_subsets():
+    """Regression: a handle whose first call has no subset of the workgroup
+    path (every subset above 16384 rows) uploads empty launch orders."""
+    import ctypes
+    from paper_1609_05530_amd import _lib
+    x, y = synth.copula_pairs("frank", 4.0, 40000, seed=77, dtype=np.float32)
+    off = np.array([0, 20000, 40000], dtype=np.int64)
+    gofs = np.array([0, 2], dtype=np.int64)
+    h = ctypes.c_void_p()
+    _lib.check(_lib.lib().cpc_create(0, ctypes.byref(h)))
+    try:
+        got = _fit_with_handle(h, dev(x, torch.float32), dev(y, torch.float32), off, gofs, ["frank"], -1)
+    finally:
+        _lib.check(_lib.lib().cpc_destroy(h))
+    ref = to_np(cpc().fit(dev(x, torch.float32), dev(y, torch.float32), off, "frank", prec="fp32c"))
+    assert np.all(got["status"] == 0)
+    for k in got:
+        assert np.array_equal(got[k], ref[k], equal_nan=True), k
