@@ -15,9 +15,11 @@
 //      element count (< 2^16), and the upper halves then take the total of
 //      the lower ones, which gives the digit-major, thread-minor prefix;
 //   3. an element's position in the stable order is its counter's prefix
-//      plus its offset.
+//      plus its offset: the 16-bit half of (prefix word + returned word)
+//      that holds its digit (neither half of that sum can carry into the
+//      other: each is at most the element count).
 // No cross-lane matching is needed: a pass costs a few LDS operations and
-// about a dozen VALU instructions per element.
+// about ten VALU instructions per element (32-bit keys).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -62,9 +64,37 @@ struct BlockDigitRank {
     if constexpr (KW == 2) return (uint32_t)((((uint64_t)hi << 32) | lo) >> off) & kMask;
     return (lo >> off) & kMask;
   }
+  // counter word (d mod C) and half (d / C) of an item's digit. INSIDE: the
+  // whole digit lies in the 32-bit key (off + B <= 32), so that each part is
+  // one field extract; otherwise the digit is extracted once (bits past 31
+  // read as zero) and split.
+  template <int KW, bool INSIDE>
+  __device__ static __forceinline__ void digit_parts(uint32_t lo, uint32_t hi, int off, uint32_t& col,
+                                                     uint32_t& half) {
+    if constexpr (KW == 1 && INSIDE) {
+      col = __builtin_amdgcn_ubfe(lo, (uint32_t)off, (uint32_t)(B - 1));
+      half = __builtin_amdgcn_ubfe(lo, (uint32_t)(off + B - 1), 1u);
+    } else if constexpr (KW == 1) {
+      const uint32_t d = __builtin_amdgcn_ubfe(lo, (uint32_t)off, (uint32_t)B);
+      col = d & (C - 1);
+      half = d >> (B - 1);
+    } else {
+      const uint32_t d = digit_of<KW>(lo, hi, off);
+      col = d & (C - 1);
+      half = d >> (B - 1);
+    }
+  }
   template <int KW>
   __device__ static __forceinline__ void rank(const uint32_t (&klo)[E], const uint32_t (&khi)[E], int off, bool active,
                                               uint32_t* cnt, uint32_t* red, uint32_t (&pos)[E]) {
+    if (KW == 1 && off + B <= 32)  // workgroup-uniform
+      rank_t<KW, true>(klo, khi, off, active, cnt, red, pos);
+    else
+      rank_t<KW, false>(klo, khi, off, active, cnt, red, pos);
+  }
+  template <int KW, bool INSIDE>
+  __device__ static __forceinline__ void rank_t(const uint32_t (&klo)[E], const uint32_t (&khi)[E], int off,
+                                                bool active, uint32_t* cnt, uint32_t* red, uint32_t (&pos)[E]) {
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     // 1. private counters: clear, then count in order (pos[j] holds the
     //    counter word before the item's increment)
@@ -73,8 +103,9 @@ struct BlockDigitRank {
     if (active) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const uint32_t d = digit_of<KW>(klo[j], khi[j], off);
-        pos[j] = atomicAdd(&cnt[(d & (C - 1)) * T + t], 1u << ((d >> (B - 1)) << 4));
+        uint32_t col, half;
+        digit_parts<KW, INSIDE>(klo[j], khi[j], off, col, half);
+        pos[j] = atomicAdd(&cnt[col * T + t], half * 0xFFFFu + 1u);  // 1 or 1 << 16
       }
     }
     __syncthreads();
@@ -109,6 +140,7 @@ struct BlockDigitRank {
       if (k < w) base += r;
       grand += r;
     }
+    base += (grand & 0xFFFFu) << 16;  // upper halves follow every lower-half digit
     if constexpr (C % 4 == 0) {
       uint4* dst = reinterpret_cast<uint4*>(cnt + t * C);
 #pragma unroll
@@ -122,18 +154,16 @@ struct BlockDigitRank {
     // 3. positions (the shift and column index are laundered so that the
     //    counting phase's digits and addresses are recomputed, not kept live
     //    across the scan)
-    const uint32_t lowtot = grand & 0xFFFFu;
     int tl = t, offl = __builtin_amdgcn_readfirstlane(off);
     asm volatile("" : "+v"(tl));
     asm volatile("" : "+s"(offl));
     if (active) {
 #pragma unroll
       for (int j = 0; j < E; ++j) {
-        const uint32_t d = digit_of<KW>(klo[j], khi[j], offl);
-        const uint32_t word = cnt[(d & (C - 1)) * T + tl];
-        const uint32_t sh = (d >> (B - 1)) << 4;
-        const uint32_t base = (d >> (B - 1)) ? (word >> 16) + lowtot : (word & 0xFFFFu);
-        pos[j] = base + ((pos[j] >> sh) & 0xFFFFu);
+        uint32_t col, half;
+        digit_parts<KW, INSIDE>(klo[j], khi[j], offl, col, half);
+        const uint32_t word = cnt[col * T + tl];
+        pos[j] = __builtin_amdgcn_ubfe(word + pos[j], half << 4, 16u);
       }
     }
   }

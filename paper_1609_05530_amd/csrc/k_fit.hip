@@ -29,8 +29,20 @@ struct FitSmem {
   CT ly[GC ? CAP : 1];
 };
 
+// Waves per SIMD asked of the register allocator: up to 4 (128 VGPRs) where
+// the workgroup's LDS lets that many waves share a CU, so that two or more
+// subsets run side by side: while one workgroup sits in its reduction and
+// serial FP64 Newton update, the other's rows keep the VALU busy.
 template <int T, int CAP, typename CT, int FAM>
-__global__ void __launch_bounds__(T) k_fit_wg(FitParams P) {
+constexpr int fit_waves_per_simd() {
+  constexpr int lds = (int)sizeof(FitSmem<CAP, CT, FAM>) + 1024;  // rows + reduction scratch and solver state
+  constexpr int wgs = (160 * 1024) / lds;
+  constexpr int w = wgs * (T / WAVE) / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+template <int T, int CAP, typename CT, int FAM>
+__global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_fit_wg(FitParams P) {
   constexpr int W = T / WAVE;
   using SM = FitSmem<CAP, CT, FAM>;
   __shared__ SM sm;
@@ -48,14 +60,28 @@ __global__ void __launch_bounds__(T) k_fit_wg(FitParams P) {
   const CT inv = (CT)1 / (CT)twon1;
   const double dn = (double)n;
 
+  // Rows i = tid + k*T: all of a thread's rank loads are issued before any is
+  // used (the loop body is too short to hide HBM latency otherwise).
+  constexpr int E = CAP / T;
+  uint32_t rab[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int ic = min(tid + k * T, n - 1);
+    rab[k] = (uint32_t)R1[ic] | ((uint32_t)R2[ic] << 16);
+  }
   long long sacc = 0;
-  for (int i = tid; i < n; i += T) {
-    const uint32_t a = R1[i], b = R2[i];
-    sacc += ((long long)a - (n + 1)) * ((long long)b - (n + 1));
-    if constexpr (SM::GC) {
-      gumbel_lxy<CT>(a, b, twon1, inv, sm.lx[i], sm.ly[i]);
-    } else {
-      sm.rr[i] = a | (b << 16);
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int i = tid + k * T;
+    const uint32_t a = rab[k] & 0xFFFFu, b = rab[k] >> 16;
+    const long long term = ((long long)a - (n + 1)) * ((long long)b - (n + 1));
+    sacc += (i < n) ? term : 0ll;
+    if (i < n) {
+      if constexpr (SM::GC) {
+        gumbel_lxy<CT>(a, b, twon1, inv, sm.lx[i], sm.ly[i]);
+      } else {
+        sm.rr[i] = rab[k];
+      }
     }
   }
   const long long S = block_sum_ll<W>(sacc, (long long*)red);
@@ -192,12 +218,15 @@ static hipError_t launch_t(int fam, const FitParams& p, int grid, hipStream_t s)
   return hipGetLastError();
 }
 
+// Threads per subset by size class: the LDS rows of a class-3 subset (64 KiB)
+// allow two workgroups per CU, of a class-2 subset four; 512 and 256 threads
+// then fill a CU with 16 waves. (The rank kernel's class shapes are separate.)
 hipError_t launch_fit_wg(int cls, int fam, int fp64, const FitParams& p, int grid, hipStream_t s) {
   switch (cls) {
     case 0: return fp64 ? launch_t<64, 512, double>(fam, p, grid, s) : launch_t<64, 512, float>(fam, p, grid, s);
     case 1: return fp64 ? launch_t<256, 2048, double>(fam, p, grid, s) : launch_t<256, 2048, float>(fam, p, grid, s);
-    case 2: return fp64 ? launch_t<512, 8192, double>(fam, p, grid, s) : launch_t<512, 8192, float>(fam, p, grid, s);
-    case 3: return fp64 ? launch_t<1024, 16384, double>(fam, p, grid, s) : launch_t<1024, 16384, float>(fam, p, grid, s);
+    case 2: return fp64 ? launch_t<256, 8192, double>(fam, p, grid, s) : launch_t<256, 8192, float>(fam, p, grid, s);
+    case 3: return fp64 ? launch_t<512, 16384, double>(fam, p, grid, s) : launch_t<512, 16384, float>(fam, p, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

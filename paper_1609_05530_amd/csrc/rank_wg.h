@@ -329,6 +329,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     plo = sm.wl()[(w - 1) * KW];
     if (KW == 2) phi = sm.wl()[(w - 1) * KW + KW - 1];
   }
+  static_assert(E <= 32, "the group-start bits of a thread's items fit one word");
   uint32_t headm = 0u;  // bit j: item j starts a group
   int hmax = -1, hmin = INT_MAX;
 #pragma unroll
