@@ -29,14 +29,30 @@
 
 namespace cpc {
 
-// Inclusive prefix sum over the lanes of a wave.
+// Lane i's value of src from lane i - n of its 16-lane row, 0 for the first
+// n lanes of the row (DPP row shift; dpp_ctrl 0x110 + n).
+template <int N>
+__device__ __forceinline__ uint32_t row_shr(uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)src, 0x110 + N, 0xF, 0xF, false);
+}
+
+// Inclusive prefix sum within each 16-lane row.
+__device__ __forceinline__ uint32_t row_incl_sum_u32(uint32_t v) {
+  v += row_shr<1>(v);
+  v += row_shr<2>(v);
+  v += row_shr<4>(v);
+  v += row_shr<8>(v);
+  return v;
+}
+
+// Inclusive prefix sum over the lanes of a wave: row scans, then the last
+// lane of row 0 is added into row 1 and of row 2 into row 3 (row_bcast:15,
+// dpp_ctrl 0x142, rows 1 and 3), then the last lane of row 1 into rows 2 and
+// 3 (row_bcast:31, dpp_ctrl 0x143).
 __device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
-  const int lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const uint32_t t = __shfl_up(v, off, WAVE);
-    if (lane >= off) v += t;
-  }
+  v = row_incl_sum_u32(v);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
   return v;
 }
 
@@ -133,13 +149,13 @@ struct BlockDigitRank {
     const uint32_t incl = wave_incl_sum_u32(run);
     if (lane == WAVE - 1) red[w] = incl;
     __syncthreads();
-    uint32_t base = incl - run, grand = 0u;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-      const uint32_t r = red[k];
-      if (k < w) base += r;
-      grand += r;
-    }
+    // the waves' totals, scanned across the first W lanes of every wave
+    static_assert(W <= 16, "wave totals fit one DPP row");
+    const uint32_t wsum = row_incl_sum_u32(lane < W ? red[lane] : 0u);
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const uint32_t before = wu ? (uint32_t)__builtin_amdgcn_readlane((int)wsum, wu - 1) : 0u;
+    const uint32_t grand = (uint32_t)__builtin_amdgcn_readlane((int)wsum, W - 1);
+    uint32_t base = incl - run + before;
     base += (grand & 0xFFFFu) << 16;  // upper halves follow every lower-half digit
     if constexpr (C % 4 == 0) {
       uint4* dst = reinterpret_cast<uint4*>(cnt + t * C);
