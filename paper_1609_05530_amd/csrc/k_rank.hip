@@ -8,14 +8,15 @@ namespace cpc {
 
 // Launch shapes per size class: (threads, items per thread, digit bits,
 // counters sharing LDS with the exchange buffer, 32-bit payloads). The class
-// capacity threads * items must match kClassThreads * kClassItems.
+// capacity threads * items must match kClassThreads * kClassItems. Every
+// launch uses the bank-conflict-free padded exchange layout.
 template <int T, int E, int B, bool ALIAS, bool P32>
 static hipError_t launch_t(int kw, const RankParams& p, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
   if (kw == 2)
-    hipLaunchKernelGGL((k_rank_wg<T, E, B, 2, ALIAS, P32>), dim3(grid), dim3(T), 0, s, p);
+    hipLaunchKernelGGL((k_rank_wg<T, E, B, 2, ALIAS, P32, false, true>), dim3(grid), dim3(T), 0, s, p);
   else
-    hipLaunchKernelGGL((k_rank_wg<T, E, B, 1, ALIAS, P32>), dim3(grid), dim3(T), 0, s, p);
+    hipLaunchKernelGGL((k_rank_wg<T, E, B, 1, ALIAS, P32, false, true>), dim3(grid), dim3(T), 0, s, p);
   return hipGetLastError();
 }
 
@@ -27,7 +28,7 @@ static_assert(kClassThreads[3] * kClassItems[3] == 1024 * 16, "class 3 capacity"
 template <int T, int E, bool PACK>
 static hipError_t launch_shape1(const RankParams& p, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_rank_wg<T, E, 4, 1, false, false, PACK>), dim3(grid), dim3(T), 0, s, p);
+  hipLaunchKernelGGL((k_rank_wg<T, E, 4, 1, false, false, PACK, true>), dim3(grid), dim3(T), 0, s, p);
   return hipGetLastError();
 }
 

@@ -86,11 +86,11 @@ constexpr RankShape kRankShapes[kNumRankShapes] = {
     {1024, 16, 16384, 1}, {512, 32, 16384, 1}};
 // built-in choices (measured fastest on MI355X: packed words pay off where
 // several workgroups share a CU, not at one workgroup per CU)
-constexpr int kRankDefaultShape[kNumClasses] = {7, 8, 10, 5};
+constexpr int kRankDefaultShape[kNumClasses] = {7, 9, 10, 5};
 // Candidate shapes per size class (-1 terminated): one wave or one larger
 // workgroup per subset for the smallest class, two thread / item splits for
 // the others; each unpacked and packed.
-constexpr int kRankCandidates[kNumClasses][5] = {{7, 8, 0, 1, -1}, {8, 9, 1, 2, -1}, {10, 11, 3, 4, -1},
+constexpr int kRankCandidates[kNumClasses][5] = {{7, 8, 0, 1, -1}, {9, 8, 2, 1, -1}, {10, 11, 3, 4, -1},
                                                  {5, 6, 12, 13, -1}};
 hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, hipStream_t s);
 hipError_t launch_fit_wg(int cls, int fam, int fp64, const FitParams& p, int grid, hipStream_t s);

@@ -32,20 +32,32 @@ namespace cpc {
 // exchange keys (between a pass's gather and its next scatter), the AND / OR
 // of the keys in the payload area (load phase), the tie-phase arrays in the
 // counters (after the last pass).
-template <int T, int E, int B, int KW, bool ALIAS, bool P32>
+// PAD: each thread's block of E keys (and of E payloads) is followed by 16
+// unused bytes where needed, so that the per-lane stride is an odd multiple
+// of 16 bytes and the lanes' 16-byte reads of their own blocks fall in
+// distinct banks.
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PAD = false>
 struct RankLds {
   static constexpr int W = T / WAVE;
   static constexpr int CAP = T * E;
   static constexpr int CNT = BlockDigitRank<T, E, B>::kCounterWords;
-  static constexpr int XW = CAP + (P32 ? CAP : CAP / 2);
+  static constexpr int KPAD = PAD ? 4 : 0;                     // u32 words after each key block
+  static constexpr int VPAD = !PAD ? 0 : P32 ? 4 : (E == 8 ? 0 : 8);  // payload elements after each block
+  static constexpr int CAPK = CAP + (CAP / E) * KPAD;          // key words
+  static constexpr int CAPV = CAP + (CAP / E) * VPAD;          // payload elements
+  static constexpr int XW = CAPK + (P32 ? CAPV : (CAPV + 1) / 2);
+  static_assert(E % 8 == 0 || !PAD, "padded blocks stay 16-byte aligned");
+  // exchange index of position p (keys; payloads)
+  __device__ static __forceinline__ int kx(int p) { return PAD ? p + (p / E) * KPAD : p; }
+  __device__ static __forceinline__ int vx(int p) { return PAD ? p + (p / E) * VPAD : p; }
   static constexpr int SMALL = 3 * W + W * KW + 8;  // red, wmax, wmin, wl, andor (+ non-finite flag)
   static constexpr int MAIN = ALIAS ? (CNT > XW ? CNT : XW) + SMALL : CNT + XW;
   static_assert(ALIAS || CNT >= 2 * W + W * KW, "tie-phase arrays fit in the counters");
   alignas(16) uint32_t main[MAIN];  // 16-byte vector reads of keys, payloads, counters
   __device__ __forceinline__ uint32_t* cnt() { return main; }
   __device__ __forceinline__ uint32_t* xk() { return ALIAS ? main : main + CNT; }
-  __device__ __forceinline__ uint32_t* xv32() { return xk() + CAP; }
-  __device__ __forceinline__ uint16_t* xv16() { return reinterpret_cast<uint16_t*>(xk() + CAP); }
+  __device__ __forceinline__ uint32_t* xv32() { return xk() + CAPK; }
+  __device__ __forceinline__ uint16_t* xv16() { return reinterpret_cast<uint16_t*>(xk() + CAPK); }
   __device__ __forceinline__ uint32_t* small() { return main + (MAIN - SMALL); }
   __device__ __forceinline__ uint32_t* red() { return ALIAS ? small() : xk(); }
   __device__ __forceinline__ int32_t* wmax() { return (int32_t*)(ALIAS ? small() + W : cnt()); }
@@ -53,7 +65,7 @@ struct RankLds {
   __device__ __forceinline__ uint32_t* wl() { return (uint32_t*)(wmax() + 2 * W); }
   __device__ __forceinline__ uint32_t* andor() { return ALIAS ? small() + 3 * W + W * KW : xv32(); }
 };
-static_assert(sizeof(RankLds<1024, 16, 4, 1, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
+static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
 
 template <typename U>
 __device__ __forceinline__ U wave_and(U v) {
@@ -72,11 +84,12 @@ __device__ __forceinline__ U wave_or(U v) {
 // position e and tie-group start lb). Returns true (in every thread) if the
 // margin holds a non-finite value; sets all_tied (in thread 0) if every value
 // is equal.
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, typename DT>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
-                                                RankLds<T, E, B, KW, ALIAS, P32>& sm, uint16_t* Rg, uint16_t* Eg,
+                                                RankLds<T, E, B, KW, ALIAS, P32, PAD>& sm, uint16_t* Rg, uint16_t* Eg,
                                                 uint16_t* Lg, uint32_t* R32, bool& all_tied) {
   using Rank = BlockDigitRank<T, E, B>;
+  using Lds = RankLds<T, E, B, KW, ALIAS, P32, PAD>;
   constexpr int W = T / WAVE;
   constexpr uint32_t MASK = Rank::kMask;
   const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
@@ -118,7 +131,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
         }
         kand &= valid ? (uint64_t)k : ~0ull;
         kor |= valid ? (uint64_t)k : 0ull;
-        xk[e] = valid ? k : ~0u;
+        xk[Lds::kx(e)] = valid ? k : ~0u;
       }
     };
     if (int_keys)
@@ -152,7 +165,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   if (lane == 0 && badw != 0ull) atomicOr(&andor[4], 1u);
   __syncthreads();
   if constexpr (KW == 1) {
-    const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+    const uint4* sk = reinterpret_cast<const uint4*>(xk + Lds::kx(p0));
 #pragma unroll
     for (int q = 0; q < E / 4; ++q) {
       const uint4 a = sk[q];
@@ -205,21 +218,21 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
         if (pack_now) {
           const int sh = off + B;
 #pragma unroll
-          for (int j = 0; j < E; ++j) xk[pos[j]] = ((sh >= 32) ? 0u : (klo[j] >> sh) << PB) | pay[j];
+          for (int j = 0; j < E; ++j) xk[Lds::kx(pos[j])] = ((sh >= 32) ? 0u : (klo[j] >> sh) << PB) | pay[j];
         } else {
 #pragma unroll
           for (int j = 0; j < E; ++j) {
-            xk[pos[j]] = klo[j];
+            xk[Lds::kx(pos[j])] = klo[j];
             if constexpr (P32)
-              sm.xv32()[pos[j]] = pay[j];
+              sm.xv32()[Lds::vx(pos[j])] = pay[j];
             else
-              sm.xv16()[pos[j]] = (uint16_t)pay[j];
+              sm.xv16()[Lds::vx(pos[j])] = (uint16_t)pay[j];
           }
         }
       }
       __syncthreads();
       if (active) {
-        const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+        const uint4* sk = reinterpret_cast<const uint4*>(xk + Lds::kx(p0));
 #pragma unroll
         for (int q = 0; q < E / 4; ++q) {
           const uint4 a = sk[q];
@@ -227,14 +240,14 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
         }
         if (!pack_now) {
           if constexpr (P32) {
-            const uint4* sv = reinterpret_cast<const uint4*>(sm.xv32() + p0);
+            const uint4* sv = reinterpret_cast<const uint4*>(sm.xv32() + Lds::vx(p0));
 #pragma unroll
             for (int q = 0; q < E / 4; ++q) {
               const uint4 a = sv[q];
               pay[4 * q] = a.x; pay[4 * q + 1] = a.y; pay[4 * q + 2] = a.z; pay[4 * q + 3] = a.w;
             }
           } else {
-            const uint4* sv = reinterpret_cast<const uint4*>(sm.xv16() + p0);
+            const uint4* sv = reinterpret_cast<const uint4*>(sm.xv16() + Lds::vx(p0));
 #pragma unroll
             for (int q = 0; q < E / 8; ++q) {
               const uint4 a = sv[q];
@@ -250,11 +263,11 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int j = 0; j < E; ++j) xk[pos[j]] = khi[j];
+          for (int j = 0; j < E; ++j) xk[Lds::kx(pos[j])] = khi[j];
         }
         __syncthreads();
         if (active) {
-          const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+          const uint4* sk = reinterpret_cast<const uint4*>(xk + Lds::kx(p0));
 #pragma unroll
           for (int q = 0; q < E / 4; ++q) {
             const uint4 a = sk[q];
@@ -282,11 +295,11 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
           if (ALIAS) __syncthreads();
           if (active) {
 #pragma unroll
-            for (int j = 0; j < E; ++j) xk[pos[j]] = klo[j];
+            for (int j = 0; j < E; ++j) xk[Lds::kx(pos[j])] = klo[j];
           }
           __syncthreads();
           if (active) {
-            const uint4* sk = reinterpret_cast<const uint4*>(xk + p0);
+            const uint4* sk = reinterpret_cast<const uint4*>(xk + Lds::kx(p0));
 #pragma unroll
             for (int q = 0; q < E / 4; ++q) {
               const uint4 a = sk[q];
@@ -402,9 +415,9 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   return bad;
 }
 
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false, bool PAD = false>
 __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
-  __shared__ RankLds<T, E, B, KW, ALIAS, P32> sm;
+  __shared__ RankLds<T, E, B, KW, ALIAS, P32, PAD> sm;
   const int sid = P.order[blockIdx.x];
   const SubDesc sd = P.subs[sid];
   const int n = sd.n;
@@ -420,17 +433,17 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   bool t1, t2, b1, b2;
   const int64_t o = sd.begin;
   if constexpr (KW == 2) {
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
                                                      P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
                                                      P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
   } else {
     const bool ik = P.int_keys != 0;
     const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
     const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
                                                     P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
                                                     P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
   }
   if (rk) return;
