@@ -41,8 +41,9 @@ PEAK_HBM = 8.0e12                       # bytes/s
 # Algorithmic HBM bytes per row of the rank step: read x, y (FP32) and write
 # the two u16 doubled ranks.
 RANK_BYTES_PER_ROW = 4 + 4 + 2 + 2
-# the rank kernel's body (its launch shapes live in k_rank.hip)
-RANK_SOURCES = ["paper_1609_05530_amd/csrc/rank_wg.h", "paper_1609_05530_amd/csrc/block_rank.h"]
+# the rank kernel's sources (body, launch shapes and shape tables)
+RANK_SOURCES = ["paper_1609_05530_amd/csrc/rank_wg.h", "paper_1609_05530_amd/csrc/block_rank.h",
+                "paper_1609_05530_amd/csrc/k_rank.hip", "paper_1609_05530_amd/csrc/kernels.h"]
 
 
 def parse():

@@ -85,6 +85,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
   const uint32_t twon1 = 2u * (uint32_t)(n + 1);
   const CT inv = (CT)1 / (CT)twon1;
   const double dn = (double)n;
+  const double idn = 1.0 / dn;  // W1, W2 are means over the subset
   const Consts<CT> c = make_consts<CT>(FAM, theta);
   const bool rd = sizeof(CT) == 4 && c.use_d;  // FP64 rows near the family boundaries
   const Consts<double> cd = make_consts<double>(FAM, theta);
@@ -160,7 +161,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
           const CT s2 = S[i2];
           const uint32_t l2 = (uint32_t)L1[i2] | ((uint32_t)L2[i2] << 16);
           const double psi =
-              (double)s0 + ((double)A1[pidx((int)(l0 & 0xFFFFu))] + (double)A2[pidx((int)(l0 >> 16))]) / dn;
+              (double)s0 + ((double)A1[pidx((int)(l0 & 0xFFFFu))] + (double)A2[pidx((int)(l0 >> 16))]) * idn;
           psum += psi;
           psq += psi * psi;
           s0 = s1; l0 = l1; s1 = s2; l1 = l2;
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
       }
       __syncthreads();
       lds_suffix_sum<T, E, CT>(A1, n, red);
-      for (int i = tid; i < n; i += T) S[i] = (CT)((double)S[i] + (double)A1[pidx(L1[i])] / dn);
+      for (int i = tid; i < n; i += T) S[i] = (CT)((double)S[i] + (double)A1[pidx(L1[i])] * idn);
       __syncthreads();
       for (int i = tid; i < n; i += T) {
         CT l, s, g1, g2;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
       __syncthreads();
       lds_suffix_sum<T, E, CT>(A1, n, red);
       for (int i = tid; i < n; i += T) {
-        const double psi = (double)S[i] + (double)A1[pidx(L2[i])] / dn;
+        const double psi = (double)S[i] + (double)A1[pidx(L2[i])] * idn;
         psum += psi;
         psq += psi * psi;
       }
