@@ -38,7 +38,9 @@ __global__ void __launch_bounds__(256) k_big_zero_flags(BigParams P) {
 template <typename DT>
 __global__ void __launch_bounds__(BT) k_big_init(const DT* data, int int_keys, BigParams P, uint32_t* klo,
                                                  uint32_t* khi, uint32_t* val) {
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   int bad = 0;
   for (int i = threadIdx.x; i < t.count; i += BT) {
@@ -64,13 +66,15 @@ __global__ void __launch_bounds__(BT) k_big_init(const DT* data, int int_keys, B
 
 __global__ void __launch_bounds__(BT) k_big_hist(const uint32_t* kw, int shift, BigParams P, uint32_t* hist) {
   __shared__ uint32_t h[256];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   h[threadIdx.x] = 0u;
   __syncthreads();
   for (int i = threadIdx.x; i < t.count; i += BT) atomicAdd(&h[(kw[s.roff + t.start + i] >> shift) & 0xFFu], 1u);
   __syncthreads();
-  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+  hist[ti * 256 + threadIdx.x] = h[threadIdx.x];
 }
 
 // Per subset: hist[tile][d] <- first destination (subset-local) of the tile's
@@ -106,7 +110,9 @@ __global__ void __launch_bounds__(BT) k_big_scatter(const uint32_t* klo, const u
                                                     int shift, int pass, BigParams P, const uint32_t* hist) {
   __shared__ uint16_t cnt[(BT / WAVE) * 256];
   __shared__ uint32_t dtot[256 + 2 + 4];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int n = t.count;
@@ -128,7 +134,7 @@ __global__ void __launch_bounds__(BT) k_big_scatter(const uint32_t* klo, const u
   for (int j = 0; j < BE; ++j) {
     const int e = (w * BE + j) * WAVE + lane;
     if (e < n) {
-      const uint32_t g = hist[(int64_t)blockIdx.x * 256 + d[j]] + (dst[j] - dtot[d[j]]);
+      const uint32_t g = hist[ti * 256 + d[j]] + (dst[j] - dtot[d[j]]);
       klo_o[s.roff + g] = lo[j];
       if (KW == 2) khi_o[s.roff + g] = hi[j];
       val_o[s.roff + g] = v[j];
@@ -137,13 +143,19 @@ __global__ void __launch_bounds__(BT) k_big_scatter(const uint32_t* klo, const u
 }
 
 // Tie groups in sorted order -> doubled ranks, sorted positions, group starts
-// (all subset-local), written at the row's compact index.
+// (all subset-local). A subset of at most kBigChunkMaxRows rows keeps R and the
+// group start in sorted order (RS, LS: coalesced) for k_big_unpermute; a
+// larger one writes R, E, L at the row's compact index directly; the rank
+// entry point writes R at the row's input index.
 template <int KW>
 __global__ void __launch_bounds__(BT) k_big_ranks(const uint32_t* klo, const uint32_t* khi, const uint32_t* val,
                                                   int ties, BigParams P, uint32_t* R, uint32_t* Eo, uint32_t* Lo,
-                                                  uint32_t* R32) {
-  const BigTile t = P.tiles[blockIdx.x];
+                                                  uint32_t* R32, uint32_t* RS, uint32_t* LS) {
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
+  const bool staged = !R32 && s.n <= kBigChunkMaxRows;  // uniform per tile
   const uint32_t* K0 = klo + s.roff;
   const uint32_t* K1 = khi + s.roff;
   auto key = [&](int64_t p) -> uint64_t { return KW == 2 ? (((uint64_t)K1[p] << 32) | K0[p]) : (uint64_t)K0[p]; };
@@ -167,8 +179,14 @@ __global__ void __launch_bounds__(BT) k_big_ranks(const uint32_t* klo, const uin
       }
       ub = lo;
     }
-    const int64_t row = val[s.roff + p];
     const uint32_t r = (ties == 1) ? (uint32_t)(2 * (p + 1)) : (uint32_t)(lb + ub + 1);
+    if (staged) {
+      RS[s.roff + p] = r;
+      LS[s.roff + p] = (uint32_t)((ties == 1) ? p : lb);
+      if (p == 0 && ub >= s.n) atomicOr(&P.flags[t.seg], 2);
+      continue;
+    }
+    const int64_t row = val[s.roff + p];
     if (R32) {
       R32[s.begin + row] = r;
     } else {
@@ -177,6 +195,49 @@ __global__ void __launch_bounds__(BT) k_big_ranks(const uint32_t* klo, const uin
       Lo[s.roff + row] = (uint32_t)((ties == 1) ? p : lb);
     }
     if (p == 0 && ub >= s.n) atomicOr(&P.flags[t.seg], 2);  // a single value
+  }
+}
+
+// Sorted order -> row order for one chunk of rows of one subset: the
+// workgroup reads the subset's sorted row indices (coalesced), keeps the
+// entries whose row falls in its chunk in LDS, and writes R, E (the sorted
+// position) and L for its rows contiguously. Replaces three scattered 4-byte
+// writes per row with reads that the chunks of a subset share through L2.
+constexpr int UT = 1024;
+__global__ void __launch_bounds__(UT) k_big_unpermute(BigParams P, const uint32_t* val, const uint32_t* RS,
+                                                      const uint32_t* LS, uint32_t* R, uint32_t* Eo, uint32_t* Lo) {
+  __shared__ uint32_t lr[kBigChunk], le[kBigChunk], ll[kBigChunk];
+  const BigTile c = P.chunks[blockIdx.x];
+  if (c.count <= 0) return;  // idle slot (uniform)
+  const BigSeg s = P.segs[c.seg];
+  const uint32_t* V = val + s.roff;
+  const uint32_t r0 = (uint32_t)c.start, cnt = (uint32_t)c.count;
+  const uint32_t n = (uint32_t)s.n;
+  constexpr int U = 4;  // loads in flight per thread
+  for (uint32_t base = 0; base < n; base += UT * U) {
+    uint32_t rows[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t p = base + k * UT + threadIdx.x;
+      rows[k] = p < n ? V[p] : 0xFFFFFFFFu;
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const uint32_t p = base + k * UT + threadIdx.x;
+      const uint32_t d = rows[k] - r0;  // rows below the chunk wrap to large values
+      if (p < n && d < cnt) {
+        lr[d] = RS[s.roff + p];
+        le[d] = p;
+        ll[d] = LS[s.roff + p];
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t o = s.roff + (int64_t)r0;
+  for (uint32_t i = threadIdx.x; i < cnt; i += UT) {
+    R[o + i] = lr[i];
+    Eo[o + i] = le[i];
+    Lo[o + i] = ll[i];
   }
 }
 
@@ -196,7 +257,9 @@ template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_start(BigParams P, const uint32_t* R1, const uint32_t* R2, CT* LX,
                                                   CT* LY, double* part) {
   __shared__ double red[(BT / WAVE) * 3];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   const uint32_t twon1 = (uint32_t)(2 * (s.n + 1));
   const CT inv = (CT)1 / (CT)twon1;
@@ -216,7 +279,7 @@ __global__ void __launch_bounds__(BT) k_big_start(BigParams P, const uint32_t* R
     }
   }
   double v[3] = {(double)sp, kp.value(), km.value()};
-  tile_partials<3>(v, red, part + (int64_t)blockIdx.x * 5);
+  tile_partials<3>(v, red, part + ti * 5);
 }
 
 __global__ void __launch_bounds__(256) k_big_start_update(BigParams P, const double* part, NewtonState* st,
@@ -264,7 +327,9 @@ __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1
                                                  const int* pending) {
   __shared__ double red[(BT / WAVE) * 3];
   if (*pending == 0) return;  // every subset has converged
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   if (st[t.seg].done) return;  // uniform per tile
   const double th = st[t.seg].theta;
@@ -296,7 +361,7 @@ __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1
     }
     v[0] = ks.value(); v[1] = kh.value(); v[2] = (double)s2;
   }
-  tile_partials<3>(v, red, part + (int64_t)blockIdx.x * 5);
+  tile_partials<3>(v, red, part + ti * 5);
 }
 
 __global__ void __launch_bounds__(256) k_big_update(BigParams P, const double* part, NewtonState* st, double tol,
@@ -336,7 +401,9 @@ __global__ void __launch_bounds__(BT) k_big_var_rows(BigParams P, const uint32_t
                                                      const uint32_t* E1, const uint32_t* E2, const NewtonState* st,
                                                      const double* theta_in, CT* A1, CT* A2, CT* S, double* part) {
   __shared__ double red[(BT / WAVE) * 3];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   const int fam = s.family;
   const double th = theta_in ? theta_in[s.sid] : st[t.seg].theta;
@@ -383,7 +450,7 @@ __global__ void __launch_bounds__(BT) k_big_var_rows(BigParams P, const uint32_t
     S[q] = sv;
   }
   double v[3] = {kl.value(), ks.value(), k2.value()};
-  tile_partials<3>(v, red, part + (int64_t)blockIdx.x * 5);
+  tile_partials<3>(v, red, part + ti * 5);
 }
 
 // Segmented suffix sums of A (by tiles of positions): tile sums, then per
@@ -391,7 +458,9 @@ __global__ void __launch_bounds__(BT) k_big_var_rows(BigParams P, const uint32_t
 template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_tilesum(BigParams P, const CT* A1, const CT* A2, double* tsum) {
   __shared__ double red[(BT / WAVE) * 2];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   double a = 0.0, b = 0.0;
   const int64_t c0 = s.roff + t.start;
@@ -400,7 +469,7 @@ __global__ void __launch_bounds__(BT) k_big_tilesum(BigParams P, const CT* A1, c
     if (q0 + i < t.count) { a += (double)A1[c0 + q0 + i]; b += (double)A2[c0 + q0 + i]; }
   double v[2] = {a, b};
   block_sum<BT / WAVE, 2>(v, red);
-  if (threadIdx.x == 0) { tsum[2 * blockIdx.x] = v[0]; tsum[2 * blockIdx.x + 1] = v[1]; }
+  if (threadIdx.x == 0) { tsum[2 * ti] = v[0]; tsum[2 * ti + 1] = v[1]; }
 }
 
 __global__ void __launch_bounds__(256) k_big_segsuffix(BigParams P, double* tsum) {
@@ -421,7 +490,9 @@ __global__ void __launch_bounds__(256) k_big_segsuffix(BigParams P, double* tsum
 template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_tilesuffix(BigParams P, CT* A1, CT* A2, const double* tsum) {
   __shared__ double sc[BT / WAVE];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   const int64_t c0 = s.roff + t.start;
   const int q0 = threadIdx.x * BE;
@@ -430,7 +501,7 @@ __global__ void __launch_bounds__(BT) k_big_tilesuffix(BigParams P, CT* A1, CT* 
     double cs = 0.0;
     for (int i = 0; i < BE; ++i)
       if (q0 + i < t.count) cs += (double)A[c0 + q0 + i];
-    double run = block_excl_suffix<BT / WAVE>(cs, sc) + tsum[2 * blockIdx.x + arr];
+    double run = block_excl_suffix<BT / WAVE>(cs, sc) + tsum[2 * ti + arr];
     for (int i = BE - 1; i >= 0; --i) {
       if (q0 + i < t.count) {
         run += (double)A[c0 + q0 + i];
@@ -444,7 +515,9 @@ template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_psi(BigParams P, const CT* A1, const CT* A2, const CT* S,
                                                 const uint32_t* L1, const uint32_t* L2, double* part) {
   __shared__ double red[(BT / WAVE) * 2];
-  const BigTile t = P.tiles[blockIdx.x];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   const double dn = (double)s.n;
   double a = 0.0, b = 0.0;
@@ -458,7 +531,7 @@ __global__ void __launch_bounds__(BT) k_big_psi(BigParams P, const CT* A1, const
   }
   double v[2] = {a, b};
   block_sum<BT / WAVE, 2>(v, red);
-  if (threadIdx.x == 0) { part[(int64_t)blockIdx.x * 5 + 3] = v[0]; part[(int64_t)blockIdx.x * 5 + 4] = v[1]; }
+  if (threadIdx.x == 0) { part[ti * 5 + 3] = v[0]; part[ti * 5 + 4] = v[1]; }
 }
 
 __global__ void __launch_bounds__(256) k_big_finalize(BigParams P, const double* part, const NewtonState* st,
@@ -510,7 +583,7 @@ static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1
 hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, const void* y, int dtype_kw,
                     int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s) {
   if (P.nsegs == 0) return hipSuccess;
-  const unsigned nt = (unsigned)P.ntiles;
+  const unsigned nt = (unsigned)P.nslots;  // tile slots in XCD order
   hipLaunchKernelGGL(k_big_zero_flags, dim3(nblk(P.nsegs, 256)), dim3(256), 0, s, P);
   for (int margin = 0; margin < 2; ++margin) {
     const void* data = margin ? y : x;
@@ -540,10 +613,17 @@ hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, cons
     uint32_t* Em = margin ? B.E2 : B.E1;
     uint32_t* Lm = margin ? B.L2 : B.L1;
     uint32_t* R32 = margin ? R2out : R1out;
+    // the other ping-pong buffers are free after the last pass: R and group
+    // starts in sorted order for the staged subsets
+    uint32_t *RS = klo2, *LS = khi2;
     if (dtype_kw == 2)
-      hipLaunchKernelGGL((k_big_ranks<2>), dim3(nt), dim3(BT), 0, s, klo, khi, val, ties, P, Rm, Em, Lm, R32);
+      hipLaunchKernelGGL((k_big_ranks<2>), dim3(nt), dim3(BT), 0, s, klo, khi, val, ties, P, Rm, Em, Lm, R32, RS,
+                         LS);
     else
-      hipLaunchKernelGGL((k_big_ranks<1>), dim3(nt), dim3(BT), 0, s, klo, khi, val, ties, P, Rm, Em, Lm, R32);
+      hipLaunchKernelGGL((k_big_ranks<1>), dim3(nt), dim3(BT), 0, s, klo, khi, val, ties, P, Rm, Em, Lm, R32, RS,
+                         LS);
+    if (!R32 && P.nchunks > 0)
+      hipLaunchKernelGGL(k_big_unpermute, dim3((unsigned)P.nchunks), dim3(UT), 0, s, P, val, RS, LS, Rm, Em, Lm);
   }
   return hipGetLastError();
 }
@@ -551,7 +631,7 @@ hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, cons
 template <typename CT>
 static hipError_t big_solve_t(const BigParams& P, const BigBuffers& B, double tol, int max_iter, int fp64,
                               int* pending_host, hipStream_t s) {
-  const unsigned nt = (unsigned)P.ntiles;
+  const unsigned nt = (unsigned)P.nslots;  // tile slots in XCD order
   hipLaunchKernelGGL((k_big_start<CT>), dim3(nt), dim3(BT), 0, s, P, B.R1, B.R2, (CT*)B.LX, (CT*)B.LY, B.part);
   hipLaunchKernelGGL(k_big_start_update, dim3(1), dim3(256), 0, s, P, B.part, B.st, tol, B.pending);
   // Newton passes in blocks of 4; the host stops once every subset is done.
@@ -576,7 +656,7 @@ static hipError_t big_solve_t(const BigParams& P, const BigBuffers& B, double to
 template <typename CT>
 static hipError_t big_variance_t(const BigParams& P, const BigBuffers& B, const double* theta_in, int var_method,
                                  int mode, double* var_out, ResultOut* out, hipStream_t s) {
-  const unsigned nt = (unsigned)P.ntiles;
+  const unsigned nt = (unsigned)P.nslots;  // tile slots in XCD order
   hipLaunchKernelGGL((k_big_var_rows<CT>), dim3(nt), dim3(BT), 0, s, P, B.R1, B.R2, B.E1, B.E2, B.st, theta_in,
                      (CT*)B.A1, (CT*)B.A2, (CT*)B.S, B.part);
   hipLaunchKernelGGL((k_big_tilesum<CT>), dim3(nt), dim3(BT), 0, s, P, (const CT*)B.A1, (const CT*)B.A2, B.tsum);

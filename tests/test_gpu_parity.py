@@ -563,3 +563,79 @@ def test_fresh_handle_only_streaming_subsets():
     assert np.all(got["status"] == 0)
     for k in got:
         assert np.array_equal(got[k], ref[k], equal_nan=True), k
+
+
+@pytest.mark.parametrize("fam,th", [("frank", -10.0), ("frank", -1.0), ("frank", 0.01), ("frank", 1.0),
+                                    ("frank", 10.0), ("frank", 30.0), ("gaussian", -0.95), ("gaussian", 0.0),
+                                    ("gaussian", 0.95)])
+def test_adjoint_drives_newton_on_benchmark_settings(fam, th):
+    """Each setting of the 9 x 1e7-row workload, on 3 subsets of U[5000, 15000]
+    rows: the FP32c adjoint's score and Hessian through autograd against the
+    oracle's analytic per-row derivatives and against central differences
+    (h = 1e-4) of the FP64 log-likelihood and score; then a Newton iteration
+    driven only by the autograd derivatives reaches the FP64 batched fit's
+    estimate."""
+    import paper_1609_05530_amd as m
+    w = synth.config5(settings=[(fam, th)], n=30000, K=3)
+    off = w.offsets
+    R1, R2 = m.rank(dev(w.x, torch.float32), dev(w.y, torch.float32), off)
+    r1 = R1.cpu().numpy().astype(np.int64)
+    r2 = R2.cpu().numpy().astype(np.int64)
+    step = (-0.05 if th > 0 else 0.05) if fam == "gaussian" else 0.1 * max(1.0, abs(th))  # towards the inside
+    t0 = torch.tensor([th + step] * w.K, dtype=torch.float64, device="cuda", requires_grad=True)
+    ll = m.LogLik.apply(t0, R1, R2, off, fam, "fp32c")
+    (g,) = torch.autograd.grad(ll.sum(), t0, create_graph=True)
+    (h,) = torch.autograd.grad(g.sum(), t0)
+    g, h = g.detach().cpu().numpy(), h.cpu().numpy()
+    hfd = 1e-4
+    tp, tm = (t0.detach() + hfd), (t0.detach() - hfd)
+    lp = m.LogLik.apply(tp, R1, R2, off, fam, "fp64").cpu().numpy()
+    lm = m.LogLik.apply(tm, R1, R2, off, fam, "fp64").cpu().numpy()
+    sp = m.Score.apply(tp, R1, R2, off, fam, "fp64").cpu().numpy()
+    sm = m.Score.apply(tm, R1, R2, off, fam, "fp64").cpu().numpy()
+    for k in range(w.K):
+        a, b = off[k], off[k + 1]
+        n = b - a
+        u, omu = O.pobs_from_ranks(r1[a:b], n)
+        v, omv = O.pobs_from_ranks(r2[a:b], n)
+        d = O.logc_derivs(fam, th + step, u, omu, v, omv)
+        ss, sh = np.abs(d[:, 1]).sum(), np.abs(d[:, 2]).sum()
+        assert abs(g[k] - d[:, 1].sum()) <= 2e-5 * ss, (fam, th, k, g[k], d[:, 1].sum())
+        assert abs(h[k] - d[:, 2].sum()) <= 2e-5 * sh, (fam, th, k, h[k], d[:, 2].sum())
+        assert abs(g[k] - (lp[k] - lm[k]) / (2 * hfd)) <= 3e-5 * ss, (fam, th, k)
+        assert abs(h[k] - (sp[k] - sm[k]) / (2 * hfd)) <= 3e-5 * sh, (fam, th, k)
+    # Newton on the adjoint alone, with step halving while the adjoint's
+    # log-likelihood does not increase (the likelihood is not concave in
+    # theta everywhere: from 0.05 off, plain Newton can leave the Gaussian's
+    # range); small steps are taken whole (there the FP32-summed
+    # log-likelihood's rounding noise exceeds its change)
+    lo, hi = (-0.999, 0.999) if fam == "gaussian" else (-200.0, 200.0)
+    theta = t0.detach().clone()
+    for _ in range(12):
+        tt = theta.clone().requires_grad_(True)
+        ll = m.LogLik.apply(tt, R1, R2, off, fam, "fp32c")
+        (g,) = torch.autograd.grad(ll.sum(), tt, create_graph=True)
+        (h,) = torch.autograd.grad(g.sum(), tt)
+        g, h, l0 = g.detach(), h.detach(), ll.detach()
+        step = torch.where(h < 0, -g / h, torch.sign(g) * 0.05)
+        for _ in range(30):
+            cand = (theta + step).clamp(lo, hi)
+            lc = m.LogLik.apply(cand, R1, R2, off, fam, "fp32c")
+            small = step.abs() <= 1e-3 * (1.0 + theta.abs())
+            worse = (lc < l0 - 1e-9 * l0.abs()) & ~small
+            if not bool(worse.any()):
+                break
+            step = torch.where(worse, 0.5 * step, step)
+        theta = cand
+    # against the FP64 fit (which matches the oracle to 1e-12). Gaussian: the
+    # adjoint sums per-row FP32 scores where the fit sums normal-score
+    # squares; near rho = 0 the two meet the estimate through different
+    # nearly cancelling sums (2e-8 absolute measured), hence 5e-6 relative
+    # above |rho| = 1e-2 (5e-8 absolute below) instead of the fit's 1e-6.
+    fit = to_np(m.fit(dev(w.x, torch.float32), dev(w.y, torch.float32), off, fam, prec="fp64"))
+    rt, floor = (5e-6, 1e-2) if fam == "gaussian" else theta_tol("fp32c", fam)
+    got = theta.cpu().numpy()
+    rel = np.abs(got - fit["theta"]) / np.maximum(np.abs(fit["theta"]), floor)
+    print(f"[adjoint newton] {fam} {th:g}: max rel dtheta vs FP64 fit {rel.max():.2e}", flush=True)
+    assert np.all(fit["status"] == 0)
+    assert rel.max() <= rt, (fam, th, got, fit["theta"])
