@@ -109,13 +109,11 @@ int size_class(int64_t rows) {
 struct Layout {
   size_t subs, order_rank, order_fit, state, gofs, r1, r2, e1, e2, l1, l2, s;
   // streaming path (subsets above kResidentMaxRows)
-  size_t bsegs, btiles, bchunks, bxorder, bflags, bgsum, bst, bpending, bhist, bpart, btsum, brow32[12], brow64[5];
+  size_t bsegs, btiles, bxorder, bflags, bgsum, bst, bpending, bhist, bpart, btsum, brow32[12], brow64[5];
   size_t total;
 };
 
 int64_t max_tiles(int64_t n, int64_t K) { return n / kBigTile + K + 1; }
-// chunk slots: eight queues (one per XCD), each at most the chunk count
-int64_t max_chunks(int64_t n, int64_t K) { return 8 * (n / kBigChunk + K + 1); }
 
 Layout layout(int64_t n, int64_t K, int64_t G) {
   Layout L;
@@ -140,7 +138,6 @@ Layout layout(int64_t n, int64_t K, int64_t G) {
   const int64_t T = max_tiles(n, K);
   L.bsegs = take(sizeof(BigSeg) * (size_t)K);
   L.btiles = take(sizeof(BigTile) * (size_t)T);
-  L.bchunks = take(sizeof(BigTile) * (size_t)max_chunks(n, K));
   L.bxorder = take(sizeof(int64_t) * 8 * (size_t)T);
   L.bflags = take(sizeof(int32_t) * (size_t)K);
   L.bgsum = take(2 * sizeof(double) * (size_t)K);
@@ -169,7 +166,6 @@ struct Plan {
   std::vector<int64_t> gofs;
   std::vector<BigSeg> bsegs;
   std::vector<BigTile> btiles;
-  std::vector<BigTile> bchunks;
   std::vector<int64_t> bxorder;
 };
 
@@ -212,7 +208,6 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
   P.subs.resize((size_t)K);
   P.bsegs.clear();
   P.btiles.clear();
-  P.bchunks.clear();
   P.bxorder.clear();
   std::vector<int> cls((size_t)K);
   int64_t roff = 0;
@@ -245,35 +240,13 @@ int make_plan(const int64_t* offsets, int64_t K, const int32_t* fam_of_subset, P
       roff += rows;
     }
   }
-  // Tile slots, and row chunks for the sorted-to-row permutation, in XCD
-  // order: the tiles (chunks) of one subset then share an XCD's L2, which
-  // holds the subset's arrays they scatter into or all read.
+  // Tile slots in XCD order: the tiles of one subset then share an XCD's
+  // L2, which holds the subset's arrays they scatter into or all read.
   if (!P.bsegs.empty()) {
     std::vector<std::vector<int64_t>> items(P.bsegs.size());
     for (size_t g = 0; g < P.bsegs.size(); ++g)
       for (int32_t k = 0; k < P.bsegs[g].ntiles; ++k) items[g].push_back(P.bsegs[g].tile0 + k);
     P.bxorder = xcd_slots(items);
-    std::vector<BigTile> chunks;
-    std::vector<std::vector<int64_t>> citems(P.bsegs.size());
-    for (size_t g = 0; g < P.bsegs.size(); ++g) {
-      const BigSeg& b = P.bsegs[g];
-      if (b.n > kBigChunkMaxRows) continue;
-      for (int64_t st = 0; st < b.n; st += kBigChunk) {
-        BigTile t;
-        t.seg = (int32_t)g;
-        t.start = st;
-        t.count = (int32_t)std::min<int64_t>(kBigChunk, b.n - st);
-        citems[g].push_back((int64_t)chunks.size());
-        chunks.push_back(t);
-      }
-    }
-    if (!chunks.empty()) {
-      BigTile idle;
-      idle.seg = 0;
-      idle.start = 0;
-      idle.count = 0;
-      for (int64_t c : xcd_slots(citems)) P.bchunks.push_back(c < 0 ? idle : chunks[(size_t)c]);
-    }
   }
   std::vector<int32_t> ids;
   ids.reserve((size_t)K);
@@ -338,7 +311,6 @@ Carved carve(void* ws, const Layout& L) {
   std::memset(&c.big, 0, sizeof(c.big));
   c.big.segs = (const BigSeg*)(b + L.bsegs);
   c.big.tiles = (const BigTile*)(b + L.btiles);
-  c.big.chunks = (const BigTile*)(b + L.bchunks);
   c.big.xorder = (const int64_t*)(b + L.bxorder);
   c.big.flags = (int32_t*)(b + L.bflags);
   c.big.gsum = (double*)(b + L.bgsum);
@@ -371,9 +343,6 @@ int upload_tables(cpc_context* h, const Plan& P, const Carved& c, const int64_t*
     HIP_OK(hipMemcpyAsync((void*)c.big.segs, P.bsegs.data(), sizeof(BigSeg) * P.bsegs.size(), hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync((void*)c.big.tiles, P.btiles.data(), sizeof(BigTile) * P.btiles.size(),
                           hipMemcpyHostToDevice, s));
-    if (!P.bchunks.empty())
-      HIP_OK(hipMemcpyAsync((void*)c.big.chunks, P.bchunks.data(), sizeof(BigTile) * P.bchunks.size(),
-                            hipMemcpyHostToDevice, s));
     HIP_OK(hipMemcpyAsync((void*)c.big.xorder, P.bxorder.data(), sizeof(int64_t) * P.bxorder.size(),
                           hipMemcpyHostToDevice, s));
   }
@@ -386,7 +355,6 @@ int upload_tables(cpc_context* h, const Plan& P, const Carved& c, const int64_t*
 void set_big(Carved& c, const Plan& P, int64_t n_min) {
   c.big.nsegs = (int32_t)P.bsegs.size();
   c.big.ntiles = (int64_t)P.btiles.size();
-  c.big.nchunks = (int64_t)P.bchunks.size();
   c.big.nslots = (int64_t)P.bxorder.size();
   c.big.n_min = n_min;
 }

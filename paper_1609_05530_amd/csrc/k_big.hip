@@ -25,6 +25,7 @@ namespace cpc {
 constexpr int BT = 256;          // threads per tile workgroup
 constexpr int BE = 16;           // elements per thread
 constexpr int BTILE = BT * BE;   // rows per tile
+static_assert(BT == 256, "one thread per digit value in the scatter pass");
 
 // ---------------------------------------------------------------------------
 // Sort
@@ -103,13 +104,18 @@ __global__ void __launch_bounds__(256) k_big_scan(BigParams P, uint32_t* hist) {
 }
 
 // Stable scatter of one digit pass: tile-local stable rank by the LDS
-// multisplit, global destination from the scanned histograms.
+// multisplit, global destination from the scanned histograms. The tile is
+// first reordered by digit in LDS, so that consecutive lanes write
+// consecutive destinations (one contiguous run per digit and tile).
 template <int KW>
 __global__ void __launch_bounds__(BT) k_big_scatter(const uint32_t* klo, const uint32_t* khi, const uint32_t* val,
                                                     uint32_t* klo_o, uint32_t* khi_o, uint32_t* val_o, int word,
                                                     int shift, int pass, BigParams P, const uint32_t* hist) {
   __shared__ uint16_t cnt[(BT / WAVE) * 256];
   __shared__ uint32_t dtot[256 + 2 + 4];
+  __shared__ uint32_t gofs[256];  // global destination minus tile-local position, per digit
+  __shared__ uint32_t xk[BTILE], xv[BTILE];
+  __shared__ uint32_t xh[KW == 2 ? BTILE : 1];
   const int64_t ti = P.xorder[blockIdx.x];
   if (ti < 0) return;  // idle slot (uniform)
   const BigTile t = P.tiles[ti];
@@ -130,15 +136,26 @@ __global__ void __launch_bounds__(BT) k_big_scatter(const uint32_t* klo, const u
     d[j] = (((KW == 2 && word) ? hi[j] : lo[j]) >> shift) & 0xFFu;
   }
   lds_multisplit<BT, BE>(d, n, pass, cnt, dtot, dst);
+  gofs[threadIdx.x] = hist[ti * 256 + threadIdx.x] - dtot[threadIdx.x];  // BT == 256 digits
 #pragma unroll
   for (int j = 0; j < BE; ++j) {
     const int e = (w * BE + j) * WAVE + lane;
     if (e < n) {
-      const uint32_t g = hist[ti * 256 + d[j]] + (dst[j] - dtot[d[j]]);
-      klo_o[s.roff + g] = lo[j];
-      if (KW == 2) khi_o[s.roff + g] = hi[j];
-      val_o[s.roff + g] = v[j];
+      xk[dst[j]] = lo[j];
+      if (KW == 2) xh[dst[j]] = hi[j];
+      xv[dst[j]] = v[j];
     }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int i = threadIdx.x; i < n; i += BT) {
+    const uint32_t kl = xk[i];
+    const uint32_t kh = (KW == 2) ? xh[i] : 0u;
+    const uint32_t dg = (((KW == 2 && word) ? kh : kl) >> shift) & 0xFFu;
+    const int64_t g = s.roff + (int64_t)(gofs[dg] + (uint32_t)i);
+    klo_o[g] = kl;
+    if (KW == 2) khi_o[g] = kh;
+    val_o[g] = xv[i];
   }
 }
 
@@ -198,22 +215,26 @@ __global__ void __launch_bounds__(BT) k_big_ranks(const uint32_t* klo, const uin
   }
 }
 
-// Sorted order -> row order for one chunk of rows of one subset: the
-// workgroup reads the subset's sorted row indices (coalesced), keeps the
-// entries whose row falls in its chunk in LDS, and writes R, E (the sorted
-// position) and L for its rows contiguously. Replaces three scattered 4-byte
-// writes per row with reads that the chunks of a subset share through L2.
+// Sorted order -> row order for one tile of rows of a subset of at most
+// kBigChunkMaxRows rows: the workgroup reads the subset's sorted row indices
+// (coalesced) and keeps, in LDS, the sorted position of every row of its
+// tile; it then writes R, E (that position) and L for its rows contiguously,
+// R and L gathered from the sorted-order arrays. The tiles of a subset run on
+// one XCD at about the same time (slot order), so these reads are served by
+// its L2; this replaces three scattered 4-byte writes per row.
 constexpr int UT = 1024;
 __global__ void __launch_bounds__(UT) k_big_unpermute(BigParams P, const uint32_t* val, const uint32_t* RS,
                                                       const uint32_t* LS, uint32_t* R, uint32_t* Eo, uint32_t* Lo) {
-  __shared__ uint32_t lr[kBigChunk], le[kBigChunk], ll[kBigChunk];
-  const BigTile c = P.chunks[blockIdx.x];
-  if (c.count <= 0) return;  // idle slot (uniform)
-  const BigSeg s = P.segs[c.seg];
+  __shared__ uint32_t le[kBigTile];
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
+  const BigSeg s = P.segs[t.seg];
+  if (s.n > kBigChunkMaxRows) return;  // scattered directly by k_big_ranks
   const uint32_t* V = val + s.roff;
-  const uint32_t r0 = (uint32_t)c.start, cnt = (uint32_t)c.count;
+  const uint32_t r0 = (uint32_t)t.start, cnt = (uint32_t)t.count;
   const uint32_t n = (uint32_t)s.n;
-  constexpr int U = 4;  // loads in flight per thread
+  constexpr int U = 8;  // loads in flight per thread
   for (uint32_t base = 0; base < n; base += UT * U) {
     uint32_t rows[U];
 #pragma unroll
@@ -224,20 +245,19 @@ __global__ void __launch_bounds__(UT) k_big_unpermute(BigParams P, const uint32_
 #pragma unroll
     for (int k = 0; k < U; ++k) {
       const uint32_t p = base + k * UT + threadIdx.x;
-      const uint32_t d = rows[k] - r0;  // rows below the chunk wrap to large values
-      if (p < n && d < cnt) {
-        lr[d] = RS[s.roff + p];
-        le[d] = p;
-        ll[d] = LS[s.roff + p];
-      }
+      const uint32_t d = rows[k] - r0;  // rows below the tile wrap to large values
+      if (p < n && d < cnt) le[d] = p;
     }
   }
   __syncthreads();
   const int64_t o = s.roff + (int64_t)r0;
+  const uint32_t* RSs = RS + s.roff;
+  const uint32_t* LSs = LS + s.roff;
   for (uint32_t i = threadIdx.x; i < cnt; i += UT) {
-    R[o + i] = lr[i];
-    Eo[o + i] = le[i];
-    Lo[o + i] = ll[i];
+    const uint32_t p = le[i];
+    R[o + i] = RSs[p];
+    Eo[o + i] = p;
+    Lo[o + i] = LSs[p];
   }
 }
 
@@ -454,7 +474,8 @@ __global__ void __launch_bounds__(BT) k_big_var_rows(BigParams P, const uint32_t
 }
 
 // Segmented suffix sums of A (by tiles of positions): tile sums, then per
-// subset a suffix over tiles, then in-tile suffixes plus the carry.
+// subset a suffix over tiles, then in-tile suffixes plus the carry. Both tile
+// kernels read their tile coalesced.
 template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_tilesum(BigParams P, const CT* A1, const CT* A2, double* tsum) {
   __shared__ double red[(BT / WAVE) * 2];
@@ -464,9 +485,11 @@ __global__ void __launch_bounds__(BT) k_big_tilesum(BigParams P, const CT* A1, c
   const BigSeg s = P.segs[t.seg];
   double a = 0.0, b = 0.0;
   const int64_t c0 = s.roff + t.start;
-  const int q0 = threadIdx.x * BE;
-  for (int i = 0; i < BE; ++i)
-    if (q0 + i < t.count) { a += (double)A1[c0 + q0 + i]; b += (double)A2[c0 + q0 + i]; }
+#pragma unroll 4
+  for (int q = threadIdx.x; q < t.count; q += BT) {
+    a += (double)A1[c0 + q];
+    b += (double)A2[c0 + q];
+  }
   double v[2] = {a, b};
   block_sum<BT / WAVE, 2>(v, red);
   if (threadIdx.x == 0) { tsum[2 * ti] = v[0]; tsum[2 * ti + 1] = v[1]; }
@@ -487,27 +510,45 @@ __global__ void __launch_bounds__(256) k_big_segsuffix(BigParams P, double* tsum
   }
 }
 
+// In-tile suffix sums: the tile is staged through LDS (coalesced load and
+// store; one pad entry per 16 so that each thread's run of BE entries is
+// conflict-free), each thread sums its own run in double.
 template <typename CT>
 __global__ void __launch_bounds__(BT) k_big_tilesuffix(BigParams P, CT* A1, CT* A2, const double* tsum) {
   __shared__ double sc[BT / WAVE];
+  __shared__ CT lt[BTILE + BTILE / 16];
   const int64_t ti = P.xorder[blockIdx.x];
   if (ti < 0) return;  // idle slot (uniform)
   const BigTile t = P.tiles[ti];
   const BigSeg s = P.segs[t.seg];
   const int64_t c0 = s.roff + t.start;
   const int q0 = threadIdx.x * BE;
+  auto pad = [](int q) { return q + (q >> 4); };
   for (int arr = 0; arr < 2; ++arr) {
     CT* A = arr ? A2 : A1;
+#pragma unroll
+    for (int k = 0; k < BE; ++k) {
+      const int q = k * BT + threadIdx.x;
+      if (q < t.count) lt[pad(q)] = A[c0 + q];
+    }
+    __syncthreads();
     double cs = 0.0;
     for (int i = 0; i < BE; ++i)
-      if (q0 + i < t.count) cs += (double)A[c0 + q0 + i];
+      if (q0 + i < t.count) cs += (double)lt[pad(q0 + i)];
     double run = block_excl_suffix<BT / WAVE>(cs, sc) + tsum[2 * ti + arr];
     for (int i = BE - 1; i >= 0; --i) {
       if (q0 + i < t.count) {
-        run += (double)A[c0 + q0 + i];
-        A[c0 + q0 + i] = (CT)run;
+        run += (double)lt[pad(q0 + i)];
+        lt[pad(q0 + i)] = (CT)run;
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BE; ++k) {
+      const int q = k * BT + threadIdx.x;
+      if (q < t.count) A[c0 + q] = lt[pad(q)];
+    }
+    __syncthreads();  // lt is refilled for the second array
   }
 }
 
@@ -622,8 +663,7 @@ hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, cons
     else
       hipLaunchKernelGGL((k_big_ranks<1>), dim3(nt), dim3(BT), 0, s, klo, khi, val, ties, P, Rm, Em, Lm, R32, RS,
                          LS);
-    if (!R32 && P.nchunks > 0)
-      hipLaunchKernelGGL(k_big_unpermute, dim3((unsigned)P.nchunks), dim3(UT), 0, s, P, val, RS, LS, Rm, Em, Lm);
+    if (!R32) hipLaunchKernelGGL(k_big_unpermute, dim3(nt), dim3(UT), 0, s, P, val, RS, LS, Rm, Em, Lm);
   }
   return hipGetLastError();
 }

@@ -123,10 +123,6 @@ struct BigParams {
   int64_t n_min;
   int32_t* flags;  // per subset: bit 0 non-finite data, bit 1 a margin with one value
   double* gsum;    // per subset: Gaussian S+, S-
-  // row chunks of the subsets of at most kBigChunkMaxRows rows, for the
-  // LDS-staged permutation from sorted to row order (count 0: an idle slot)
-  const BigTile* chunks;
-  int64_t nchunks;
   // tile launch slots: block b runs tile xorder[b] (-1: idle). Blocks go to
   // the 8 XCDs in turn, so slot order puts a subset's tiles on one XCD (its
   // L2 then holds the subset's arrays); a subset larger than an XCD's share
@@ -151,12 +147,10 @@ hipError_t big_solve(const BigParams& P, const BigBuffers& B, double tol, int ma
 hipError_t big_variance(const BigParams& P, const BigBuffers& B, int fp64, const double* theta_in, int var_method,
                         int mode, double* var_out, ResultOut* out, hipStream_t s);
 constexpr int kBigTile = 4096;
-// Rows per chunk of the sorted-to-row permutation (three u32 arrays in LDS),
-// and the largest subset that takes it: each chunk reads its whole subset's
-// sorted row indices, so the work grows as rows^2 / kBigChunk; larger subsets
-// scatter to row order directly.
-constexpr int kBigChunk = 12288;
-constexpr int64_t kBigChunkMaxRows = 1 << 18;
+// Largest subset whose sorted-to-row permutation is staged through LDS tile
+// by tile: each tile reads its whole subset's sorted row indices, so the work
+// grows as rows^2 / kBigTile; larger subsets scatter to row order directly.
+constexpr int64_t kBigChunkMaxRows = 1 << 17;
 
 // Adjoint of eq. (13): per-subset sums of l, dl/dtheta, d2l/dtheta2.
 hipError_t launch_eval_wg(const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t K, int fam,
