@@ -43,7 +43,7 @@ PEAK_HBM = 8.0e12                       # bytes/s
 RANK_BYTES_PER_ROW = 4 + 4 + 2 + 2
 # the rank kernel's sources (body, launch shapes and shape tables)
 RANK_SOURCES = ["paper_1609_05530_amd/csrc/rank_wg.h", "paper_1609_05530_amd/csrc/block_rank.h",
-                "paper_1609_05530_amd/csrc/k_rank.hip", "paper_1609_05530_amd/csrc/kernels.h"]
+                "paper_1609_05530_amd/csrc/k_rank.hip", "paper_1609_05530_amd/csrc/rank_shapes.h"]
 
 
 def parse():
