@@ -107,7 +107,7 @@ int size_class(int64_t rows) {
 
 // Workspace layout shared by all entry points.
 struct Layout {
-  size_t subs, order_rank, order_fit, state, gofs, r1, r2, e1, e2, l1, l2, s;
+  size_t subs, order_rank, order_fit, state, gofs, r1, r2, e1, e2, l1, l2, s, g;
   // streaming path (subsets above kResidentMaxRows)
   size_t bsegs, btiles, bxorder, bflags, bgsum, bst, bpending, bhist, bpart, btsum, brow32[12], brow64[5];
   size_t total;
@@ -135,6 +135,7 @@ Layout layout(int64_t n, int64_t K, int64_t G) {
   L.l1 = take(2 * (size_t)n);
   L.l2 = take(2 * (size_t)n);
   L.s = take(8 * (size_t)n);
+  L.g = take(8 * (size_t)n);
   const int64_t T = max_tiles(n, K);
   L.bsegs = take(sizeof(BigSeg) * (size_t)K);
   L.btiles = take(sizeof(BigTile) * (size_t)T);
@@ -308,6 +309,7 @@ Carved carve(void* ws, const Layout& L) {
   c.rows.L1 = (uint16_t*)(b + L.l1);
   c.rows.L2 = (uint16_t*)(b + L.l2);
   c.rows.S = (void*)(b + L.s);
+  c.rows.G = (void*)(b + L.g);
   std::memset(&c.big, 0, sizeof(c.big));
   c.big.segs = (const BigSeg*)(b + L.bsegs);
   c.big.tiles = (const BigTile*)(b + L.btiles);

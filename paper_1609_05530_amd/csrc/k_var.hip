@@ -45,11 +45,11 @@ __device__ __forceinline__ void lds_suffix_sum(CT* A, int n, double* scratch) {
   __syncthreads();
 }
 
-template <int T, int CAP, typename CT, int FAM>
-__global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
+template <int T, int CAP, typename CT, int FAM, bool ONE = false, int MINW = 1>
+__global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   constexpr int W = T / WAVE;
   constexpr int E = CAP / T;
-  constexpr bool TWO = 2 * sizeof(CT) * padded(CAP) <= 144 * 1024;
+  constexpr bool TWO = !ONE && 2 * sizeof(CT) * padded(CAP) <= 144 * 1024;
   __shared__ CT A1[padded(CAP)];
   __shared__ CT A2[TWO ? padded(CAP) : 1];
   __shared__ double red[W * 5];
@@ -114,9 +114,6 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
     }
     l = (CT)lr; s = (CT)sr; g1 = (CT)g1r; g2 = (CT)g2r;
   };
-  auto row_eval_t = [&](auto rt_tag, auto form_tag, int i, CT& l, CT& s, CT& g1, CT& g2) {
-    row_eval_ab(rt_tag, form_tag, R1[i], R2[i], l, s, g1, g2);
-  };
 
   RowSum<CT> kl, ksc, ks2;
   double psum = 0.0, psq = 0.0;
@@ -168,22 +165,33 @@ __global__ void __launch_bounds__(T) k_var_wg(VarParams P) {
         }
       }
     } else {
-      for (int i = tid; i < n; i += T) {
-        CT l, s, g1, g2;
-        row_eval_t(RT{}, FT{}, i, l, s, g1, g2);
-        kl.add(l); ksc.add(s); ks2.add(s * s);
-        A1[pidx(E1[i])] = g1;
-        S[i] = s;
+      // One suffix array in LDS: g2 waits in the workspace (row order) while
+      // the u-order suffix sums are formed and read.
+      CT* G2 = (CT*)P.rows.G + o;
+      {
+        const int last = n - 1;
+        int i1 = min(tid + T, last);
+        const int i0 = min(tid, last);
+        uint32_t r0 = (uint32_t)R1[i0] | ((uint32_t)R2[i0] << 16), e0 = E1[i0];
+        uint32_t r1 = (uint32_t)R1[i1] | ((uint32_t)R2[i1] << 16), e1 = E1[i1];
+#pragma unroll 1
+        for (int i = tid; i < n; i += T) {
+          const int i2 = min(i + 2 * T, last);
+          const uint32_t r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16), e2 = E1[i2];
+          CT l, s, g1, g2;
+          row_eval_ab(RT{}, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
+          kl.add(l); ksc.add(s); ks2.add(s * s);
+          A1[pidx((int)e0)] = g1;
+          S[i] = s;
+          G2[i] = g2;
+          r0 = r1; e0 = e1; r1 = r2; e1 = e2;
+        }
       }
       __syncthreads();
       lds_suffix_sum<T, E, CT>(A1, n, red);
       for (int i = tid; i < n; i += T) S[i] = (CT)((double)S[i] + (double)A1[pidx(L1[i])] * idn);
       __syncthreads();
-      for (int i = tid; i < n; i += T) {
-        CT l, s, g1, g2;
-        row_eval_t(RT{}, FT{}, i, l, s, g1, g2);
-        A1[pidx(E2[i])] = g2;
-      }
+      for (int i = tid; i < n; i += T) A1[pidx(E2[i])] = G2[i];
       __syncthreads();
       lds_suffix_sum<T, E, CT>(A1, n, red);
       for (int i = tid; i < n; i += T) {

@@ -34,6 +34,7 @@ struct RowArrays {
   uint16_t *E1, *E2;  // sorted positions
   uint16_t *L1, *L2;  // start of the row's tie group in sorted order
   void* S;            // per-row score scratch (row arithmetic type)
+  void* G;            // per-row d2l/dtheta dv scratch (row arithmetic type)
 };
 
 struct RankParams {

@@ -328,6 +328,25 @@ def test_big_fit_parity(fam, th, prec, storage):
     compare(res, sub, comb, prec, fam, f"big {fam} {th} {prec} {storage}")
 
 
+@pytest.mark.parametrize("fam", ["frank", "gumbel"])
+def test_big_ties_fit_and_variance(fam):
+    """Heavily tied margins in subsets of the streaming path, on both of its
+    sorted-to-row permutations (staged through LDS up to 2^17 rows, scattered
+    directly above): estimates, variances (the tie-group starts enter the
+    variance's suffix sums) and log-likelihoods against the oracle, FP64."""
+    sizes = np.array([20000, 45000, 140000])
+    n = int(sizes.sum())
+    x, y = synth.copula_pairs(fam, 3.0, n, 77)
+    x = np.round(x * 8) / 8
+    y = np.round(y * 4) / 4
+    off = synth.offsets_from_sizes(sizes)
+    sub, comb = O.fit(x, y, off, fam, nthreads=0)
+    res = to_np(cpc().fit(dev(x, torch.float64), dev(y, torch.float64), off, fam, prec="fp64"))
+    compare(res, sub, comb, "fp64", fam, f"big ties {fam}")
+    res32 = to_np(cpc().fit(dev(x, torch.float32), dev(y, torch.float32), off, fam, prec="fp32c"))
+    compare(res32, sub, comb, "fp32c", fam, f"big ties {fam} fp32c")
+
+
 def test_big_statuses():
     z = np.arange(20000, dtype=np.float64)
     rng = np.random.default_rng(4)
