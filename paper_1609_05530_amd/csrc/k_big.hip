@@ -264,9 +264,9 @@ __global__ void __launch_bounds__(UT) k_big_unpermute(BigParams P, const uint32_
 // ---------------------------------------------------------------------------
 // Per-tile partial sums; per-subset reductions in tile order.
 
-template <int NV>
+template <int NV, int T = BT>
 __device__ __forceinline__ void tile_partials(double (&v)[NV], double* red, double* out) {
-  block_sum<BT / WAVE, NV>(v, red);
+  block_sum<T / WAVE, NV>(v, red);
   if (threadIdx.x == 0)
     for (int k = 0; k < NV; ++k) out[k] = v[k];
 }
@@ -552,10 +552,13 @@ __global__ void __launch_bounds__(BT) k_big_tilesuffix(BigParams P, CT* A1, CT* 
   }
 }
 
+// Wide workgroups (VT threads per tile): fewer tiles in flight per XCD, so
+// that the suffix arrays of the subsets being read stay in its L2.
+constexpr int VT = 1024;
 template <typename CT>
-__global__ void __launch_bounds__(BT) k_big_psi(BigParams P, const CT* A1, const CT* A2, const CT* S,
+__global__ void __launch_bounds__(VT) k_big_psi(BigParams P, const CT* A1, const CT* A2, const CT* S,
                                                 const uint32_t* L1, const uint32_t* L2, double* part) {
-  __shared__ double red[(BT / WAVE) * 2];
+  __shared__ double red[(VT / WAVE) * 2];
   const int64_t ti = P.xorder[blockIdx.x];
   if (ti < 0) return;  // idle slot (uniform)
   const BigTile t = P.tiles[ti];
@@ -563,7 +566,7 @@ __global__ void __launch_bounds__(BT) k_big_psi(BigParams P, const CT* A1, const
   const double dn = (double)s.n;
   double a = 0.0, b = 0.0;
   if (P.flags[t.seg] == 0) {
-    for (int i = threadIdx.x; i < t.count; i += BT) {
+    for (int i = threadIdx.x; i < t.count; i += VT) {
       const int64_t q = s.roff + t.start + i;
       const double psi = (double)S[q] + ((double)A1[s.roff + L1[q]] + (double)A2[s.roff + L2[q]]) / dn;
       a += psi;
@@ -571,7 +574,7 @@ __global__ void __launch_bounds__(BT) k_big_psi(BigParams P, const CT* A1, const
     }
   }
   double v[2] = {a, b};
-  block_sum<BT / WAVE, 2>(v, red);
+  block_sum<VT / WAVE, 2>(v, red);
   if (threadIdx.x == 0) { part[ti * 5 + 3] = v[0]; part[ti * 5 + 4] = v[1]; }
 }
 
@@ -702,7 +705,7 @@ static hipError_t big_variance_t(const BigParams& P, const BigBuffers& B, const 
   hipLaunchKernelGGL((k_big_tilesum<CT>), dim3(nt), dim3(BT), 0, s, P, (const CT*)B.A1, (const CT*)B.A2, B.tsum);
   hipLaunchKernelGGL(k_big_segsuffix, dim3(nblk(P.nsegs, 256)), dim3(256), 0, s, P, B.tsum);
   hipLaunchKernelGGL((k_big_tilesuffix<CT>), dim3(nt), dim3(BT), 0, s, P, (CT*)B.A1, (CT*)B.A2, B.tsum);
-  hipLaunchKernelGGL((k_big_psi<CT>), dim3(nt), dim3(BT), 0, s, P, (const CT*)B.A1, (const CT*)B.A2, (const CT*)B.S,
+  hipLaunchKernelGGL((k_big_psi<CT>), dim3(nt), dim3(VT), 0, s, P, (const CT*)B.A1, (const CT*)B.A2, (const CT*)B.S,
                      B.L1, B.L2, B.part);
   hipLaunchKernelGGL(k_big_finalize, dim3(nblk(P.nsegs, 256)), dim3(256), 0, s, P, B.part, B.st, var_method, mode,
                      var_out, out);

@@ -93,8 +93,11 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
   __syncthreads();
 
   if constexpr (FAM == FAM_GAUSSIAN) {
-    // z in double for near-perfect dependence (S- then needs the digits)
+    // z in double for near-perfect dependence (S- then needs the digits).
+    // FP32 rows leave their normal scores in the workspace for the variance
+    // kernel (which otherwise evaluates the same two quantiles per row again).
     const bool zd = sizeof(CT) == 4 && fabs(bc[0]) > 0.98;
+    float2* ZC = (float2*)P.rows.G + sd.begin;
     double v[2];
     if (zd) {
       KSum<double> kp, km;
@@ -104,6 +107,9 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
         gauss_z<double>(r & 0xFFFFu, r >> 16, twon1, z1, z2);
         kp.add((z1 + z2) * (z1 + z2));
         km.add((z1 - z2) * (z1 - z2));
+        float f1, f2;
+        gauss_z<float>(r & 0xFFFFu, r >> 16, twon1, f1, f2);
+        ZC[i] = make_float2(f1, f2);
       }
       v[0] = kp.value();
       v[1] = km.value();
@@ -115,6 +121,7 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
         gauss_z<CT>(r & 0xFFFFu, r >> 16, twon1, z1, z2);
         kp.add((z1 + z2) * (z1 + z2));
         km.add((z1 - z2) * (z1 - z2));
+        if constexpr (sizeof(CT) == 4) ZC[i] = make_float2(z1, z2);
       }
       v[0] = kp.value();
       v[1] = km.value();
