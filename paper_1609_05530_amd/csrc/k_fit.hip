@@ -78,7 +78,12 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
     sacc += (i < n) ? term : 0ll;
     if (i < n) {
       if constexpr (SM::GC) {
-        gumbel_lxy<CT>(a, b, twon1, inv, sm.lx[i], sm.ly[i]);
+        CT lx, ly;
+        gumbel_lxy<CT>(a, b, twon1, inv, lx, ly);
+        sm.lx[i] = lx;
+        sm.ly[i] = ly;
+        // FP32 rows: also left in the workspace for the variance kernel
+        if constexpr (sizeof(CT) == 4) ((float2*)P.rows.G + sd.begin)[i] = make_float2(lx, ly);
       } else {
         sm.rr[i] = rab[k];
       }

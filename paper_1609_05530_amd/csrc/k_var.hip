@@ -121,9 +121,10 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   auto rows = [&](auto rt_tag, auto form_tag) {
     using RT = decltype(rt_tag);
     using FT = decltype(form_tag);
-    // Gaussian FP32 rows after the fit: the normal scores the fit kernel left
-    // in the workspace (its rows and these use the same FP32 quantiles)
-    constexpr bool ZFAM = FAM == FAM_GAUSSIAN && std::is_same<RT, float>::value && sizeof(CT) == 4;
+    // FP32 rows after the fit: the theta-free per-row terms the fit kernel
+    // left in the workspace (Gaussian normal scores; Gumbel log(-log u),
+    // log(-log v)), computed there by the same FP32 code
+    constexpr bool ZFAM = FAM != FAM_FRANK && std::is_same<RT, float>::value && sizeof(CT) == 4;
     const bool zcache = ZFAM && P.mode == MODE_FIT;
     if constexpr (TWO && ZFAM) {
       if (zcache) {
@@ -132,18 +133,28 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
         const int i0 = min(tid, last), i1 = min(tid + T, last);
         float2 z0 = ZC[i0], z1 = ZC[i1];
         uint32_t q0 = (uint32_t)E1[i0] | ((uint32_t)E2[i0] << 16), q1 = (uint32_t)E1[i1] | ((uint32_t)E2[i1] << 16);
+        uint32_t r0 = 0u, r1 = 0u;
+        if constexpr (FAM == FAM_GUMBEL) {
+          r0 = (uint32_t)R1[i0] | ((uint32_t)R2[i0] << 16);
+          r1 = (uint32_t)R1[i1] | ((uint32_t)R2[i1] << 16);
+        }
 #pragma unroll 1
         for (int i = tid; i < n; i += T) {
           const int i2 = min(i + 2 * T, last);
           const float2 z2 = ZC[i2];
           const uint32_t q2 = (uint32_t)E1[i2] | ((uint32_t)E2[i2] << 16);
+          uint32_t r2 = 0u;
+          if constexpr (FAM == FAM_GUMBEL) r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16);
           CT l, s, g1, g2;
-          gauss_rfull<CT>(c, z0.x, z0.y, l, s, g1, g2);
+          if constexpr (FAM == FAM_GUMBEL)
+            gumbel_rfull<CT>(c, r0 & 0xFFFFu, r0 >> 16, twon1, inv, z0.x, z0.y, l, s, g1, g2);
+          else
+            gauss_rfull<CT>(c, z0.x, z0.y, l, s, g1, g2);
           kl.add(l); ksc.add(s); ks2.add(s * s);
           A1[pidx((int)(q0 & 0xFFFFu))] = g1;
           A2[pidx((int)(q0 >> 16))] = g2;
           S[i] = s;
-          z0 = z1; q0 = q1; z1 = z2; q1 = q2;
+          z0 = z1; q0 = q1; z1 = z2; q1 = q2; r0 = r1; r1 = r2;
         }
       }
     }
