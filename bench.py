@@ -36,7 +36,10 @@ if ROOT not in sys.path:
 #   Gumbel:                exp x2, log x1, rcp x2      -> 20 + 40
 #   Gaussian (one pass):   AS 241 x2 (rcp + ~10 FMA)  -> 8 + 23
 SLOTS_PER_ROW_PASS = {"frank": 46.0, "gumbel": 60.0, "gaussian": 31.0}
-PEAK_LANE_SLOTS = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock (non-packed FP32 VALU)
+# FP32 vector peak 157.3 TFLOP/s = 78.6 T FMA lane-operations/s (256 CUs x 128
+# FMA lanes per clock x 2.4 GHz); the issue probe (libcpc_probe.so) sustains
+# most of it with ordinary (non-packed) FP32 instructions.
+PEAK_LANE_SLOTS = 256 * 128 * 2.4e9
 PEAK_HBM = 8.0e12                       # bytes/s
 # Algorithmic HBM bytes per row of the rank step: read x, y (FP32) and write
 # the two u16 doubled ranks.
@@ -69,6 +72,29 @@ def rank_source_hash() -> str:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def valu_probe():
+    """Measured lane operations per second of FP32 FMA and of the FP32
+    transcendental instructions (libcpc_probe.so), and each transcendental's
+    cost in FMA issue slots; None if the probe library is missing."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1609_05530_amd", "libcpc_probe.so")
+    if not os.path.exists(path):
+        return None
+    L = ctypes.CDLL(path)
+    L.cpc_probe_valu.restype = ctypes.c_int
+    L.cpc_probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_float)]
+    rates = {}
+    for op, name in enumerate(("fma", "exp2", "log2", "rcp", "sqrt")):
+        r, ms = ctypes.c_double(), ctypes.c_float()
+        if L.cpc_probe_valu(0, op, 2048, ctypes.byref(r), ctypes.byref(ms)) != 0:
+            return None
+        rates[name] = r.value
+    return {"lane_ops_per_s": {k: v for k, v in rates.items()},
+            "slots_per_op": {k: rates["fma"] / v for k, v in rates.items() if k != "fma"},
+            "fma_vs_peak": rates["fma"] / PEAK_LANE_SLOTS}
 
 
 def measured_rank_traffic():
@@ -221,6 +247,9 @@ def main():
             "traffic": None,
         },
     }
+
+    if not a.profile:
+        line["valu_probe"] = valu_probe()
 
     if not a.profile and not a.no_fp64_compare and a.prec == "fp32c":
         step64, out64 = make_step("fp64")

@@ -1,7 +1,8 @@
 """Builds libcpc.so (the HIP kernels + C ABI) for gfx950, in-tree.
 
 Also builds libcpc_hostmath.so, a host-only compilation of the kernels'
-per-row arithmetic used by CPU unit tests.
+per-row arithmetic used by CPU unit tests, and libcpc_probe.so, the VALU
+issue-rate probe (include/cpc_probe.h) that bench.py runs.
 
 Usage: python -m paper_1609_05530_amd.build [-v]
 """
@@ -20,6 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcpc.so")
 HOSTMATH = os.path.join(HERE, "libcpc_hostmath.so")
+PROBE = os.path.join(HERE, "libcpc_probe.so")
 
 ARCH = "gfx950"
 SOURCES = ["cpc_api.cpp", "k_rank.hip", "k_fit.hip", "k_var.hip", "k_big.hip", "k_eval.hip", "k_combine.hip"]
@@ -68,6 +70,9 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     tmp = HOSTMATH + ".tmp"
     _run([hipcc(), *COMMON, "-shared", "-o", tmp, os.path.join(CSRC, "host_math_shim.hip")], verbose)
     os.replace(tmp, HOSTMATH)
+    tmp = PROBE + ".tmp"
+    _run([hipcc(), *COMMON, "-shared", "-o", tmp, os.path.join(CSRC, "probe_valu.hip")], verbose)
+    os.replace(tmp, PROBE)
     return LIB
 
 

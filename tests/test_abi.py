@@ -61,3 +61,20 @@ def test_errors_before_any_device_call(L):
         assert len(L.cpc_strerror(code)) > 0
     h = ctypes.c_void_p()
     assert L.cpc_create(0, None) == -1  # CPC_E_NULL
+
+
+PROBE_HEADER = os.path.join(ROOT, "include", "cpc_probe.h")
+
+
+def test_probe_library_exports_its_header():
+    text = re.sub(r"/\*.*?\*/", "", open(PROBE_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(cpc_probe_[a-z_]+)\s*\(", text)))
+    assert names == ["cpc_probe_valu"]
+    P = ctypes.CDLL(os.path.join(ROOT, "paper_1609_05530_amd", "libcpc_probe.so"))
+    for name in names:
+        assert hasattr(P, name), name
+    P.cpc_probe_valu.restype = ctypes.c_int
+    r, ms = ctypes.c_double(), ctypes.c_float()
+    # argument checks come before any device call
+    assert P.cpc_probe_valu(0, 7, 16, ctypes.byref(r), ctypes.byref(ms)) == -1
+    assert P.cpc_probe_valu(0, 0, 0, ctypes.byref(r), ctypes.byref(ms)) == -1
