@@ -1,6 +1,6 @@
-// lds_sort.h — workgroup-local stable LSD radix sort in LDS and the tie-group
-// bookkeeping used to turn sorted order into the doubled ranks of eq. (12)
-// of arXiv:1609.05530 (average ranks for ties, or ties broken by row order).
+// lds_sort.h — one stable 8-bit counting pass of a workgroup's elements in
+// LDS (a ballot multisplit), the tile step of the streaming path's global
+// radix sort behind the ranks of eq. (12) of arXiv:1609.05530.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,29 +8,6 @@
 #include "cpc_device.h"
 
 namespace cpc {
-
-// Group start (first sorted position with the same key) and group end (one
-// past the last) of sorted position e, from a bitmask with a bit per sorted
-// position that marks the first element of each group (and every position
-// >= n). Position 0 is always a group start.
-__device__ __forceinline__ int group_lb(const uint32_t* heads, int e) {
-  int wi = e >> 5;
-  const int b = e & 31;
-  uint32_t m = heads[wi] & (0xFFFFFFFFu >> (31 - b));
-  while (m == 0u) m = heads[--wi];
-  return wi * 32 + 31 - __clz((int)m);
-}
-__device__ __forceinline__ int group_ub(const uint32_t* heads, int e, int n, int nwords) {
-  int wi = e >> 5;
-  const int b = e & 31;
-  uint32_t m = (b == 31) ? 0u : (heads[wi] & (0xFFFFFFFFu << (b + 1)));
-  while (m == 0u) {
-    if (++wi >= nwords) return n;
-    m = heads[wi];
-  }
-  const int ub = wi * 32 + __ffs((int)m) - 1;
-  return ub < n ? ub : n;
-}
 
 // One stable counting pass over the digits d[j] of the elements held in
 // wave-striped order (element e = (w*E + j)*64 + lane; only e < n take
@@ -108,66 +85,6 @@ __device__ __forceinline__ void lds_multisplit(const uint32_t (&d)[E], int n, in
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < E; ++j) dst[j] += dtot[d[j]] + cnt[w * 256 + d[j]];
-}
-
-// Stable LSD radix sort of up to CAP = T*E keys held in registers in
-// wave-striped order. Only e < n take part. The payload (the element's
-// original index) does not occupy registers: it moves between two LDS
-// buffers, starting as the identity in vb0. Returns which of the two buffers
-// holds the final payload (vb[k][e] = original index of sorted position e).
-// 8-bit digits, least significant first; a pass in which every element has
-// the same digit moves nothing and is skipped (uniformly).
-template <int T, int E, int KW>
-__device__ __forceinline__ int lds_radix_sort(uint32_t (&klo)[E], uint32_t (&khi)[E], int n,
-                                              uint32_t* buf, uint16_t* vb0, uint16_t* vb1,
-                                              uint16_t* cnt, uint32_t* dtot) {
-  const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-  for (int e = tid; e < n; e += T) vb0[e] = (uint16_t)e;
-  int cur = 0;
-  uint32_t dst[E];
-#pragma unroll 1
-  for (int pass = 0; pass < 4 * KW; ++pass) {
-    const int word = pass >> 2;
-    const int shift = (pass & 3) * 8;
-    uint32_t d[E];
-#pragma unroll
-    for (int j = 0; j < E; ++j) d[j] = (((KW == 2 && word) ? khi[j] : klo[j]) >> shift) & 0xFFu;
-    lds_multisplit<T, E>(d, n, pass, cnt, dtot, dst);
-    if (dtot[256 + (pass & 1)] != 0u) continue;  // identity permutation: nothing moves
-    const uint16_t* vs = cur ? vb1 : vb0;
-    uint16_t* vd = cur ? vb0 : vb1;
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int e = (w * E + j) * WAVE + lane;
-      if (e < n) {
-        buf[dst[j]] = klo[j];
-        vd[dst[j]] = vs[e];
-      }
-    }
-    cur ^= 1;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int e = (w * E + j) * WAVE + lane;
-      if (e < n) klo[j] = buf[e];
-    }
-    __syncthreads();
-    if (KW == 2) {
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int e = (w * E + j) * WAVE + lane;
-        if (e < n) buf[dst[j]] = khi[j];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < E; ++j) {
-        const int e = (w * E + j) * WAVE + lane;
-        if (e < n) khi[j] = buf[e];
-      }
-      __syncthreads();
-    }
-  }
-  return cur;
 }
 
 }  // namespace cpc
