@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(UT) k_big_unpermute(BigParams P, const uint32_
   const uint32_t* RSs = RS + s.roff;
   const uint32_t* LSs = LS + s.roff;
   for (uint32_t i = threadIdx.x; i < cnt; i += UT) {
-    const uint32_t p = le[i];
+    const uint32_t p = min(le[i], n - 1u);  // every entry is set (val is a permutation); the clamp keeps reads in bounds regardless
     R[o + i] = RSs[p];
     Eo[o + i] = p;
     Lo[o + i] = LSs[p];
