@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch eagerly instead of replaying a hipGraph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=3, help="subsets per setting in the CPU-baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=64, help="subsets per setting in the CPU-baseline sample")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler (no oracle, no checks)")
     return ap.parse_args()
 
@@ -138,8 +138,10 @@ def main():
                             torch.empty((G, 5), dtype=torch.float64, device=dev))
 
         def step(**kw):
-            g = graph and not kw.get("phase_times", False)
-            cpc.fit_batched(x, y, w.offsets, w.group_offsets, fams, workspace=ws, out=out, prec=prec, graph=g, **kw)
+            # every step records the phase events (in graph mode the library
+            # replays one graph per phase, with the events between them)
+            cpc.fit_batched(x, y, w.offsets, w.group_offsets, fams, workspace=ws, out=out, prec=prec, graph=graph,
+                            phase_times=True, **kw)
         return step, out
 
     def timed(step, steps, warmup):
@@ -167,13 +169,9 @@ def main():
         torch.cuda.synchronize()
         del xc
 
-    # per-phase durations (HIP events recorded by the library on the launch stream)
-    phases = np.zeros(4)
-    nph = max(3, min(a.steps, 10))
-    for _ in range(nph):
-        step(phase_times=True)
-        phases += np.array(cpc.phase_times(0))
-    phases /= nph
+    # per-phase durations of the last timed step (HIP events the library
+    # records on the launch stream between the phase graphs)
+    phases = np.array(cpc.phase_times(0), dtype=np.float64)
 
     theta = out.theta.cpu().numpy()
     iters = out.iters.cpu().numpy()

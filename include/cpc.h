@@ -188,8 +188,10 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
 /* Durations (milliseconds) of the phases of the handle's last cpc_fit /
  * cpc_fit_batched call made with CPC_FLAG_PHASE_TIMES: ms[0] ranks (eq. 12),
  * ms[1] maximisation of eq. (13), ms[2] variance (Sec. 2.3), ms[3] combine
- * (eq. 15). Measured with hipEvents on the call's stream; blocks until the
- * last phase has completed. CPC_E_OPTIONS if no such call was made. */
+ * (eq. 15). Measured with hipEvents on the call's stream. With
+ * CPC_FLAG_GRAPH as well, the call captures one graph per phase and every
+ * replay records the events between the four graph launches. Blocks until
+ * the last phase has completed. CPC_E_OPTIONS if no such call was made. */
 int cpc_phase_times(cpc_handle_t h, float* ms);
 
 /* Message for an error code, and the thread-local detail of the last error. */

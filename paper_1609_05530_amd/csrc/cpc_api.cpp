@@ -23,11 +23,15 @@
 
 using namespace cpc;
 
+// phases of a fit: ranks (eq. 12), maximisation of eq. (13), variance
+// (Sec. 2.3), combine (eq. 15)
+static constexpr int kPhases = 4;
+
 struct cpc_context {
   int device;
   int magic;
   void* plan;               // host copy of the last call's launch tables, kept alive past the call
-  hipEvent_t ev[5];         // phase boundaries of the last fit (CPC_FLAG_PHASE_TIMES)
+  hipEvent_t ev[kPhases + 1];  // phase boundaries of the last fit (CPC_FLAG_PHASE_TIMES)
   int have_times;
   int* pending_host;        // pinned: subsets of the streaming path still iterating
   hipStream_t cap_stream;   // the fit is captured here in graph mode (default priority)
@@ -374,7 +378,9 @@ int check_handle(cpc_handle_t h) {
 // key is every pointer, size and option of the call plus the offsets, group
 // offsets and families; a replay also requires that the workspace still
 // holds the tables of the capture, so any other call through this handle
-// with the same workspace drops the cached graph.
+// with the same workspace drops the cached graph. With CPC_FLAG_PHASE_TIMES
+// each phase is a graph of its own (events recorded inside a graph cannot be
+// timed), launched back to back with the phase events recorded between them.
 struct GraphCache {
   bool valid = false;
   const void *x = nullptr, *y = nullptr;
@@ -386,12 +392,23 @@ struct GraphCache {
   void* ws = nullptr;
   size_t ws_bytes = 0;
   void *out = nullptr, *comb = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec[kPhases] = {};
+  int nexec = 0;
 
   void drop() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    exec = nullptr;
+    for (int i = 0; i < nexec; ++i) (void)hipGraphExecDestroy(exec[i]);
+    nexec = 0;
     valid = false;
+  }
+  // replay: one graph, or the phase graphs between the handle's events
+  hipError_t launch(hipEvent_t* ev, hipStream_t s) const {
+    hipError_t e = hipSuccess;
+    if (nexec == 1) return hipGraphLaunch(exec[0], s);
+    for (int i = 0; i < nexec && e == hipSuccess; ++i) {
+      e = hipEventRecord(ev[i], s);
+      if (e == hipSuccess) e = hipGraphLaunch(exec[i], s);
+    }
+    return e == hipSuccess ? hipEventRecord(ev[nexec], s) : e;
   }
   bool same(const void* x_, const void* y_, int32_t dtype_, int64_t n_, const int64_t* off_, int64_t K_,
             const int64_t* gofs_, int64_t G_, const std::vector<int32_t>& fam_, const Options& o_, void* ws_,
@@ -412,8 +429,11 @@ void touch_workspace(cpc_handle_t h, const void* ws) {
   if (gc.valid && gc.ws == ws) gc.drop();
 }
 
+int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype,
+                  int64_t G, const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph,
+                  hipStream_t s);
 int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
-                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph, hipStream_t s);
+                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, hipStream_t s);
 
 // Autotuner: the rank kernel's launch shape per size class, chosen by timing
 // each candidate shape on the call's own subsets (the rank kernel is exact
@@ -522,13 +542,12 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   if (ws_bytes < L.total)
     return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
   const bool graph = (o.flags & CPC_FLAG_GRAPH) != 0;
-  if (graph && (o.flags & CPC_FLAG_PHASE_TIMES))
-    return fail(CPC_E_OPTIONS, "phase times are not recorded in graph mode");
+  const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
   GraphCache& gc = graph_of(h);
   HIP_OK(hipSetDevice(h->device));
   if (graph && gc.same(x, y, dtype, n, offsets, K, gofs, G, fam_of_subset, o, ws, ws_bytes, out, comb)) {
-    h->have_times = 0;
-    HIP_OK(hipGraphLaunch(gc.exec, s));
+    h->have_times = timed ? 1 : 0;
+    HIP_OK(gc.launch(h->ev, s));
     return CPC_SUCCESS;
   }
   touch_workspace(h, ws);
@@ -543,83 +562,114 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   set_big(c, P, o.n_min);
   rc = choose_rank_shapes(h, P, c, x, y, dtype == CPC_F64 ? 2 : 1, o, s);
   if (rc) return rc;
-  if (!graph) return enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, false, s);
+  if (!graph) return enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, s);
 
-  // capture on the handle's stream once the uploads on `s` are done
+  // capture on the handle's stream once the uploads on `s` are done: one
+  // graph, or one per phase when the phases are timed
   HIP_OK(hipStreamSynchronize(s));
-  HIP_OK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-  rc = enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, true, h->cap_stream);
-  hipGraph_t g = nullptr;
-  const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
-  if (rc) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
+  const int nexec = timed ? kPhases : 1;
+  hipGraphExec_t ex[kPhases] = {};
+  for (int e = 0; e < nexec; ++e) {
+    hipError_t he = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    const char* what = "hipStreamBeginCapture";
+    if (he == hipSuccess) {
+      for (int ph = timed ? e : 0; ph < (timed ? e + 1 : kPhases) && rc == CPC_SUCCESS; ++ph)
+        rc = enqueue_phase(ph, h, P, c, x, y, dtype, G, o, out, comb, true, h->cap_stream);
+      hipGraph_t g = nullptr;
+      he = hipStreamEndCapture(h->cap_stream, &g);
+      what = "hipStreamEndCapture";
+      if (rc == CPC_SUCCESS && he == hipSuccess) {
+        he = hipGraphInstantiate(&ex[e], g, nullptr, nullptr, 0);
+        what = "hipGraphInstantiate";
+      }
+      if (g) (void)hipGraphDestroy(g);
+    }
+    if (rc != CPC_SUCCESS || he != hipSuccess) {
+      for (int i = 0; i < e; ++i) (void)hipGraphExecDestroy(ex[i]);
+      return rc != CPC_SUCCESS ? rc : fail(CPC_E_HIP, "%s: %s", what, hipGetErrorString(he));
+    }
   }
-  if (ec != hipSuccess) return fail(CPC_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
-  hipGraphExec_t ex = nullptr;
-  const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (ei != hipSuccess) return fail(CPC_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
   gc.drop();
   gc.x = x; gc.y = y; gc.dtype = dtype; gc.n = n; gc.K = K; gc.G = G;
   gc.offsets.assign(offsets, offsets + K + 1);
   gc.gofs.assign(gofs, gofs + G + 1);
   gc.fam = fam_of_subset;
   gc.o = o; gc.ws = ws; gc.ws_bytes = ws_bytes; gc.out = out; gc.comb = comb;
-  gc.exec = ex;
+  for (int e = 0; e < nexec; ++e) gc.exec[e] = ex[e];
+  gc.nexec = nexec;
   gc.valid = true;
-  HIP_OK(hipGraphLaunch(ex, s));
+  h->have_times = timed ? 1 : 0;
+  HIP_OK(gc.launch(h->ev, s));
   return CPC_SUCCESS;
 }
 
-// The launch sequence of a fit (tables already in the workspace):
-// rank -> fit -> variance -> combine. In graph mode nothing here waits on
-// the host: the streaming path's Newton loop runs its full pass budget, its
-// kernels returning at once when every subset is done.
-int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
-                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph, hipStream_t s) {
-  const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
+// The launch sequence of a fit (tables already in the workspace), one phase
+// at a time: rank -> fit -> variance -> combine. In graph mode nothing here
+// waits on the host: the streaming path's Newton loop runs its full pass
+// budget, its kernels returning at once when every subset is done.
+int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype,
+                  int64_t G, const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph,
+                  hipStream_t s) {
   const int kw = (dtype == CPC_F64) ? 2 : 1;
   const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
+  switch (ph) {
+    case 0: {
+      RankParams rp = rank_params(c, x, y, o);
+      for (const Bucket& b : P.rank_buckets) {
+        rp.order = c.order_rank + b.first;
+        HIP_OK(launch_rank_shape(b.shape >= 0 ? b.shape : kRankDefaultShape[b.cls], kw, rp, b.count, s));
+      }
+      HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, nullptr, nullptr, s));
+      return CPC_SUCCESS;
+    }
+    case 1: {
+      FitParams fp;
+      std::memset(&fp, 0, sizeof(fp));
+      fp.subs = c.subs;
+      fp.rows = c.rows;
+      fp.state = c.state;
+      fp.max_iter = o.max_iter;
+      fp.tol = o.tol;
+      for (const Bucket& b : P.fit_buckets) {
+        fp.order = c.order_fit + b.first;
+        HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
+      }
+      HIP_OK(big_solve(c.big, c.bb, o.tol, o.max_iter, fp64, graph ? nullptr : h->pending_host, s));
+      return CPC_SUCCESS;
+    }
+    case 2: {
+      VarParams vp;
+      std::memset(&vp, 0, sizeof(vp));
+      vp.subs = c.subs;
+      vp.rows = c.rows;
+      vp.state = c.state;
+      vp.mode = MODE_FIT;
+      vp.var_method = o.var;
+      vp.out = (ResultOut*)out;
+      for (const Bucket& b : P.fit_buckets) {
+        vp.order = c.order_fit + b.first;
+        HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
+      }
+      HIP_OK(big_variance(c.big, c.bb, fp64, nullptr, o.var, MODE_FIT, nullptr, (ResultOut*)out, s));
+      return CPC_SUCCESS;
+    }
+    default:
+      HIP_OK(launch_combine((const ResultOut*)out, c.gofs, G, (CombinedOut*)comb, s));
+      return CPC_SUCCESS;
+  }
+}
 
-  RankParams rp = rank_params(c, x, y, o);
-  if (timed) HIP_OK(hipEventRecord(h->ev[0], s));
-  for (const Bucket& b : P.rank_buckets) {
-    rp.order = c.order_rank + b.first;
-    HIP_OK(launch_rank_shape(b.shape >= 0 ? b.shape : kRankDefaultShape[b.cls], kw, rp, b.count, s));
+// Eager launch of every phase, with the phase events when asked for.
+int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
+                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, hipStream_t s) {
+  const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
+  for (int ph = 0; ph < kPhases; ++ph) {
+    if (timed) HIP_OK(hipEventRecord(h->ev[ph], s));
+    const int rc = enqueue_phase(ph, h, P, c, x, y, dtype, G, o, out, comb, false, s);
+    if (rc) return rc;
   }
-  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, nullptr, nullptr, s));
-  if (timed) HIP_OK(hipEventRecord(h->ev[1], s));
-  FitParams fp;
-  std::memset(&fp, 0, sizeof(fp));
-  fp.subs = c.subs;
-  fp.rows = c.rows;
-  fp.state = c.state;
-  fp.max_iter = o.max_iter;
-  fp.tol = o.tol;
-  for (const Bucket& b : P.fit_buckets) {
-    fp.order = c.order_fit + b.first;
-    HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
-  }
-  HIP_OK(big_solve(c.big, c.bb, o.tol, o.max_iter, fp64, graph ? nullptr : h->pending_host, s));
-  if (timed) HIP_OK(hipEventRecord(h->ev[2], s));
-  VarParams vp;
-  std::memset(&vp, 0, sizeof(vp));
-  vp.subs = c.subs;
-  vp.rows = c.rows;
-  vp.state = c.state;
-  vp.mode = MODE_FIT;
-  vp.var_method = o.var;
-  vp.out = (ResultOut*)out;
-  for (const Bucket& b : P.fit_buckets) {
-    vp.order = c.order_fit + b.first;
-    HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
-  }
-  HIP_OK(big_variance(c.big, c.bb, fp64, nullptr, o.var, MODE_FIT, nullptr, (ResultOut*)out, s));
-  if (timed) HIP_OK(hipEventRecord(h->ev[3], s));
-  HIP_OK(launch_combine((const ResultOut*)out, c.gofs, G, (CombinedOut*)comb, s));
   if (timed) {
-    HIP_OK(hipEventRecord(h->ev[4], s));
+    HIP_OK(hipEventRecord(h->ev[kPhases], s));
     h->have_times = 1;
   }
   return CPC_SUCCESS;
@@ -672,7 +722,7 @@ int cpc_create(int device, cpc_handle_t* out) {
     delete h;
     return fail(CPC_E_HIP, "hipStreamCreateWithFlags failed");
   }
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i <= kPhases; ++i) {
     if (hipEventCreate(&h->ev[i]) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(h->ev[j]);
       (void)hipStreamDestroy(h->cap_stream);
@@ -696,7 +746,7 @@ int cpc_destroy(cpc_handle_t h) {
   delete (GraphCache*)h->graph;
   delete (Tuner*)h->tuner;
   (void)hipStreamDestroy(h->cap_stream);
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(h->ev[i]);
+  for (int i = 0; i <= kPhases; ++i) (void)hipEventDestroy(h->ev[i]);
   (void)hipHostFree(h->pending_host);
   delete (Plan*)h->plan;
   delete h;
@@ -891,8 +941,8 @@ int cpc_phase_times(cpc_handle_t h, float* ms) {
   if (int rc = check_handle(h)) return rc;
   if (!ms) return fail(CPC_E_NULL, "ms is NULL");
   if (!h->have_times) return fail(CPC_E_OPTIONS, "no fit with CPC_FLAG_PHASE_TIMES on this handle");
-  HIP_OK(hipEventSynchronize(h->ev[4]));
-  for (int i = 0; i < 4; ++i) HIP_OK(hipEventElapsedTime(&ms[i], h->ev[i], h->ev[i + 1]));
+  HIP_OK(hipEventSynchronize(h->ev[kPhases]));
+  for (int i = 0; i < kPhases; ++i) HIP_OK(hipEventElapsedTime(&ms[i], h->ev[i], h->ev[i + 1]));
   return CPC_SUCCESS;
 }
 

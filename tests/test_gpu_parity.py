@@ -450,6 +450,39 @@ def test_graph_replays_match_eager(prec):
             assert np.array_equal(again[k], eager[k], equal_nan=True), (r, k)
 
 
+def test_graph_phase_times():
+    """Timed graph mode: one graph per phase, with the phase events between
+    them. Results equal the eager fit; every replay gives phase times that
+    lie inside events recorded around the call on the same stream."""
+    m = cpc()
+    x, y, off, gofs, fams = _graph_case()
+    dx, dy = dev(x, torch.float32), dev(y, torch.float32)
+    eager = to_np(m.fit_batched(dx, dy, off, gofs, fams, prec="fp32c"))
+    K, G = len(off) - 1, len(gofs) - 1
+    ws = torch.empty(m.workspace_bytes(len(x), K, G, dtype=torch.float32, prec="fp32c"), dtype=torch.uint8,
+                     device="cuda")
+    out = m.FitResult(torch.empty((K, 6), dtype=torch.float64, device="cuda"),
+                      torch.empty((G, 5), dtype=torch.float64, device="cuda"))
+    for r in range(3):
+        out.raw.fill_(float("nan"))
+        out.raw_comb.fill_(float("nan"))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec="fp32c", phase_times=True)
+        b.record()
+        ph = np.array(m.phase_times(0))
+        torch.cuda.synchronize()
+        got = to_np(out)
+        for k in eager:
+            assert np.array_equal(got[k], eager[k], equal_nan=True), (r, k)
+        assert ph.shape == (4,) and np.all(ph > 0) and np.all(np.isfinite(ph)), (r, ph)
+        assert ph.sum() <= a.elapsed_time(b) + 1e-3, (r, ph, a.elapsed_time(b))
+    # an untimed graph replay leaves no phase times behind
+    m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec="fp32c")
+    with pytest.raises(m.CpcError):
+        m.phase_times(0)
+
+
 def test_graph_replay_reads_current_data():
     m = cpc()
     x, y, off, gofs, fams = _graph_case()
