@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="subsets per setting in the CPU-baseline sample")
     ap.add_argument("--profile", action="store_true", help="short run for a profiler (no oracle, no checks)")
+    ap.add_argument("--no-small-configs", action="store_true",
+                    help="skip the GPU times of the n=1e4 and n=1e6 FP64 workloads")
+    ap.add_argument("--oracle-1thread", action="store_true",
+                    help="also time the oracle on one thread on the n=1e4 and n=1e6 workloads (minutes)")
     return ap.parse_args()
 
 
@@ -95,6 +99,72 @@ def valu_probe():
     return {"lane_ops_per_s": {k: v for k, v in rates.items()},
             "slots_per_op": {k: rates["fma"] / v for k, v in rates.items() if k != "fma"},
             "fma_vs_peak": rates["fma"] / PEAK_LANE_SLOTS}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def small_configs(cpc, synth, dev, oracle_1thread):
+    """The n = 1e4 Gaussian workload (K = 1, 10) and the n = 1e6 workloads of
+    the three families (K = 1, 10, 100) on the FP64 GPU path: median time of
+    a graph replay with inputs resident in HBM. With oracle_1thread, the
+    oracle's one-thread wall time (host arrays to results) on each, all of
+    them run side by side on host threads, and the GPU's error against it."""
+    import torch
+    cases = [synth.config1(K) for K in (1, 10)]
+    cases += [synth.config2(f, K) for f in ("gaussian", "frank", "gumbel") for K in (1, 10, 100)]
+    rows = []
+    for w in cases:
+        x = torch.from_numpy(w.x).to(dev)
+        y = torch.from_numpy(w.y).to(dev)
+        ws = torch.empty(cpc.workspace_bytes(w.n, w.K, w.G, dtype=x.dtype, prec="fp64"), dtype=torch.uint8,
+                         device=dev)
+        out = cpc.FitResult(torch.empty((w.K, 6), dtype=torch.float64, device=dev),
+                            torch.empty((w.G, 5), dtype=torch.float64, device=dev))
+
+        def step():
+            cpc.fit_batched(x, y, w.offsets, w.group_offsets, w.families, workspace=ws, out=out, prec="fp64",
+                            graph=True)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+        evs[0].record()
+        for i in range(10):
+            step()
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        ms = float(np.median([evs[i].elapsed_time(evs[i + 1]) for i in range(10)]))
+        rows.append({"workload": w.name, "gpu_ms": ms, "theta_combined": float(out.combined_theta.cpu().numpy()[0]),
+                     "_theta": out.theta.cpu().numpy()})
+        print(f"[small configs] {w.name}: {ms:.3f} ms", file=sys.stderr, flush=True)
+        del x, y, ws, out
+    if oracle_1thread:
+        from concurrent.futures import ThreadPoolExecutor
+        import oracle.oracle as O
+
+        def run(w):
+            t0 = time.perf_counter()
+            sub, _ = O.fit(w.x, w.y, w.offsets, w.families, w.group_offsets, nthreads=1)
+            dt = time.perf_counter() - t0
+            print(f"[oracle 1 thread] {w.name}: {dt:.1f} s", file=sys.stderr, flush=True)
+            return dt, sub["theta"]
+        with ThreadPoolExecutor(max_workers=len(cases)) as ex:
+            res = list(ex.map(run, cases))
+        for r, (dt, th) in zip(rows, res):
+            r["oracle_1thread_s"] = dt
+            r["theta_max_rel_vs_oracle"] = float(np.max(np.abs(r["_theta"] - th) / np.maximum(np.abs(th), 1e-2)))
+    for r in rows:
+        del r["_theta"]
+    return rows
 
 
 def measured_rank_traffic():
@@ -248,6 +318,8 @@ def main():
 
     if not a.profile:
         line["valu_probe"] = valu_probe()
+    if not a.profile and not a.no_small_configs:
+        line["small_configs_fp64"] = small_configs(cpc, synth, dev, a.oracle_1thread)
 
     if not a.profile and not a.no_fp64_compare and a.prec == "fp32c":
         step64, out64 = make_step("fp64")
@@ -297,6 +369,7 @@ def main():
             "value": len(pick) / cpu_s,
             "unit": "subset-fits/s",
             "cores": nt,
+            "cpu_model": cpu_model(),
             "kind": "oracle",
             "sample": f"{len(pick)} subsets ({a.cpu_sample} per setting, {int(sizes.sum())} rows), FP64 oracle, "
                       f"OpenMP over subsets, {cpu_s:.1f} s",
