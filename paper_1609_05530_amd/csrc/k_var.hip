@@ -125,43 +125,78 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     // left in the workspace (Gaussian normal scores; Gumbel log(-log u),
     // log(-log v)), computed there by the same FP32 code
     constexpr bool ZFAM = FAM != FAM_FRANK && std::is_same<RT, float>::value && sizeof(CT) == 4;
-    const bool zcache = ZFAM && P.mode == MODE_FIT;
-    if constexpr (TWO && ZFAM) {
-      if (zcache) {
-        const float2* ZC = (const float2*)P.rows.G + o;
-        const int last = n - 1;
-        const int i0 = min(tid, last), i1 = min(tid + T, last);
-        float2 z0 = ZC[i0], z1 = ZC[i1];
-        uint32_t q0 = (uint32_t)E1[i0] | ((uint32_t)E2[i0] << 16), q1 = (uint32_t)E1[i1] | ((uint32_t)E2[i1] << 16);
-        uint32_t r0 = 0u, r1 = 0u;
-        if constexpr (FAM == FAM_GUMBEL) {
-          r0 = (uint32_t)R1[i0] | ((uint32_t)R2[i0] << 16);
-          r1 = (uint32_t)R1[i1] | ((uint32_t)R2[i1] << 16);
-        }
-#pragma unroll 1
-        for (int i = tid; i < n; i += T) {
-          const int i2 = min(i + 2 * T, last);
-          const float2 z2 = ZC[i2];
-          const uint32_t q2 = (uint32_t)E1[i2] | ((uint32_t)E2[i2] << 16);
-          uint32_t r2 = 0u;
-          if constexpr (FAM == FAM_GUMBEL) r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16);
+    [[maybe_unused]] const bool zcache = ZFAM && P.mode == MODE_FIT;
+    if constexpr (TWO && sizeof(CT) == 4 && std::is_same<RT, float>::value) {
+      // FP32 rows: a thread's rows i = tid + k*T live in registers. Their
+      // loads are issued H rows at a time (H sized so that the rows in flight
+      // fit 128 VGPRs), the score s stays in a register
+      // until the psi pass, and the loads of the tie-group starts for that
+      // pass are issued before the suffix sums, so the workgroup waits on
+      // HBM a few times per phase instead of once per row.
+      constexpr int HF = FAM == FAM_FRANK ? 2 : 4;
+      constexpr int H = E < HF ? E : HF;
+      const int last = n - 1;
+      const float2* ZC = (const float2*)P.rows.G + o;
+      const bool need_r = !zcache || FAM == FAM_GUMBEL;
+      float sk[E];
+#pragma unroll
+      for (int h = 0; h < E; h += H) {
+      uint32_t qk[H], rk[H];
+      float2 zk[ZFAM ? H : 1];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int i = min(tid + (h + j) * T, last);
+        qk[j] = (uint32_t)E1[i] | ((uint32_t)E2[i] << 16);
+        rk[j] = need_r ? ((uint32_t)R1[i] | ((uint32_t)R2[i] << 16)) : 0u;
+        if constexpr (ZFAM) zk[j] = zcache ? ZC[i] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int k = h + j;
+        sk[k] = 0.f;
+        if (tid + k * T < n) {
           CT l, s, g1, g2;
-          if constexpr (FAM == FAM_GUMBEL)
-            gumbel_rfull<CT>(c, r0 & 0xFFFFu, r0 >> 16, twon1, inv, z0.x, z0.y, l, s, g1, g2);
-          else
-            gauss_rfull<CT>(c, z0.x, z0.y, l, s, g1, g2);
+          if constexpr (ZFAM) {
+            if (zcache) {
+              if constexpr (FAM == FAM_GUMBEL)
+                gumbel_rfull<CT>(c, rk[j] & 0xFFFFu, rk[j] >> 16, twon1, inv, zk[j].x, zk[j].y, l, s, g1, g2);
+              else
+                gauss_rfull<CT>(c, zk[j].x, zk[j].y, l, s, g1, g2);
+            } else {
+              row_eval_ab(RT{}, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
+            }
+          } else {
+            row_eval_ab(RT{}, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
+          }
           kl.add(l); ksc.add(s); ks2.add(s * s);
-          A1[pidx((int)(q0 & 0xFFFFu))] = g1;
-          A2[pidx((int)(q0 >> 16))] = g2;
-          S[i] = s;
-          z0 = z1; q0 = q1; z1 = z2; q1 = q2; r0 = r1; r1 = r2;
+          A1[pidx((int)(qk[j] & 0xFFFFu))] = g1;
+          A2[pidx((int)(qk[j] >> 16))] = g2;
+          sk[k] = s;
         }
       }
-    }
-    if constexpr (TWO) {
+      }
+      uint32_t lk[E];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int i = min(tid + k * T, last);
+        lk[k] = (uint32_t)L1[i] | ((uint32_t)L2[i] << 16);
+      }
+      __syncthreads();
+      lds_suffix_sum<T, E, CT>(A1, n, red);
+      lds_suffix_sum<T, E, CT>(A2, n, red);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        if (tid + k * T < n) {
+          const double psi = (double)sk[k] +
+                             ((double)A1[pidx((int)(lk[k] & 0xFFFFu))] + (double)A2[pidx((int)(lk[k] >> 16))]) * idn;
+          psum += psi;
+          psq += psi * psi;
+        }
+      }
+    } else if constexpr (TWO) {
       // Rows i = tid, tid + T, ...; the loads of the next two rows are in
       // flight while a row is evaluated (their latency dominates otherwise).
-      if (!zcache) {
+      {
         const int last = n - 1;
         int i1 = min(tid + T, last), i2 = min(tid + 2 * T, last);
         const int i0 = min(tid, last);
@@ -278,13 +313,32 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   }
 }
 
+// Waves per SIMD asked of the register allocator for FP32 Frank and Gumbel
+// results: as many as the workgroup's LDS lets share a CU, up to 4 (128
+// VGPRs), so that the rows a thread keeps in registers do not cost
+// occupancy. FP64 results and the Gaussian (whose FP64 normal-quantile rows
+// near |rho| = 1 need about 200 VGPRs) keep the allocator's default.
+template <int T, int CAP, typename CT, int FAM>
+constexpr int var_waves_per_simd() {
+  if (sizeof(CT) == 8 || FAM == FAM_GAUSSIAN) return 1;
+  constexpr int lds = 2 * (int)sizeof(CT) * padded(CAP) + 1024;
+  constexpr int wgs = (160 * 1024) / lds;
+  constexpr int w = wgs * (T / WAVE) / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
 template <int T, int CAP, typename CT>
 static hipError_t launch_t(int fam, const VarParams& p, int grid, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
+  constexpr int MG = var_waves_per_simd<T, CAP, CT, FAM_GAUSSIAN>();
+  constexpr int MF = var_waves_per_simd<T, CAP, CT, FAM_FRANK>();
+  constexpr int MU = var_waves_per_simd<T, CAP, CT, FAM_GUMBEL>();
   switch (fam) {
-    case FAM_GAUSSIAN: hipLaunchKernelGGL((k_var_wg<T, CAP, CT, FAM_GAUSSIAN>), dim3(grid), dim3(T), 0, s, p); break;
-    case FAM_FRANK: hipLaunchKernelGGL((k_var_wg<T, CAP, CT, FAM_FRANK>), dim3(grid), dim3(T), 0, s, p); break;
-    default: hipLaunchKernelGGL((k_var_wg<T, CAP, CT, FAM_GUMBEL>), dim3(grid), dim3(T), 0, s, p); break;
+    case FAM_GAUSSIAN:
+      hipLaunchKernelGGL((k_var_wg<T, CAP, CT, FAM_GAUSSIAN, false, MG>), dim3(grid), dim3(T), 0, s, p);
+      break;
+    case FAM_FRANK: hipLaunchKernelGGL((k_var_wg<T, CAP, CT, FAM_FRANK, false, MF>), dim3(grid), dim3(T), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_var_wg<T, CAP, CT, FAM_GUMBEL, false, MU>), dim3(grid), dim3(T), 0, s, p); break;
   }
   return hipGetLastError();
 }
