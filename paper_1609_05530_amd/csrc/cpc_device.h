@@ -146,4 +146,34 @@ __device__ __forceinline__ double block_excl_suffix(double v, double* scratch) {
   return incl + carry - v;
 }
 
+// Two exclusive suffix sums at once (the same arithmetic as block_excl_suffix
+// on each value; one pair of workgroup barriers for both). scratch: 2W doubles.
+template <int W>
+__device__ __forceinline__ void block_excl_suffix2(double va, double vb, double* scratch, double& ea, double& eb) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  double ia = va, ib = vb;
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const double xa = __shfl_down(ia, off, WAVE);
+    const double xb = __shfl_down(ib, off, WAVE);
+    if (lane + off < WAVE) {
+      ia += xa;
+      ib += xb;
+    }
+  }
+  if (lane == 0) {
+    scratch[w] = ia;
+    scratch[W + w] = ib;
+  }
+  __syncthreads();
+  double ca = 0.0, cb = 0.0;
+  for (int k = W - 1; k > w; --k) {
+    ca += scratch[k];
+    cb += scratch[W + k];
+  }
+  __syncthreads();
+  ea = ia + ca - va;
+  eb = ib + cb - vb;
+}
+
 }  // namespace cpc

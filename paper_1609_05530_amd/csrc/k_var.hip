@@ -45,6 +45,34 @@ __device__ __forceinline__ void lds_suffix_sum(CT* A, int n, double* scratch) {
   __syncthreads();
 }
 
+// The same for two arrays at once (the u-order and v-order sums share the
+// workgroup scan of their chunk totals).
+template <int T, int E, typename CT>
+__device__ __forceinline__ void lds_suffix_sum2(CT* A, CT* B, int n, double* scratch) {
+  constexpr int W = T / WAVE;
+  const int c0 = threadIdx.x * E;
+  double ca = 0.0, cb = 0.0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    if (c0 + i < n) {
+      ca += (double)A[pidx(c0 + i)];
+      cb += (double)B[pidx(c0 + i)];
+    }
+  }
+  double ra, rb;
+  block_excl_suffix2<W>(ca, cb, scratch, ra, rb);
+#pragma unroll
+  for (int i = E - 1; i >= 0; --i) {
+    if (c0 + i < n) {
+      ra += (double)A[pidx(c0 + i)];
+      A[pidx(c0 + i)] = (CT)ra;
+      rb += (double)B[pidx(c0 + i)];
+      B[pidx(c0 + i)] = (CT)rb;
+    }
+  }
+  __syncthreads();
+}
+
 template <int T, int CAP, typename CT, int FAM, bool ONE = false, int MINW = 1>
 __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   constexpr int W = T / WAVE;
@@ -182,8 +210,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
         lk[k] = (uint32_t)L1[i] | ((uint32_t)L2[i] << 16);
       }
       __syncthreads();
-      lds_suffix_sum<T, E, CT>(A1, n, red);
-      lds_suffix_sum<T, E, CT>(A2, n, red);
+      lds_suffix_sum2<T, E, CT>(A1, A2, n, red);
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         if (tid + k * T < n) {
@@ -217,8 +244,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
         }
       }
       __syncthreads();
-      lds_suffix_sum<T, E, CT>(A1, n, red);
-      lds_suffix_sum<T, E, CT>(A2, n, red);
+      lds_suffix_sum2<T, E, CT>(A1, A2, n, red);
       {
         const int last = n - 1;
         const int i0 = min(tid, last), i1 = min(tid + T, last);
