@@ -92,8 +92,10 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 }
 
 // Sums NV doubles over the workgroup; result valid in thread 0.
-// scratch: at least W * NV doubles of LDS.
-template <int W, int NV>
+// scratch: at least W * NV doubles of LDS. TAIL = false leaves out the
+// closing barrier: the caller then synchronises the workgroup before
+// scratch is written again.
+template <int W, int NV, bool TAIL = true>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
@@ -111,10 +113,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
       v[i] = a;
     }
   }
-  __syncthreads();
+  if (TAIL) __syncthreads();
 }
 
-template <int W>
+template <int W, bool TAIL = true>
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* scratch) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   v = wave_sum_ll(v);
@@ -123,7 +125,7 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* scratc
   long long a = 0;
   if (threadIdx.x == 0)
     for (int k = 0; k < W; ++k) a += scratch[k];
-  __syncthreads();
+  if (TAIL) __syncthreads();
   return a;
 }
 

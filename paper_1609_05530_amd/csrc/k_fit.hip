@@ -89,7 +89,9 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
       }
     }
   }
-  const long long S = block_sum_ll<W>(sacc, (long long*)red);
+  // only thread 0 reads the sums; the barrier after its update closes each
+  // reduction before the scratch is written again
+  const long long S = block_sum_ll<W, false>(sacc, (long long*)red);
   if (tid == 0) {
     const double rho_s = 3.0 * (double)S / (dn * (dn * dn - 1.0));
     newton_init(nst, FAM, start_theta(FAM, rho_s));
@@ -131,7 +133,7 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
       v[0] = kp.value();
       v[1] = km.value();
     }
-    block_sum<W, 2>(v, red);
+    block_sum<W, 2, false>(v, red);
     if (tid == 0) {
       gauss_solve(nst, dn, v[0], v[1], 1e-14);
       SubState& st = P.state[sid];
@@ -203,7 +205,7 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
           pass(std::integral_constant<int, 0>{});
         noise = 16.0 * (sizeof(CT) == 4 ? 5.9604644775390625e-08 : 1.1102230246251565e-16);
       }
-      block_sum<W, 3>(v, red);
+      block_sum<W, 3, false>(v, red);
       if (tid == 0) newton_update(nst, FAM, v[0], v[1], v[2], P.tol, noise, P.max_iter);
       __syncthreads();
       if (nst.done) break;

@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   else
     rows(CT{}, std::integral_constant<int, 0>{});
   double v[5] = {kl.value(), ksc.value(), ks2.value(), psum, psq};
-  block_sum<W, 5>(v, red);
+  block_sum<W, 5, false>(v, red);  // thread 0 finishes alone
   if (tid == 0) {
     const double mpsi = v[3] / dn;
     const double nu = v[4] / dn - mpsi * mpsi;
