@@ -116,18 +116,15 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   const double idn = 1.0 / dn;  // W1, W2 are means over the subset
   const Consts<CT> c = make_consts<CT>(FAM, theta);
   const bool rd = sizeof(CT) == 4 && c.use_d;  // FP64 rows near the family boundaries
-  const Consts<double> cd = make_consts<double>(FAM, theta);
 
   // Row arithmetic in RT (CT, or double near the family boundaries), results
   // in CT. The choice is uniform over the workgroup and made once, outside
   // the row loops.
-  auto row_eval_ab = [&](auto rt_tag, auto form_tag, uint32_t a, uint32_t b, CT& l, CT& s, CT& g1, CT& g2) {
+  auto row_eval_ab = [&](auto rt_tag, const Consts<decltype(rt_tag)>& cc, auto form_tag, uint32_t a, uint32_t b,
+                         CT& l, CT& s, CT& g1, CT& g2) {
     using RT = decltype(rt_tag);
     constexpr int FORM = decltype(form_tag)::value;
     const RT invr = (RT)1 / (RT)twon1;
-    const Consts<RT>& cc = [&]() -> const Consts<RT>& {
-      if constexpr (std::is_same<RT, double>::value) return cd; else return c;
-    }();
     RT lr, sr, g1r, g2r;
     if constexpr (FAM == FAM_FRANK) {
       frank_rfull<RT, FORM>(cc, a, b, twon1, invr, lr, sr, g1r, g2r);
@@ -149,6 +146,11 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   auto rows = [&](auto rt_tag, auto form_tag) {
     using RT = decltype(rt_tag);
     using FT = decltype(form_tag);
+    // the constants in the row type (the FP64 ones of an FP32 kernel are
+    // formed only when its rows are evaluated in double)
+    const Consts<RT> cc = [&]() {
+      if constexpr (std::is_same<RT, CT>::value) return c; else return make_consts<RT>(FAM, theta);
+    }();
     // FP32 rows after the fit: the theta-free per-row terms the fit kernel
     // left in the workspace (Gaussian normal scores; Gumbel log(-log u),
     // log(-log v)), computed there by the same FP32 code
@@ -191,10 +193,10 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
               else
                 gauss_rfull<CT>(c, zk[j].x, zk[j].y, l, s, g1, g2);
             } else {
-              row_eval_ab(RT{}, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
+              row_eval_ab(RT{}, cc, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
             }
           } else {
-            row_eval_ab(RT{}, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
+            row_eval_ab(RT{}, cc, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
           }
           kl.add(l); ksc.add(s); ks2.add(s * s);
           A1[pidx((int)(qk[j] & 0xFFFFu))] = g1;
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           const uint32_t r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16);
           const uint32_t q2 = (uint32_t)E1[i2] | ((uint32_t)E2[i2] << 16);
           CT l, s, g1, g2;
-          row_eval_ab(RT{}, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
+          row_eval_ab(RT{}, cc, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
           kl.add(l); ksc.add(s); ks2.add(s * s);
           A1[pidx((int)(q0 & 0xFFFFu))] = g1;
           A2[pidx((int)(q0 >> 16))] = g2;
@@ -277,7 +279,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           const int i2 = min(i + 2 * T, last);
           const uint32_t r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16), e2 = E1[i2];
           CT l, s, g1, g2;
-          row_eval_ab(RT{}, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
+          row_eval_ab(RT{}, cc, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
           kl.add(l); ksc.add(s); ks2.add(s * s);
           A1[pidx((int)e0)] = g1;
           S[i] = s;
