@@ -56,6 +56,42 @@ __device__ __forceinline__ uint32_t wave_incl_sum_u32(uint32_t v) {
   return v;
 }
 
+// Inclusive max-scan within each 16-lane row (identity INT_MIN), and over the
+// whole wave (the row ends carried forward as in wave_incl_sum_u32).
+__device__ __forceinline__ int row_incl_max_i32(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xF, 0xF, false));
+  return v;
+}
+__device__ __forceinline__ int wave_incl_max_i32(int v) {
+  v = row_incl_max_i32(v);
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xA, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xC, 0xF, false));
+  return v;
+}
+// Inclusive min-scan from the right (lane i: minimum over lanes >= i) within
+// each 16-lane row (DPP row shift left; identity INT_MAX), and over the wave:
+// the first lane of a row then holds the row's minimum, read into scalars
+// and folded into the rows before it.
+__device__ __forceinline__ int row_incl_suffix_min_i32(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x101, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x102, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x104, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x108, 0xF, 0xF, false));
+  return v;
+}
+__device__ __forceinline__ int wave_incl_suffix_min_i32(int v) {
+  v = row_incl_suffix_min_i32(v);
+  const int r1 = __builtin_amdgcn_readlane(v, 16), r2 = __builtin_amdgcn_readlane(v, 32),
+            r3 = __builtin_amdgcn_readlane(v, 48);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int m23 = min(r2, r3);
+  const int after = lane < 16 ? min(r1, m23) : (lane < 32 ? m23 : (lane < 48 ? r3 : INT_MAX));
+  return min(v, after);
+}
+
 template <int T, int E, int B>
 struct BlockDigitRank {
   static_assert(T % WAVE == 0, "whole waves");

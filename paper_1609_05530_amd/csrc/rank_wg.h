@@ -355,14 +355,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     hmin = head ? min(hmin, p0 + j) : hmin;
   }
   // exclusive max-scan from the left and min-scan from the right
-  int imax = hmax, imin = hmin;
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const int a = __shfl_up(imax, off, WAVE);
-    const int b = __shfl_down(imin, off, WAVE);
-    if (lane >= off) imax = max(imax, a);
-    if (lane + off < WAVE) imin = min(imin, b);
-  }
+  const int imax = wave_incl_max_i32(hmax);
+  const int imin = wave_incl_suffix_min_i32(hmin);
   if (lane == WAVE - 1) sm.wmax()[w] = imax;
   if (lane == 0) sm.wmin()[w] = imin;
   int cl = __shfl_up(imax, 1, WAVE);
@@ -370,8 +364,16 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   if (lane == 0) cl = -1;
   if (lane == WAVE - 1) cr = INT_MAX;
   __syncthreads();
-  for (int k = 0; k < w; ++k) cl = max(cl, sm.wmax()[k]);
-  for (int k = w + 1; k < W; ++k) cr = min(cr, sm.wmin()[k]);
+  {
+    // the waves before (max) and after (min) this one: every lane of row 0
+    // reads one wave's value, scanned across the row
+    static_assert(W <= 16, "wave values fit one DPP row");
+    const int a = row_incl_max_i32(lane < W ? sm.wmax()[lane] : INT_MIN);
+    const int b = row_incl_suffix_min_i32(lane < W ? sm.wmin()[lane] : INT_MAX);
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    if (wu > 0) cl = max(cl, __builtin_amdgcn_readlane(a, wu - 1));
+    if (wu + 1 < W) cr = min(cr, __builtin_amdgcn_readlane(b, wu + 1));
+  }
   cr = min(cr, n);
   uint32_t lb[E], ub[E];
   {
