@@ -67,18 +67,6 @@ struct RankLds {
 };
 static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
 
-template <typename U>
-__device__ __forceinline__ U wave_and(U v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v &= __shfl_xor(v, off, WAVE);
-  return v;
-}
-template <typename U>
-__device__ __forceinline__ U wave_or(U v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, WAVE);
-  return v;
-}
 
 // Ranks one margin and writes, per row of the subset, R (and the sorted
 // position e and tie-group start lb). Returns true (in every thread) if the
@@ -152,8 +140,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
       khi[j] = (uint32_t)(k >> 32);
     }
   }
-  kand = wave_and(kand);
-  kor = wave_or(kor);
+  kand = ((uint64_t)wave_and_u32((uint32_t)(kand >> 32)) << 32) | wave_and_u32((uint32_t)kand);
+  kor = ((uint64_t)wave_or_u32((uint32_t)(kor >> 32)) << 32) | wave_or_u32((uint32_t)kor);
   __syncthreads();  // andor initialised; previous margin's LDS use finished
   if (lane == 0) {
     atomicAnd(&andor[0], (uint32_t)kand);
