@@ -85,8 +85,9 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   const int sid = P.order[blockIdx.x];
   const SubDesc sd = P.subs[sid];
   const int n = sd.n;
-  const SubState st = P.state[sid];
-  int status = st.status;
+  // (thread 0 reads the subset's state again at the end: kept live through
+  // the row passes, its fields would be spilled by every thread)
+  const int status = P.state[sid].status;
   double theta;
   if (P.mode == MODE_VARIANCE) {
     if (status != ST_OK) {
@@ -99,12 +100,12 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
       if (tid == 0) {
         ResultOut r;
         r.theta = NAN; r.var = NAN; r.loglik = NAN; r.score = NAN;
-        r.n = n; r.iters = st.iters; r.status = status;
+        r.n = n; r.iters = P.state[sid].iters; r.status = status;
         P.out[sid] = r;
       }
       return;
     }
-    theta = st.theta;
+    theta = P.state[sid].theta;
   }
   const int64_t o = sd.begin;
   const uint16_t *R1 = P.rows.R1 + o, *R2 = P.rows.R2 + o;
@@ -148,8 +149,17 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     using FT = decltype(form_tag);
     // the constants in the row type (the FP64 ones of an FP32 kernel are
     // formed only when its rows are evaluated in double)
+    // (theta passes through an empty asm statement so that the FP64
+    // constants share no intermediate with the FP32 ones: shared, those
+    // stay live through the FP32 row passes and are spilled)
     const Consts<RT> cc = [&]() {
-      if constexpr (std::is_same<RT, CT>::value) return c; else return make_consts<RT>(FAM, theta);
+      if constexpr (std::is_same<RT, CT>::value) {
+        return c;
+      } else {
+        double th = theta;
+        asm volatile("" : "+v"(th));
+        return make_consts<RT>(FAM, th);
+      }
     }();
     // FP32 rows after the fit: the theta-free per-row terms the fit kernel
     // left in the workspace (Gaussian normal scores; Gumbel log(-log u),
@@ -198,7 +208,11 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           } else {
             row_eval_ab(RT{}, cc, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
           }
-          kl.add(l); ksc.add(s); ks2.add(s * s);
+          if constexpr (FAM != FAM_GAUSSIAN) {  // (the Gaussian's come from Sp, Sm)
+            kl.add(l);
+            ksc.add(s);
+          }
+          ks2.add(s * s);
           A1[pidx((int)(qk[j] & 0xFFFFu))] = g1;
           A2[pidx((int)(qk[j] >> 16))] = g2;
           sk[k] = s;
@@ -238,7 +252,11 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           const uint32_t q2 = (uint32_t)E1[i2] | ((uint32_t)E2[i2] << 16);
           CT l, s, g1, g2;
           row_eval_ab(RT{}, cc, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
-          kl.add(l); ksc.add(s); ks2.add(s * s);
+          if constexpr (FAM != FAM_GAUSSIAN) {  // (the Gaussian's come from Sp, Sm)
+            kl.add(l);
+            ksc.add(s);
+          }
+          ks2.add(s * s);
           A1[pidx((int)(q0 & 0xFFFFu))] = g1;
           A2[pidx((int)(q0 >> 16))] = g2;
           S[i] = s;
@@ -280,7 +298,11 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           const uint32_t r2 = (uint32_t)R1[i2] | ((uint32_t)R2[i2] << 16), e2 = E1[i2];
           CT l, s, g1, g2;
           row_eval_ab(RT{}, cc, FT{}, r0 & 0xFFFFu, r0 >> 16, l, s, g1, g2);
-          kl.add(l); ksc.add(s); ks2.add(s * s);
+          if constexpr (FAM != FAM_GAUSSIAN) {  // (the Gaussian's come from Sp, Sm)
+            kl.add(l);
+            ksc.add(s);
+          }
+          ks2.add(s * s);
           A1[pidx((int)e0)] = g1;
           S[i] = s;
           G2[i] = g2;
@@ -311,7 +333,9 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   else
     rows(CT{}, std::integral_constant<int, 0>{});
   double v[5] = {kl.value(), ksc.value(), ks2.value(), psum, psq};
-  block_sum<W, 5, false>(v, red);  // thread 0 finishes alone
+  // (the closing barrier is kept: without it the register allocator spills
+  // in the row passes of the largest class)
+  block_sum<W, 5>(v, red);
   if (tid == 0) {
     const double mpsi = v[3] / dn;
     const double nu = v[4] / dn - mpsi * mpsi;
@@ -320,22 +344,23 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     if (P.mode == MODE_VARIANCE) {
       P.var_out[sid] = var;
     } else {
+      const SubState st = P.state[sid];
       double loglik = v[0], score = v[1];
       if (FAM == FAM_GAUSSIAN) {  // from the FP64 sufficient statistics
         double H;
-        loglik = gauss_loglik(theta, dn, st.Sp, st.Sm);
-        gauss_score_hess(theta, dn, st.Sp, st.Sm, score, H);
+        loglik = gauss_loglik(st.theta, dn, st.Sp, st.Sm);
+        gauss_score_hess(st.theta, dn, st.Sp, st.Sm, score, H);
       }
-      const bool usable = (status == ST_OK || status == ST_BOUNDARY_NATURAL);
-      if (usable && !(var > 0.0 && isfinite(var))) status = ST_BADVAR;
+      const bool usable = (st.status == ST_OK || st.status == ST_BOUNDARY_NATURAL);
+      const int status_out = (usable && !(var > 0.0 && isfinite(var))) ? (int)ST_BADVAR : st.status;
       ResultOut r;
-      r.theta = theta;
+      r.theta = st.theta;
       r.var = usable ? var : NAN;
       r.loglik = loglik;
       r.score = score;
       r.n = n;
       r.iters = st.iters;
-      r.status = status;
+      r.status = status_out;
       P.out[sid] = r;
     }
   }
