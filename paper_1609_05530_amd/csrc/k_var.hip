@@ -166,14 +166,15 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     // log(-log v)), computed there by the same FP32 code
     constexpr bool ZFAM = FAM != FAM_FRANK && std::is_same<RT, float>::value && sizeof(CT) == 4;
     [[maybe_unused]] const bool zcache = ZFAM && P.mode == MODE_FIT;
-    if constexpr (TWO && sizeof(CT) == 4 && std::is_same<RT, float>::value) {
-      // FP32 rows: a thread's rows i = tid + k*T live in registers. Their
+    if constexpr (TWO && sizeof(CT) == 4) {
+      // FP32 results (rows evaluated in FP32, or in FP64 near the family
+      // boundaries): a thread's rows i = tid + k*T live in registers. Their
       // loads are issued H rows at a time (H sized so that the rows in flight
       // fit 128 VGPRs), the score s stays in a register
       // until the psi pass, and the loads of the tie-group starts for that
       // pass are issued before the suffix sums, so the workgroup waits on
       // HBM a few times per phase instead of once per row.
-      constexpr int HF = FAM == FAM_FRANK ? 2 : 4;
+      constexpr int HF = std::is_same<RT, double>::value ? 1 : (FAM == FAM_FRANK ? 2 : 4);
       constexpr int H = E < HF ? E : HF;
       const int last = n - 1;
       const float2* ZC = (const float2*)P.rows.G + o;
