@@ -180,17 +180,23 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
       const float2* ZC = (const float2*)P.rows.G + o;
       const bool need_r = !zcache || FAM == FAM_GUMBEL;
       float sk[E];
+      uint32_t qk[E], rk[E];
+      float2 zk[ZFAM ? E : 1];
+      // rows h .. h+H-1 (h a constant after unrolling)
+      auto load_rows = [&](int h) {
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          const int k = h + j;
+          const int i = min(tid + k * T, last);
+          qk[k] = (uint32_t)E1[i] | ((uint32_t)E2[i] << 16);
+          rk[k] = need_r ? ((uint32_t)R1[i] | ((uint32_t)R2[i] << 16)) : 0u;
+          if constexpr (ZFAM) zk[k] = zcache ? ZC[i] : make_float2(0.f, 0.f);
+        }
+      };
+      load_rows(0);
 #pragma unroll
       for (int h = 0; h < E; h += H) {
-      uint32_t qk[H], rk[H];
-      float2 zk[ZFAM ? H : 1];
-#pragma unroll
-      for (int j = 0; j < H; ++j) {
-        const int i = min(tid + (h + j) * T, last);
-        qk[j] = (uint32_t)E1[i] | ((uint32_t)E2[i] << 16);
-        rk[j] = need_r ? ((uint32_t)R1[i] | ((uint32_t)R2[i] << 16)) : 0u;
-        if constexpr (ZFAM) zk[j] = zcache ? ZC[i] : make_float2(0.f, 0.f);
-      }
+      if (h + H < E) load_rows(h + H);  // the next rows are in flight while these are evaluated
 #pragma unroll
       for (int j = 0; j < H; ++j) {
         const int k = h + j;
@@ -200,22 +206,22 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           if constexpr (ZFAM) {
             if (zcache) {
               if constexpr (FAM == FAM_GUMBEL)
-                gumbel_rfull<CT>(c, rk[j] & 0xFFFFu, rk[j] >> 16, twon1, inv, zk[j].x, zk[j].y, l, s, g1, g2);
+                gumbel_rfull<CT>(c, rk[k] & 0xFFFFu, rk[k] >> 16, twon1, inv, zk[k].x, zk[k].y, l, s, g1, g2);
               else
-                gauss_rfull<CT>(c, zk[j].x, zk[j].y, l, s, g1, g2);
+                gauss_rfull<CT>(c, zk[k].x, zk[k].y, l, s, g1, g2);
             } else {
-              row_eval_ab(RT{}, cc, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
+              row_eval_ab(RT{}, cc, FT{}, rk[k] & 0xFFFFu, rk[k] >> 16, l, s, g1, g2);
             }
           } else {
-            row_eval_ab(RT{}, cc, FT{}, rk[j] & 0xFFFFu, rk[j] >> 16, l, s, g1, g2);
+            row_eval_ab(RT{}, cc, FT{}, rk[k] & 0xFFFFu, rk[k] >> 16, l, s, g1, g2);
           }
           if constexpr (FAM != FAM_GAUSSIAN) {  // (the Gaussian's come from Sp, Sm)
             kl.add(l);
             ksc.add(s);
           }
           ks2.add(s * s);
-          A1[pidx((int)(qk[j] & 0xFFFFu))] = g1;
-          A2[pidx((int)(qk[j] >> 16))] = g2;
+          A1[pidx((int)(qk[k] & 0xFFFFu))] = g1;
+          A2[pidx((int)(qk[k] >> 16))] = g2;
           sk[k] = s;
         }
       }
