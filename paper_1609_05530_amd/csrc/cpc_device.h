@@ -85,6 +85,42 @@ __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
   return v;
 }
+// DPP move of a double (each 32-bit half; lanes without a source read 0.0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                          __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+// Sum over the lanes of a wave, left in the last lane (inclusive scan: row
+// shifts right, then each row's last lane carried into the rows after it).
+__device__ __forceinline__ double wave_sum_last(double v) {
+  v += dpp_f64<0x111, 0xF>(v);
+  v += dpp_f64<0x112, 0xF>(v);
+  v += dpp_f64<0x114, 0xF>(v);
+  v += dpp_f64<0x118, 0xF>(v);
+  v += dpp_f64<0x142, 0xA>(v);
+  v += dpp_f64<0x143, 0xC>(v);
+  return v;
+}
+// Inclusive suffix sum over the lanes of a wave (lane i: sum over lanes >= i):
+// row shifts left within each row, then the totals of the later rows (the
+// first lane of each) added in.
+__device__ __forceinline__ double wave_incl_suffix_sum(double v) {
+  v += dpp_f64<0x101, 0xF>(v);
+  v += dpp_f64<0x102, 0xF>(v);
+  v += dpp_f64<0x104, 0xF>(v);
+  v += dpp_f64<0x108, 0xF>(v);
+  const double r1 = readlane_f64(v, 16), r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+  const int lane = threadIdx.x & (WAVE - 1);
+  const double r23 = r2 + r3;
+  const double after = lane < 16 ? r1 + r23 : (lane < 32 ? r23 : (lane < 48 ? r3 : 0.0));
+  return v + after;
+}
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
@@ -99,8 +135,8 @@ template <int W, int NV, bool TAIL = true>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0) {
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum_last(v[i]);
+  if (lane == WAVE - 1) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) scratch[w * NV + i] = v[i];
   }
@@ -134,12 +170,7 @@ __device__ __forceinline__ long long block_sum_ll(long long v, long long* scratc
 template <int W>
 __device__ __forceinline__ double block_excl_suffix(double v, double* scratch) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  double incl = v;
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const double x = __shfl_down(incl, off, WAVE);
-    if (lane + off < WAVE) incl += x;
-  }
+  const double incl = wave_incl_suffix_sum(v);
   if (lane == 0) scratch[w] = incl;
   __syncthreads();
   double carry = 0.0;
@@ -153,16 +184,7 @@ __device__ __forceinline__ double block_excl_suffix(double v, double* scratch) {
 template <int W>
 __device__ __forceinline__ void block_excl_suffix2(double va, double vb, double* scratch, double& ea, double& eb) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  double ia = va, ib = vb;
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const double xa = __shfl_down(ia, off, WAVE);
-    const double xb = __shfl_down(ib, off, WAVE);
-    if (lane + off < WAVE) {
-      ia += xa;
-      ib += xb;
-    }
-  }
+  const double ia = wave_incl_suffix_sum(va), ib = wave_incl_suffix_sum(vb);
   if (lane == 0) {
     scratch[w] = ia;
     scratch[W + w] = ib;
