@@ -121,6 +121,23 @@ __device__ __forceinline__ double wave_incl_suffix_sum(double v) {
   const double after = lane < 16 ? r1 + r23 : (lane < 32 ? r23 : (lane < 48 ? r3 : 0.0));
   return v + after;
 }
+// Sum of 64-bit integers over the lanes of a wave, left in the last lane
+// (exact, so the same value as any other order).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ long long dpp_i64(long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(uint64_t)v, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)((uint64_t)v >> 32), CTRL, ROWS, 0xF, false);
+  return (long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ long long wave_sum_ll_last(long long v) {
+  v += dpp_i64<0x111, 0xF>(v);
+  v += dpp_i64<0x112, 0xF>(v);
+  v += dpp_i64<0x114, 0xF>(v);
+  v += dpp_i64<0x118, 0xF>(v);
+  v += dpp_i64<0x142, 0xA>(v);
+  v += dpp_i64<0x143, 0xC>(v);
+  return v;
+}
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
@@ -155,8 +172,8 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
 template <int W, bool TAIL = true>
 __device__ __forceinline__ long long block_sum_ll(long long v, long long* scratch) {
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
-  v = wave_sum_ll(v);
-  if (lane == 0) scratch[w] = v;
+  v = wave_sum_ll_last(v);
+  if (lane == WAVE - 1) scratch[w] = v;
   __syncthreads();
   long long a = 0;
   if (threadIdx.x == 0)

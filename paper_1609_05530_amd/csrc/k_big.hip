@@ -91,11 +91,7 @@ __global__ void __launch_bounds__(256) k_big_scan(BigParams P, uint32_t* hist) {
     *hp = run;
     run += c;
   }
-  uint32_t incl = run;
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const uint32_t x = __shfl_up(incl, off, WAVE);
-    if (lane >= off) incl += x;
-  }
+  const uint32_t incl = wave_incl_sum_u32(run);
   if (lane == WAVE - 1) wt[w] = incl;
   __syncthreads();
   uint32_t base = incl - run;

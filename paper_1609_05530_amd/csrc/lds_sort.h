@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "block_rank.h"
 #include "cpc_device.h"
 
 namespace cpc {
@@ -65,12 +66,7 @@ __device__ __forceinline__ void lds_multisplit(const uint32_t (&d)[E], int n, in
       if (run == (uint32_t)n) dtot[256 + (pass & 1)] = 1u;
     }
   }
-  uint32_t incl = local;
-#pragma unroll
-  for (int off = 1; off < WAVE; off <<= 1) {
-    const uint32_t t = __shfl_up(incl, off, WAVE);
-    if (lane >= off) incl += t;
-  }
+  const uint32_t incl = wave_incl_sum_u32(local);
   if (tid < NT && lane == WAVE - 1) dtot[258 + w] = incl;
   __syncthreads();
   if (tid < NT) {
