@@ -107,6 +107,31 @@ __device__ __forceinline__ double wave_sum_last(double v) {
   v += dpp_f64<0x143, 0xC>(v);
   return v;
 }
+// Inclusive sum and inclusive suffix sum within each 16-lane row.
+__device__ __forceinline__ double row_incl_sum_f64(double v) {
+  v += dpp_f64<0x111, 0xF>(v);
+  v += dpp_f64<0x112, 0xF>(v);
+  v += dpp_f64<0x114, 0xF>(v);
+  v += dpp_f64<0x118, 0xF>(v);
+  return v;
+}
+__device__ __forceinline__ double row_incl_suffix_sum_f64(double v) {
+  v += dpp_f64<0x101, 0xF>(v);
+  v += dpp_f64<0x102, 0xF>(v);
+  v += dpp_f64<0x104, 0xF>(v);
+  v += dpp_f64<0x108, 0xF>(v);
+  return v;
+}
+// The waves' totals after wave w (scratch[k] holds wave k's), in every lane:
+// lane k < W of each wave reads scratch[k], summed from the right in row 0.
+template <int W>
+__device__ __forceinline__ double waves_after(const double* scratch, int w) {
+  static_assert(W <= 16, "wave totals fit one DPP row");
+  const int lane = threadIdx.x & (WAVE - 1);
+  const double s = row_incl_suffix_sum_f64(lane < W ? scratch[lane] : 0.0);
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  return wu + 1 < W ? readlane_f64(s, wu + 1) : 0.0;
+}
 // Inclusive suffix sum over the lanes of a wave (lane i: sum over lanes >= i):
 // row shifts left within each row, then the totals of the later rows (the
 // first lane of each) added in.
@@ -158,13 +183,11 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* scratch) {
     for (int i = 0; i < NV; ++i) scratch[w * NV + i] = v[i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  static_assert(W <= 16, "wave partials fit one DPP row");
+  if (w == 0) {  // wave 0 sums the W partials (lane k reads wave k's) in row 0
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double a = 0.0;
-      for (int k = 0; k < W; ++k) a += scratch[k * NV + i];
-      v[i] = a;
-    }
+    for (int i = 0; i < NV; ++i)
+      v[i] = readlane_f64(row_incl_sum_f64(lane < W ? scratch[lane * NV + i] : 0.0), W - 1);
   }
   if (TAIL) __syncthreads();
 }
@@ -190,8 +213,7 @@ __device__ __forceinline__ double block_excl_suffix(double v, double* scratch) {
   const double incl = wave_incl_suffix_sum(v);
   if (lane == 0) scratch[w] = incl;
   __syncthreads();
-  double carry = 0.0;
-  for (int k = W - 1; k > w; --k) carry += scratch[k];
+  const double carry = waves_after<W>(scratch, w);
   __syncthreads();
   return incl + carry - v;
 }
@@ -207,11 +229,7 @@ __device__ __forceinline__ void block_excl_suffix2(double va, double vb, double*
     scratch[W + w] = ib;
   }
   __syncthreads();
-  double ca = 0.0, cb = 0.0;
-  for (int k = W - 1; k > w; --k) {
-    ca += scratch[k];
-    cb += scratch[W + k];
-  }
+  const double ca = waves_after<W>(scratch, w), cb = waves_after<W>(scratch + W, w);
   __syncthreads();
   ea = ia + ca - va;
   eb = ib + cb - vb;
