@@ -54,38 +54,48 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
   if (P.state[sid].status != ST_OK) return;  // uniform: set by the rank kernel
   const SubDesc sd = P.subs[sid];
   const int n = sd.n;
-  const uint16_t* R1 = P.rows.R1 + sd.begin;
-  const uint16_t* R2 = P.rows.R2 + sd.begin;
   const uint32_t twon1 = 2u * (uint32_t)(n + 1);
   const CT inv = (CT)1 / (CT)twon1;
   const double dn = (double)n;
 
-  // Rows i = tid + k*T: all of a thread's rank loads are issued before any is
-  // used (the loop body is too short to hide HBM latency otherwise).
-  constexpr int E = CAP / T;
-  uint32_t rab[E];
+  // The ranks are read as aligned 32-bit words (two rows each: the subset
+  // spans at most CAP/2 + 1 words; a row of a word outside the subset is
+  // skipped), all of a thread's words issued before any is used (the loop
+  // body is too short to hide HBM latency otherwise). The rank arrays start
+  // 256-byte aligned and are padded to a multiple of 256 bytes, so every word
+  // read lies inside them.
+  constexpr int EW = (CAP / 2 + T) / T;
+  const int64_t wlo = sd.begin >> 1;
+  const int nw = (int)(((sd.begin + n + 1) >> 1) - wlo);
+  const int odd = (int)(sd.begin & 1);
+  const uint32_t* W1 = reinterpret_cast<const uint32_t*>(P.rows.R1) + wlo;
+  const uint32_t* W2 = reinterpret_cast<const uint32_t*>(P.rows.R2) + wlo;
+  uint32_t wa[EW], wb[EW];
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int ic = min(tid + k * T, n - 1);
-    rab[k] = (uint32_t)R1[ic] | ((uint32_t)R2[ic] << 16);
+  for (int k = 0; k < EW; ++k) {
+    const int j = min(tid + k * T, nw - 1);
+    wa[k] = W1[j];
+    wb[k] = W2[j];
   }
   long long sacc = 0;
 #pragma unroll
-  for (int k = 0; k < E; ++k) {
-    const int i = tid + k * T;
-    const uint32_t a = rab[k] & 0xFFFFu, b = rab[k] >> 16;
-    const long long term = ((long long)a - (n + 1)) * ((long long)b - (n + 1));
-    sacc += (i < n) ? term : 0ll;
-    if (i < n) {
-      if constexpr (SM::GC) {
-        CT lx, ly;
-        gumbel_lxy<CT>(a, b, twon1, inv, lx, ly);
-        sm.lx[i] = lx;
-        sm.ly[i] = ly;
-        // FP32 rows: also left in the workspace for the variance kernel
-        if constexpr (sizeof(CT) == 4) ((float2*)P.rows.G + sd.begin)[i] = make_float2(lx, ly);
-      } else {
-        sm.rr[i] = rab[k];
+  for (int k = 0; k < EW; ++k) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = 2 * (tid + k * T) + h - odd;  // row within the subset
+      if (i >= 0 && i < n) {
+        const uint32_t a = (wa[k] >> (16 * h)) & 0xFFFFu, b = (wb[k] >> (16 * h)) & 0xFFFFu;
+        sacc += ((long long)a - (n + 1)) * ((long long)b - (n + 1));
+        if constexpr (SM::GC) {
+          CT lx, ly;
+          gumbel_lxy<CT>(a, b, twon1, inv, lx, ly);
+          sm.lx[i] = lx;
+          sm.ly[i] = ly;
+          // FP32 rows: also left in the workspace for the variance kernel
+          if constexpr (sizeof(CT) == 4) ((float2*)P.rows.G + sd.begin)[i] = make_float2(lx, ly);
+        } else {
+          sm.rr[i] = a | (b << 16);
+        }
       }
     }
   }
