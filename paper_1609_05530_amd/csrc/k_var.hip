@@ -168,79 +168,109 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     [[maybe_unused]] const bool zcache = ZFAM && P.mode == MODE_FIT;
     if constexpr (TWO && sizeof(CT) == 4) {
       // FP32 results (rows evaluated in FP32, or in FP64 near the family
-      // boundaries): a thread's rows i = tid + k*T live in registers. Their
-      // loads are issued H rows at a time (H sized so that the rows in flight
-      // fit 128 VGPRs), the score s stays in a register
-      // until the psi pass, and the loads of the tie-group starts for that
-      // pass are issued before the suffix sums, so the workgroup waits on
-      // HBM a few times per phase instead of once per row.
-      constexpr int HF = std::is_same<RT, double>::value ? 1 : (FAM == FAM_FRANK ? 2 : 4);
-      constexpr int H = E < HF ? E : HF;
-      const int last = n - 1;
+      // boundaries): a thread's rows live in registers. The 16-bit row arrays
+      // are read as aligned 32-bit words, two rows each (word j of the
+      // subset's span, rows 2j - odd and 2j + 1 - odd; the span is at most
+      // CAP/2 + 1 words, and the arrays start 256-byte aligned and are padded
+      // to a multiple of 256 bytes, so every word read lies inside them);
+      // thread t takes words t, t + T, ... Their loads are issued H words at a
+      // time, the next H in flight while the current ones are evaluated (H
+      // sized so that the rows in flight fit 128 VGPRs); the score s stays in
+      // a register until the psi pass, and the tie-group starts for that pass
+      // are loaded before the suffix sums.
+      constexpr int EW = (CAP / 2 + T) / T;
+      constexpr int HF = (std::is_same<RT, double>::value || FAM == FAM_FRANK) ? 1 : 2;
+      constexpr int H = EW < HF ? EW : HF;
+      const int64_t wlo = o >> 1;
+      const int nw = (int)(((o + n + 1) >> 1) - wlo);
+      const int odd = (int)(o & 1);
+      auto words = [&](const uint16_t* base) { return reinterpret_cast<const uint32_t*>(base) + wlo; };
+      const uint32_t *WE1 = words(P.rows.E1), *WE2 = words(P.rows.E2);
+      const uint32_t *WR1 = words(P.rows.R1), *WR2 = words(P.rows.R2);
+      const uint32_t *WL1 = words(P.rows.L1), *WL2 = words(P.rows.L2);
       const float2* ZC = (const float2*)P.rows.G + o;
       const bool need_r = !zcache || FAM == FAM_GUMBEL;
-      float sk[E];
-      uint32_t qk[E], rk[E];
-      float2 zk[ZFAM ? E : 1];
-      // rows h .. h+H-1 (h a constant after unrolling)
-      auto load_rows = [&](int h) {
+      float sk[2 * EW];
+      uint32_t qa[EW], qb[EW], ra[EW], rb[EW];
+      float2 zk[ZFAM ? 2 * EW : 1];
+      // words h .. h+H-1 (h a constant after unrolling)
+      auto load_words = [&](int h) {
 #pragma unroll
         for (int j = 0; j < H; ++j) {
           const int k = h + j;
-          const int i = min(tid + k * T, last);
-          qk[k] = (uint32_t)E1[i] | ((uint32_t)E2[i] << 16);
-          rk[k] = need_r ? ((uint32_t)R1[i] | ((uint32_t)R2[i] << 16)) : 0u;
-          if constexpr (ZFAM) zk[k] = zcache ? ZC[i] : make_float2(0.f, 0.f);
+          const int wj = min(tid + k * T, nw - 1);
+          qa[k] = WE1[wj];
+          qb[k] = WE2[wj];
+          ra[k] = need_r ? WR1[wj] : 0u;
+          rb[k] = need_r ? WR2[wj] : 0u;
+          if constexpr (ZFAM) {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+              const int i = min(max(2 * wj + hh - odd, 0), n - 1);
+              zk[2 * k + hh] = zcache ? ZC[i] : make_float2(0.f, 0.f);
+            }
+          }
         }
       };
-      load_rows(0);
+      load_words(0);
 #pragma unroll
-      for (int h = 0; h < E; h += H) {
-      if (h + H < E) load_rows(h + H);  // the next rows are in flight while these are evaluated
+      for (int h = 0; h < EW; h += H) {
+      if (h + H < EW) load_words(h + H);  // the next words are in flight while these are evaluated
 #pragma unroll
       for (int j = 0; j < H; ++j) {
         const int k = h + j;
-        sk[k] = 0.f;
-        if (tid + k * T < n) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+        const int m = 2 * k + hh;
+        const int i = 2 * (tid + k * T) + hh - odd;  // row within the subset
+        sk[m] = 0.f;
+        if (i >= 0 && i < n) {
+          const uint32_t a = (ra[k] >> (16 * hh)) & 0xFFFFu, b = (rb[k] >> (16 * hh)) & 0xFFFFu;
           CT l, s, g1, g2;
           if constexpr (ZFAM) {
             if (zcache) {
               if constexpr (FAM == FAM_GUMBEL)
-                gumbel_rfull<CT>(c, rk[k] & 0xFFFFu, rk[k] >> 16, twon1, inv, zk[k].x, zk[k].y, l, s, g1, g2);
+                gumbel_rfull<CT>(c, a, b, twon1, inv, zk[m].x, zk[m].y, l, s, g1, g2);
               else
-                gauss_rfull<CT>(c, zk[k].x, zk[k].y, l, s, g1, g2);
+                gauss_rfull<CT>(c, zk[m].x, zk[m].y, l, s, g1, g2);
             } else {
-              row_eval_ab(RT{}, cc, FT{}, rk[k] & 0xFFFFu, rk[k] >> 16, l, s, g1, g2);
+              row_eval_ab(RT{}, cc, FT{}, a, b, l, s, g1, g2);
             }
           } else {
-            row_eval_ab(RT{}, cc, FT{}, rk[k] & 0xFFFFu, rk[k] >> 16, l, s, g1, g2);
+            row_eval_ab(RT{}, cc, FT{}, a, b, l, s, g1, g2);
           }
           if constexpr (FAM != FAM_GAUSSIAN) {  // (the Gaussian's come from Sp, Sm)
             kl.add(l);
             ksc.add(s);
           }
           ks2.add(s * s);
-          A1[pidx((int)(qk[k] & 0xFFFFu))] = g1;
-          A2[pidx((int)(qk[k] >> 16))] = g2;
-          sk[k] = s;
+          A1[pidx((int)((qa[k] >> (16 * hh)) & 0xFFFFu))] = g1;
+          A2[pidx((int)((qb[k] >> (16 * hh)) & 0xFFFFu))] = g2;
+          sk[m] = s;
+        }
         }
       }
       }
-      uint32_t lk[E];
+      uint32_t la[EW], lb[EW];
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const int i = min(tid + k * T, last);
-        lk[k] = (uint32_t)L1[i] | ((uint32_t)L2[i] << 16);
+      for (int k = 0; k < EW; ++k) {
+        const int wj = min(tid + k * T, nw - 1);
+        la[k] = WL1[wj];
+        lb[k] = WL2[wj];
       }
       __syncthreads();
       lds_suffix_sum2<T, E, CT>(A1, A2, n, red);
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        if (tid + k * T < n) {
-          const double psi = (double)sk[k] +
-                             ((double)A1[pidx((int)(lk[k] & 0xFFFFu))] + (double)A2[pidx((int)(lk[k] >> 16))]) * idn;
-          psum += psi;
-          psq += psi * psi;
+      for (int k = 0; k < EW; ++k) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int i = 2 * (tid + k * T) + hh - odd;
+          if (i >= 0 && i < n) {
+            const int q1 = (int)((la[k] >> (16 * hh)) & 0xFFFFu), q2 = (int)((lb[k] >> (16 * hh)) & 0xFFFFu);
+            const double psi = (double)sk[2 * k + hh] + ((double)A1[pidx(q1)] + (double)A2[pidx(q2)]) * idn;
+            psum += psi;
+            psq += psi * psi;
+          }
         }
       }
     } else if constexpr (TWO) {
