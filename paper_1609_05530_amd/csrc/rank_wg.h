@@ -391,14 +391,27 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     xl[pay[j]] = (uint16_t)l;
   }
   __syncthreads();
-  for (int i = t; i < n; i += T) {
-    const uint32_t v = xk[i];
-    if (R32) {
-      R32[i] = v & 0xFFFFu;
-    } else {
-      Rg[i] = (uint16_t)(v & 0xFFFFu);
-      Eg[i] = (uint16_t)(v >> 16);
-      Lg[i] = xl[i];
+  if (R32) {
+    for (int i = t; i < n; i += T) R32[i] = xk[i] & 0xFFFFu;
+  } else {
+    // 32-bit stores of row pairs that start at an even row of the arrays (the
+    // three arrays share that parity); a first or last row without its pair
+    // is stored alone, so no store touches another subset's rows
+    const int odd = (int)((reinterpret_cast<uintptr_t>(Rg) >> 1) & 1u);
+    const int npair = (n - odd) >> 1;
+    for (int q = t; q < npair; q += T) {
+      const int i = odd + 2 * q;
+      const uint32_t v0 = xk[i], v1 = xk[i + 1];
+      *reinterpret_cast<uint32_t*>(Rg + i) = (v0 & 0xFFFFu) | (v1 << 16);
+      *reinterpret_cast<uint32_t*>(Eg + i) = (v0 >> 16) | (v1 & 0xFFFF0000u);
+      *reinterpret_cast<uint32_t*>(Lg + i) = (uint32_t)xl[i] | ((uint32_t)xl[i + 1] << 16);
+    }
+    const int single = (t == 0 && odd) ? 0 : ((t == T - 1 && odd + 2 * npair < n) ? n - 1 : -1);
+    if (single >= 0) {
+      const uint32_t v = xk[single];
+      Rg[single] = (uint16_t)(v & 0xFFFFu);
+      Eg[single] = (uint16_t)(v >> 16);
+      Lg[single] = xl[single];
     }
   }
   __syncthreads();
