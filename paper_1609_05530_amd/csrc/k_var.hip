@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
       const uint32_t *WE1 = words(P.rows.E1), *WE2 = words(P.rows.E2);
       const uint32_t *WR1 = words(P.rows.R1), *WR2 = words(P.rows.R2);
       const uint32_t *WL1 = words(P.rows.L1), *WL2 = words(P.rows.L2);
-      const float2* ZC = (const float2*)P.rows.G + o;
+      const float4* ZC4 = reinterpret_cast<const float4*>(P.rows.G);
       const bool need_r = !zcache || FAM == FAM_GUMBEL;
       float sk[2 * EW];
       uint32_t qa[EW], qb[EW], ra[EW], rb[EW];
@@ -204,11 +204,11 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           ra[k] = need_r ? WR1[wj] : 0u;
           rb[k] = need_r ? WR2[wj] : 0u;
           if constexpr (ZFAM) {
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-              const int i = min(max(2 * wj + hh - odd, 0), n - 1);
-              zk[2 * k + hh] = zcache ? ZC[i] : make_float2(0.f, 0.f);
-            }
+            // the word's two rows are rows 2(wlo + wj) and 2(wlo + wj) + 1 of
+            // the 8-byte-per-row cache: one aligned 16-byte load
+            const float4 z = zcache ? ZC4[wlo + wj] : make_float4(0.f, 0.f, 0.f, 0.f);
+            zk[2 * k] = make_float2(z.x, z.y);
+            zk[2 * k + 1] = make_float2(z.z, z.w);
           }
         }
       };
