@@ -110,7 +110,12 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   const int64_t o = sd.begin;
   const uint16_t *R1 = P.rows.R1 + o, *R2 = P.rows.R2 + o;
   const uint16_t *E1 = P.rows.E1 + o, *E2 = P.rows.E2 + o;
-  const uint16_t *L1 = P.rows.L1 + o, *L2 = P.rows.L2 + o;
+  // a margin without ties stored only the sorted positions, which are then
+  // also the group starts
+  const int eqm = P.state[sid].eqmask;
+  const uint16_t* L1base = (eqm & 1) ? P.rows.E1 : P.rows.L1;
+  const uint16_t* L2base = (eqm & 2) ? P.rows.E2 : P.rows.L2;
+  const uint16_t *L1 = L1base + o, *L2 = L2base + o;
   const uint32_t twon1 = 2u * (uint32_t)(n + 1);
   const CT inv = (CT)1 / (CT)twon1;
   const double dn = (double)n;
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
       auto words = [&](const uint16_t* base) { return reinterpret_cast<const uint32_t*>(base) + wlo; };
       const uint32_t *WE1 = words(P.rows.E1), *WE2 = words(P.rows.E2);
       const uint32_t *WR1 = words(P.rows.R1), *WR2 = words(P.rows.R2);
-      const uint32_t *WL1 = words(P.rows.L1), *WL2 = words(P.rows.L2);
+      const uint32_t *WL1 = words(L1base), *WL2 = words(L2base);
       const float4* ZC4 = reinterpret_cast<const float4*>(P.rows.G);
       const bool need_r = !zcache || FAM == FAM_GUMBEL;
       float sk[2 * EW];

@@ -19,6 +19,10 @@ struct SubState {
   double theta;
   double Sp, Sm;  // Gaussian sufficient statistics
   int32_t status, iters;
+  // bit m (margin x: 0, y: 1): every row's sorted position equals its
+  // tie-group start (no ties, or ties in row order), and only the positions
+  // were stored (set by the rank kernel)
+  int32_t eqmask, pad;
 };
 
 // Size classes of the workgroup-per-subset kernels: (threads, items per

@@ -63,6 +63,9 @@ struct RankLds {
   __device__ __forceinline__ int32_t* wmax() { return (int32_t*)(ALIAS ? small() + W : cnt()); }
   __device__ __forceinline__ int32_t* wmin() { return wmax() + W; }
   __device__ __forceinline__ uint32_t* wl() { return (uint32_t*)(wmax() + 2 * W); }
+  // per-wave "has a tie" votes (counter region, free after the passes;
+  // unaliased layout only)
+  __device__ __forceinline__ int32_t* wflag() { return wmax() + 2 * W + W * KW; }
   __device__ __forceinline__ uint32_t* andor() { return ALIAS ? small() + 3 * W + W * KW : xv32(); }
 };
 static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
@@ -75,7 +78,7 @@ static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024,
 template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
                                                 RankLds<T, E, B, KW, ALIAS, P32, PAD>& sm, uint16_t* Rg, uint16_t* Eg,
-                                                uint16_t* Lg, uint32_t* R32, bool& all_tied) {
+                                                uint16_t* Lg, uint32_t* R32, bool& all_tied, bool& e_is_l) {
   using Rank = BlockDigitRank<T, E, B>;
   using Lds = RankLds<T, E, B, KW, ALIAS, P32, PAD>;
   constexpr int W = T / WAVE;
@@ -87,6 +90,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   uint32_t* xk = sm.xk();
   uint32_t* andor = sm.andor();
   all_tied = false;
+  e_is_l = false;
   if (n <= 0) return false;
 
   // load, keys, non-finite flag, AND / OR of the keys. 32-bit keys are read
@@ -347,6 +351,14 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   const int imin = wave_incl_suffix_min_i32(hmin);
   if (lane == WAVE - 1) sm.wmax()[w] = imax;
   if (lane == 0) sm.wmin()[w] = imin;
+  // does any valid item continue a tie group? (then the sorted positions
+  // and the group starts differ and both are stored)
+  const uint32_t vmask = nv >= 32 ? 0xFFFFFFFFu : ((1u << nv) - 1u);
+  const bool tied_here = (headm & vmask) != vmask;
+  if constexpr (!ALIAS) {
+    const bool wtie = __ballot(tied_here) != 0ull;
+    if (lane == 0) sm.wflag()[w] = wtie ? 1 : 0;
+  }
   int cl = __shfl_up(imax, 1, WAVE);
   int cr = __shfl_down(imin, 1, WAVE);
   if (lane == 0) cl = -1;
@@ -362,6 +374,13 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     if (wu > 0) cl = max(cl, __builtin_amdgcn_readlane(a, wu - 1));
     if (wu + 1 < W) cr = min(cr, __builtin_amdgcn_readlane(b, wu + 1));
   }
+  // workgroup-uniform: every row's group start equals its sorted position
+  bool eq = false;
+  if constexpr (!ALIAS) {
+    const int f = lane < W ? sm.wflag()[lane] : 0;
+    eq = (ties == 1) || (__ballot(f != 0) == 0ull);
+  }
+  e_is_l = eq;
   cr = min(cr, n);
   uint32_t lb[E], ub[E];
   {
@@ -388,7 +407,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     const uint32_t R = (ties == 1) ? 2u * (e + 1u) : lb[j] + ub[j] + 1u;
     const uint32_t l = (ties == 1) ? e : lb[j];
     xk[pay[j]] = R | (e << 16);
-    xl[pay[j]] = (uint16_t)l;
+    if (!eq) xl[pay[j]] = (uint16_t)l;
   }
   __syncthreads();
   if (R32) {
@@ -404,14 +423,14 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
       const uint32_t v0 = xk[i], v1 = xk[i + 1];
       *reinterpret_cast<uint32_t*>(Rg + i) = (v0 & 0xFFFFu) | (v1 << 16);
       *reinterpret_cast<uint32_t*>(Eg + i) = (v0 >> 16) | (v1 & 0xFFFF0000u);
-      *reinterpret_cast<uint32_t*>(Lg + i) = (uint32_t)xl[i] | ((uint32_t)xl[i + 1] << 16);
+      if (!eq) *reinterpret_cast<uint32_t*>(Lg + i) = (uint32_t)xl[i] | ((uint32_t)xl[i + 1] << 16);
     }
     const int single = (t == 0 && odd) ? 0 : ((t == T - 1 && odd + 2 * npair < n) ? n - 1 : -1);
     if (single >= 0) {
       const uint32_t v = xk[single];
       Rg[single] = (uint16_t)(v & 0xFFFFu);
       Eg[single] = (uint16_t)(v >> 16);
-      Lg[single] = xl[single];
+      if (!eq) Lg[single] = xl[single];
     }
   }
   __syncthreads();
@@ -429,25 +448,26 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
       P.state[sid].status = ST_DEGENERATE;
       P.state[sid].iters = 0;
       P.state[sid].theta = NAN;
+      P.state[sid].eqmask = 0;
     }
     return;
   }
   const bool rk = P.mode == MODE_RANK;
-  bool t1, t2, b1, b2;
+  bool t1, t2, b1, b2, q1, q2;
   const int64_t o = sd.begin;
   if constexpr (KW == 2) {
     b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
-                                                     P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
+                                                     P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1);
     b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
-                                                     P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
+                                                     P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2);
   } else {
     const bool ik = P.int_keys != 0;
     const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
     const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
     b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
-                                                    P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1);
+                                                    P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1);
     b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
-                                                    P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2);
+                                                    P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2);
   }
   if (rk) return;
   const bool bad = b1 || b2;
@@ -456,6 +476,7 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
     P.state[sid].status = bad ? ST_NONFINITE : ((t1 || t2) ? ST_DEGENERATE : ST_OK);
     P.state[sid].iters = 0;
     P.state[sid].theta = NAN;
+    P.state[sid].eqmask = (q1 ? 1 : 0) | (q2 ? 2 : 0);
   }
 }
 

@@ -347,6 +347,34 @@ def test_big_ties_fit_and_variance(fam):
     compare(res32, sub, comb, "fp32c", fam, f"big ties {fam} fp32c")
 
 
+@pytest.mark.parametrize("fam", ["frank", "gumbel", "gaussian"])
+def test_ties_per_margin_workgroup_path(fam):
+    """Workgroup-path subsets with ties in x only, in y only, in both and in
+    neither (a margin without ties stores only its sorted positions, which
+    then also serve as the tie-group starts of the variance): estimates,
+    variances and log-likelihoods against the oracle, FP64 and FP32c."""
+    sizes = np.array([300, 1500, 5000, 12000, 16000, 2500, 9000, 700])
+    off = synth.offsets_from_sizes(sizes)
+    n = int(sizes.sum())
+    th = {"frank": 4.0, "gumbel": 2.0, "gaussian": 0.6}[fam]
+    x, y = synth.copula_pairs(fam, th, n, 91)
+    for m in range(len(sizes)):
+        a, b = off[m], off[m + 1]
+        if m % 4 in (0, 2):
+            x[a:b] = np.round(x[a:b] * 8) / 8
+        if m % 4 in (1, 2):
+            y[a:b] = np.round(y[a:b] * 4) / 4
+    sub, comb = O.fit(x, y, off, fam, nthreads=0)
+    res = to_np(cpc().fit(dev(x, torch.float64), dev(y, torch.float64), off, fam, prec="fp64"))
+    compare(res, sub, comb, "fp64", fam, f"ties per margin {fam}")
+    # FP32 storage: the oracle sees the same rounded values (rounding may tie
+    # values of the continuous margins as well)
+    x32, y32 = x.astype(np.float32), y.astype(np.float32)
+    sub32, comb32 = O.fit(x32.astype(np.float64), y32.astype(np.float64), off, fam, nthreads=0)
+    res32 = to_np(cpc().fit(dev(x32, torch.float32), dev(y32, torch.float32), off, fam, prec="fp32c"))
+    compare(res32, sub32, comb32, "fp32c", fam, f"ties per margin {fam} fp32c")
+
+
 def test_big_statuses():
     z = np.arange(20000, dtype=np.float64)
     rng = np.random.default_rng(4)
