@@ -68,8 +68,12 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
   const int64_t wlo = sd.begin >> 1;
   const int nw = (int)(((sd.begin + n + 1) >> 1) - wlo);
   const int odd = (int)(sd.begin & 1);
-  const uint32_t* W1 = reinterpret_cast<const uint32_t*>(P.rows.R1) + wlo;
-  const uint32_t* W2 = reinterpret_cast<const uint32_t*>(P.rows.R2) + wlo;
+  // a margin without ties stored only the sorted positions E (its doubled
+  // rank is 2E + 2)
+  const int eqm = P.state[sid].eqmask;
+  const bool q1 = (eqm & 1) != 0, q2 = (eqm & 2) != 0;
+  const uint32_t* W1 = reinterpret_cast<const uint32_t*>(q1 ? P.rows.E1 : P.rows.R1) + wlo;
+  const uint32_t* W2 = reinterpret_cast<const uint32_t*>(q2 ? P.rows.E2 : P.rows.R2) + wlo;
   uint32_t wa[EW], wb[EW];
 #pragma unroll
   for (int k = 0; k < EW; ++k) {
@@ -84,7 +88,9 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
     for (int h = 0; h < 2; ++h) {
       const int i = 2 * (tid + k * T) + h - odd;  // row within the subset
       if (i >= 0 && i < n) {
-        const uint32_t a = (wa[k] >> (16 * h)) & 0xFFFFu, b = (wb[k] >> (16 * h)) & 0xFFFFu;
+        uint32_t a = (wa[k] >> (16 * h)) & 0xFFFFu, b = (wb[k] >> (16 * h)) & 0xFFFFu;
+        a = q1 ? 2u * a + 2u : a;
+        b = q2 ? 2u * b + 2u : b;
         sacc += ((long long)a - (n + 1)) * ((long long)b - (n + 1));
         if constexpr (SM::GC) {
           CT lx, ly;

@@ -108,14 +108,18 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     theta = P.state[sid].theta;
   }
   const int64_t o = sd.begin;
-  const uint16_t *R1 = P.rows.R1 + o, *R2 = P.rows.R2 + o;
-  const uint16_t *E1 = P.rows.E1 + o, *E2 = P.rows.E2 + o;
-  // a margin without ties stored only the sorted positions, which are then
-  // also the group starts
+  // a margin without ties stored only the sorted positions E: they are also
+  // the group starts, and the doubled rank is 2E + 2
   const int eqm = P.state[sid].eqmask;
-  const uint16_t* L1base = (eqm & 1) ? P.rows.E1 : P.rows.L1;
-  const uint16_t* L2base = (eqm & 2) ? P.rows.E2 : P.rows.L2;
+  const bool q1 = (eqm & 1) != 0, q2 = (eqm & 2) != 0;
+  const uint16_t* R1base = q1 ? P.rows.E1 : P.rows.R1;
+  const uint16_t* R2base = q2 ? P.rows.E2 : P.rows.R2;
+  const uint16_t* L1base = q1 ? P.rows.E1 : P.rows.L1;
+  const uint16_t* L2base = q2 ? P.rows.E2 : P.rows.L2;
+  const uint16_t *R1 = R1base + o, *R2 = R2base + o;
+  const uint16_t *E1 = P.rows.E1 + o, *E2 = P.rows.E2 + o;
   const uint16_t *L1 = L1base + o, *L2 = L2base + o;
+  auto rank_of = [](uint32_t v, bool from_e) { return from_e ? 2u * v + 2u : v; };
   const uint32_t twon1 = 2u * (uint32_t)(n + 1);
   const CT inv = (CT)1 / (CT)twon1;
   const double dn = (double)n;
@@ -131,6 +135,8 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     using RT = decltype(rt_tag);
     constexpr int FORM = decltype(form_tag)::value;
     const RT invr = (RT)1 / (RT)twon1;
+    a = rank_of(a, q1);
+    b = rank_of(b, q2);
     RT lr, sr, g1r, g2r;
     if constexpr (FAM == FAM_FRANK) {
       frank_rfull<RT, FORM>(cc, a, b, twon1, invr, lr, sr, g1r, g2r);
@@ -191,7 +197,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
       const int odd = (int)(o & 1);
       auto words = [&](const uint16_t* base) { return reinterpret_cast<const uint32_t*>(base) + wlo; };
       const uint32_t *WE1 = words(P.rows.E1), *WE2 = words(P.rows.E2);
-      const uint32_t *WR1 = words(P.rows.R1), *WR2 = words(P.rows.R2);
+      const uint32_t *WR1 = words(R1base), *WR2 = words(R2base);
       const uint32_t *WL1 = words(L1base), *WL2 = words(L2base);
       const float4* ZC4 = reinterpret_cast<const float4*>(P.rows.G);
       const bool need_r = !zcache || FAM == FAM_GUMBEL;
@@ -235,7 +241,7 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
           if constexpr (ZFAM) {
             if (zcache) {
               if constexpr (FAM == FAM_GUMBEL)
-                gumbel_rfull<CT>(c, a, b, twon1, inv, zk[m].x, zk[m].y, l, s, g1, g2);
+                gumbel_rfull<CT>(c, rank_of(a, q1), rank_of(b, q2), twon1, inv, zk[m].x, zk[m].y, l, s, g1, g2);
               else
                 gauss_rfull<CT>(c, zk[m].x, zk[m].y, l, s, g1, g2);
             } else {

@@ -19,9 +19,9 @@ struct SubState {
   double theta;
   double Sp, Sm;  // Gaussian sufficient statistics
   int32_t status, iters;
-  // bit m (margin x: 0, y: 1): every row's sorted position equals its
-  // tie-group start (no ties, or ties in row order), and only the positions
-  // were stored (set by the rank kernel)
+  // bit m (margin x: 0, y: 1): every row's sorted position E equals its
+  // tie-group start (no ties, or ties in row order), its doubled rank is
+  // 2E + 2, and only the positions were stored (set by the rank kernel)
   int32_t eqmask, pad;
 };
 

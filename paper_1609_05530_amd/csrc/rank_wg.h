@@ -375,6 +375,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     if (wu + 1 < W) cr = min(cr, __builtin_amdgcn_readlane(b, wu + 1));
   }
   // workgroup-uniform: every row's group start equals its sorted position
+  // (and its doubled rank is 2 x position + 2: neither is stored then)
   bool eq = false;
   if constexpr (!ALIAS) {
     const int f = lane < W ? sm.wflag()[lane] : 0;
@@ -421,14 +422,14 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     for (int q = t; q < npair; q += T) {
       const int i = odd + 2 * q;
       const uint32_t v0 = xk[i], v1 = xk[i + 1];
-      *reinterpret_cast<uint32_t*>(Rg + i) = (v0 & 0xFFFFu) | (v1 << 16);
+      if (!eq) *reinterpret_cast<uint32_t*>(Rg + i) = (v0 & 0xFFFFu) | (v1 << 16);
       *reinterpret_cast<uint32_t*>(Eg + i) = (v0 >> 16) | (v1 & 0xFFFF0000u);
       if (!eq) *reinterpret_cast<uint32_t*>(Lg + i) = (uint32_t)xl[i] | ((uint32_t)xl[i + 1] << 16);
     }
     const int single = (t == 0 && odd) ? 0 : ((t == T - 1 && odd + 2 * npair < n) ? n - 1 : -1);
     if (single >= 0) {
       const uint32_t v = xk[single];
-      Rg[single] = (uint16_t)(v & 0xFFFFu);
+      if (!eq) Rg[single] = (uint16_t)(v & 0xFFFFu);
       Eg[single] = (uint16_t)(v >> 16);
       if (!eq) Lg[single] = xl[single];
     }
