@@ -78,8 +78,9 @@ template <typename T>
 using RowSum = KSum<T>;
 
 // ---------------------------------------------------------------------------
-// Reductions with a fixed tree: wave butterfly, then wave partials summed in
-// wave order by thread 0. Results are returned to thread 0 only.
+// Reductions in a fixed order (results do not depend on timing): wave_sum is
+// a butterfly; the workgroup reductions below scan each wave with DPP and
+// combine the waves' partials with a DPP row scan.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);

@@ -190,9 +190,7 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
           constexpr int FORM = decltype(form_tag)::value;
           RowSum<CT> ks, kh;
           CT s2 = (CT)0;
-#pragma unroll 2
-          for (int i = tid; i < n; i += T) {
-            CT s, h;
+          auto row = [&](int i, CT& s, CT& h) {
             if constexpr (FAM == FAM_FRANK) {
               const uint32_t r = sm.rr[i];
               frank_rsh<CT, FORM>(c, r & 0xFFFFu, r >> 16, twon1, inv, s, h);
@@ -204,9 +202,22 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
               gumbel_lxy<CT>(r & 0xFFFFu, r >> 16, twon1, inv, lx, ly);
               gumbel_sh(c.gk, lx, ly, s, h);
             }
+          };
+          // rows i and i + T: their terms are added in pairs, each pair
+          // entering the compensated sums once
+          for (int i = tid; i < n; i += 2 * T) {
+            CT s, h;
+            row(i, s, h);
+            s2 += s * s;
+            if (i + T < n) {
+              CT sb, hb;
+              row(i + T, sb, hb);
+              s2 += sb * sb;
+              s += sb;
+              h += hb;
+            }
             ks.add(s);
             kh.add(h);
-            s2 += s * s;
           }
           v[0] = ks.value();
           v[1] = kh.value();
