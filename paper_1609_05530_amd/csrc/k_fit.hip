@@ -172,13 +172,22 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
         const double invd = 1.0 / (double)twon1;
         KSum<double> ks, kh;
         double s2 = 0.0;
-        for (int i = tid; i < n; i += T) {
-          const uint32_t r = sm.rr[i];
+        // rows i and i + T added in pairs before the compensated sums
+        for (int i = tid; i < n; i += 2 * T) {
+          uint32_t r = sm.rr[i];
           double s, h;
           frank_rsh<double>(cd, r & 0xFFFFu, r >> 16, twon1, invd, s, h);
+          s2 += s * s;
+          if (i + T < n) {
+            r = sm.rr[i + T];
+            double sb, hb;
+            frank_rsh<double>(cd, r & 0xFFFFu, r >> 16, twon1, invd, sb, hb);
+            s2 += sb * sb;
+            s += sb;
+            h += hb;
+          }
           ks.add(s);
           kh.add(h);
-          s2 += s * s;
         }
         v[0] = ks.value();
         v[1] = kh.value();
