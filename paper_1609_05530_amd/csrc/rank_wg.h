@@ -71,10 +71,12 @@ struct RankLds {
 static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
 
 
-// Ranks one margin and writes, per row of the subset, R (and the sorted
-// position e and tie-group start lb). Returns true (in every thread) if the
-// margin holds a non-finite value; sets all_tied (in thread 0) if every value
-// is equal.
+// Ranks one margin and writes, per row of the subset, the sorted position e
+// and, if the margin has ties, the doubled rank R and the tie-group start lb
+// (without ties R = 2e + 2 and lb = e, and e_is_l is set in every thread;
+// MODE_RANK writes R alone, as 32-bit values). Returns true (in every thread)
+// if the margin holds a non-finite value; sets all_tied (in thread 0) if
+// every value is equal.
 template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
                                                 RankLds<T, E, B, KW, ALIAS, P32, PAD>& sm, uint16_t* Rg, uint16_t* Eg,
@@ -351,8 +353,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   const int imin = wave_incl_suffix_min_i32(hmin);
   if (lane == WAVE - 1) sm.wmax()[w] = imax;
   if (lane == 0) sm.wmin()[w] = imin;
-  // does any valid item continue a tie group? (then the sorted positions
-  // and the group starts differ and both are stored)
+  // does any valid item continue a tie group? (then the doubled ranks and
+  // group starts are stored beside the sorted positions)
   const uint32_t vmask = nv >= 32 ? 0xFFFFFFFFu : ((1u << nv) - 1u);
   const bool tied_here = (headm & vmask) != vmask;
   if constexpr (!ALIAS) {
