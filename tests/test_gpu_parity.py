@@ -364,6 +364,10 @@ def test_ties_per_margin_workgroup_path(fam):
             x[a:b] = np.round(x[a:b] * 8) / 8
         if m % 4 in (1, 2):
             y[a:b] = np.round(y[a:b] * 4) / 4
+    # a single tied pair in an otherwise continuous margin (rows far apart,
+    # so in different waves of the rank kernel): x of subset 3, y of subset 7
+    x[off[3] + 5] = x[off[3] + 9000]
+    y[off[7] + 1] = y[off[7] + 600]
     sub, comb = O.fit(x, y, off, fam, nthreads=0)
     res = to_np(cpc().fit(dev(x, torch.float64), dev(y, torch.float64), off, fam, prec="fp64"))
     compare(res, sub, comb, "fp64", fam, f"ties per margin {fam}")
