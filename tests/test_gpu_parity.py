@@ -254,6 +254,26 @@ def test_eval_and_variance_entry_points(fam, th, prec):
         assert abs(var[m] / vref - 1.0) <= vt, (fam, th, prec, m, var[m], vref)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32c"])
+def test_variance_entry_point_with_ties(prec):
+    """cpc_variance on ranks with tie groups (x heavily tied, y with a single
+    tied pair, and a subset without ties): against the oracle's GGR."""
+    sizes = np.array([1500, 9000, 4000])
+    x, y = synth.copula_pairs("frank", 4.0, int(sizes.sum()), 23)
+    off = synth.offsets_from_sizes(sizes)
+    x[off[0]:off[2]] = np.round(x[off[0]:off[2]] * 8) / 8
+    y[off[1] + 3] = y[off[1] + 7000]
+    R1, R2 = cpc().rank(dev(x, torch.float64), dev(y, torch.float64), off)
+    thetas = torch.tensor([4.0, 3.5, 4.5], dtype=torch.float64).cuda()
+    var = cpc().variance(R1, R2, off, "frank", thetas, prec=prec).cpu().numpy()
+    r1 = R1.cpu().numpy().astype(np.int64); r2 = R2.cpu().numpy().astype(np.int64)
+    vt = 1e-8 if prec == "fp64" else 1e-4
+    for m in range(len(sizes)):
+        a, b = off[m], off[m + 1]
+        vref, _ = O.ggr(r1[a:b], r2[a:b], "frank", float(thetas[m]))
+        assert abs(var[m] / vref - 1.0) <= vt, (prec, m, var[m], vref)
+
+
 def test_autograd_loglik_and_score():
     import paper_1609_05530_amd as m
     fam = "frank"
