@@ -558,6 +558,30 @@ def test_graph_replay_reads_current_data():
         assert np.array_equal(got[k], ref[k], equal_nan=True), k
 
 
+def test_graph_replay_switches_to_tied_data():
+    """A graph captured on continuous data, replayed after x is overwritten
+    with tied values: each replay decides per margin whether it has ties, so
+    the replay equals an eager fit of the tied data."""
+    m = cpc()
+    x, y, off, gofs, fams = _graph_case()
+    dx, dy = dev(x, torch.float32), dev(y, torch.float32)
+    K, G = len(off) - 1, len(gofs) - 1
+    ws = torch.empty(m.workspace_bytes(len(x), K, G, dtype=torch.float32, prec="fp32c"), dtype=torch.uint8,
+                     device="cuda")
+    out = m.FitResult(torch.empty((K, 6), dtype=torch.float64, device="cuda"),
+                      torch.empty((G, 5), dtype=torch.float64, device="cuda"))
+    m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec="fp32c")
+    torch.cuda.synchronize()
+    dx.copy_(dev(np.round(x * 4) / 4, torch.float32))
+    for _ in range(2):
+        m.fit_batched(dx, dy, off, gofs, fams, workspace=ws, out=out, graph=True, prec="fp32c")
+        torch.cuda.synchronize()
+        got = to_np(out)
+        ref = to_np(m.fit_batched(dx, dy, off, gofs, fams, prec="fp32c"))
+        for k in ref:
+            assert np.array_equal(got[k], ref[k], equal_nan=True), k
+
+
 # ---------------------------------------------------------------------------
 # Autotuner: rank-kernel launch shapes (speed only; results are identical)
 
