@@ -53,15 +53,22 @@ def gaussian_pairs(n: int, rho: float, rng: np.random.Generator):
 
 
 def frank_pairs(n: int, theta: float, rng: np.random.Generator):
+    """Conditional inversion of dC/du = w, written so that no step cancels for
+    large |theta|: e^{-theta v} = (omw e^{-theta u} + w e^{-theta}) / (w +
+    omw e^{-theta u}) gives v = u - D / theta and 1 - v = (1 - u) + D / theta
+    with D = log1p(w expm1(-theta (1 - u))) - log1p(omw expm1(-theta u))."""
     u = _open_uniform(rng, n)
     w = _open_uniform(rng, n)
+    omu = 1.0 - u
     if abs(theta) < 1e-12:
-        v = w
+        v, omv = w, 1.0 - w
     else:
-        t = w * np.expm1(-theta) / (w + (1.0 - w) * np.exp(-theta * u))
-        v = -np.log1p(t) / theta
+        D = np.log1p(w * np.expm1(-theta * omu)) - np.log1p((1.0 - w) * np.expm1(-theta * u))
+        v = u - D / theta
+        omv = omu + D / theta
     v = np.clip(v, 2.0**-1000, 1.0 - 2.0**-53)
-    return _normal_margin(u, 1.0 - u), _normal_margin(v, 1.0 - v)
+    omv = np.clip(omv, 2.0**-1000, 1.0 - 2.0**-53)
+    return _normal_margin(u, omu), _normal_margin(v, omv)
 
 
 def gumbel_pairs(n: int, theta: float, rng: np.random.Generator):
