@@ -353,7 +353,8 @@ __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1
   const CT inv = (CT)1 / (CT)twon1;
   const Consts<CT> c = make_consts<CT>(s.family, th);
   double v[3];
-  if (s.family == FAM_FRANK && sizeof(CT) == 4 && c.use_d) {
+  if (sizeof(CT) == 4 && c.use_d) {
+    // FP64 rows (Frank near independence or far out, Gumbel next to theta = 1)
     const Consts<double> cd = make_consts<double>(s.family, th);
     const double invd = 1.0 / (double)twon1;
     KSum<double> ks, kh;
@@ -361,7 +362,13 @@ __global__ void __launch_bounds__(BT) k_big_eval(BigParams P, const uint32_t* R1
     for (int i = threadIdx.x; i < t.count; i += BT) {
       const int64_t q = s.roff + t.start + i;
       double sv, hv;
-      frank_rsh<double>(cd, R1[q], R2[q], twon1, invd, sv, hv);
+      if (s.family == FAM_FRANK) {
+        frank_rsh<double>(cd, R1[q], R2[q], twon1, invd, sv, hv);
+      } else {
+        double lx, ly;
+        gumbel_lxy<double>(R1[q], R2[q], twon1, invd, lx, ly);
+        gumbel_sh(cd.gk, lx, ly, sv, hv);
+      }
       ks.add(sv); kh.add(hv); s2 += sv * sv;
     }
     v[0] = ks.value(); v[1] = kh.value(); v[2] = s2;
@@ -396,8 +403,7 @@ __global__ void __launch_bounds__(256) k_big_update(BigParams P, const double* p
         const double* q = part + (s.tile0 + k) * 5;
         a += q[0]; b += q[1]; c2 += q[2];
       }
-      const bool d_rows = fp64 || (s.family == FAM_FRANK &&
-                                   (fabs(S.theta) < FRANK_F32_MIN_ABS || fabs(S.theta) > FRANK_F32_MAX_ABS));
+      const bool d_rows = fp64 || rows_in_fp64(s.family, S.theta);
       const double noise = 16.0 * (d_rows ? 1.1102230246251565e-16 : 5.9604644775390625e-08);
       newton_update(S, s.family, a, b, c2, tol, noise, max_iter);
     }

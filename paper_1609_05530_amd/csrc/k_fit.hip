@@ -166,12 +166,35 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
       const Consts<CT> c = make_consts<CT>(FAM, th);
       double v[3];
       double noise;
-      if (FAM == FAM_FRANK && sizeof(CT) == 4 && c.use_d) {
-        // FP64 rows (Frank near independence or far out)
+      if (sizeof(CT) == 4 && c.use_d) {
+        // FP64 rows (Frank near independence or far out, Gumbel next to
+        // theta = 1)
         const Consts<double> cd = make_consts<double>(FAM, th);
         const double invd = 1.0 / (double)twon1;
         KSum<double> ks, kh;
         double s2 = 0.0;
+        if constexpr (FAM == FAM_GUMBEL) {
+          // log(-log u), log(-log v) in FP64 from the ranks in the workspace
+          // (the LDS holds the FP32 ones), read as the aligned words above
+          for (int j = tid; j < nw; j += T) {
+            const uint32_t w1 = W1[j], w2 = W2[j];
+#pragma unroll 1
+            for (int hh = 0; hh < 2; ++hh) {
+              const int i = 2 * j + hh - odd;
+              if (i >= 0 && i < n) {
+                uint32_t a = (w1 >> (16 * hh)) & 0xFFFFu, b = (w2 >> (16 * hh)) & 0xFFFFu;
+                a = q1 ? 2u * a + 2u : a;
+                b = q2 ? 2u * b + 2u : b;
+                double lx, ly, s, h;
+                gumbel_lxy<double>(a, b, twon1, invd, lx, ly);
+                gumbel_sh(cd.gk, lx, ly, s, h);
+                s2 += s * s;
+                ks.add(s);
+                kh.add(h);
+              }
+            }
+          }
+        } else {
         // rows i and i + T added in pairs before the compensated sums
         for (int i = tid; i < n; i += 2 * T) {
           uint32_t r = sm.rr[i];
@@ -188,6 +211,7 @@ __global__ void __launch_bounds__(T, (fit_waves_per_simd<T, CAP, CT, FAM>())) k_
           }
           ks.add(s);
           kh.add(h);
+        }
         }
         v[0] = ks.value();
         v[1] = kh.value();

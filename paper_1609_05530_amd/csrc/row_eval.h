@@ -17,7 +17,12 @@ enum Family { FAM_GAUSSIAN = 0, FAM_FRANK = 1, FAM_GUMBEL = 2 };
 
 // Rows switch from FP32 to FP64 arithmetic (in the FP32-compensated mode)
 // where the FP32 forms lose digits: Frank near independence or far out
-// (e^{-theta} leaves FP32 range), Gaussian with |rho| near 1. Near Frank
+// (e^{-theta} leaves FP32 range), Gaussian with |rho| near 1, and Gumbel
+// next to its natural boundary theta = 1. There the sign of the summed
+// score at theta = 1 decides between the boundary estimate and an interior
+// one (an integer status), so it is taken in the oracle's precision; the
+// FP32 forms themselves stay accurate to ~2e-8 absolute down to
+// theta = 1.001 (the factor theta - 1 is formed in FP64). Near Frank
 // independence the log-likelihood is flat (mean d2l/dtheta2 ~ -0.03 at
 // theta = 0.1), so a rounding bias of one FP32 ulp in the per-row score
 // moves the root by ~2e-6 absolute: FP64 rows below |theta| = 0.5 keep the
@@ -25,6 +30,14 @@ enum Family { FAM_GAUSSIAN = 0, FAM_FRANK = 1, FAM_GUMBEL = 2 };
 constexpr double FRANK_F32_MIN_ABS = 0.5;
 constexpr double FRANK_F32_MAX_ABS = 50.0;
 constexpr double GAUSS_F32_MAX_ABS = 0.99;
+constexpr double GUMBEL_F32_MIN = 1.01;
+
+// FP64 rows of an FP32-compensated solve at theta (the bands above).
+CPC_HD bool rows_in_fp64(int fam, double theta) {
+  if (fam == FAM_FRANK) return fabs(theta) < FRANK_F32_MIN_ABS || fabs(theta) > FRANK_F32_MAX_ABS;
+  if (fam == FAM_GUMBEL) return theta < GUMBEL_F32_MIN;
+  return fabs(theta) > GAUSS_F32_MAX_ABS;
+}
 
 // Search box per family (the parameter ranges of eq. 8, 10 and 11).
 CPC_HD double box_lo(int fam) { return fam == FAM_GAUSSIAN ? -(1.0 - 1e-9) : (fam == FAM_FRANK ? -200.0 : 1.0); }
@@ -47,16 +60,14 @@ CPC_HD Consts<CT> make_consts(int fam, double theta) {
   c.fam = fam;
   c.theta = theta;
   c.neg = false;
-  c.use_d = false;
+  c.use_d = sizeof(CT) == 4 && rows_in_fp64(fam, theta);
   if (fam == FAM_FRANK) {
     const double a = fabs(theta);
     c.neg = theta < 0.0;
-    if (sizeof(CT) == 4 && (a < FRANK_F32_MIN_ABS || a > FRANK_F32_MAX_ABS)) c.use_d = true;
     c.fk = frank_const<CT>(a > 0.0 ? a : 1.0);  // the FP32 forms only see |theta| >= 0.5
   } else if (fam == FAM_GUMBEL) {
     c.gk = gumbel_const<CT>(theta);
   } else {
-    if (sizeof(CT) == 4 && fabs(theta) > GAUSS_F32_MAX_ABS) c.use_d = true;
     c.gc = gauss_const<CT>(theta);
   }
   return c;
