@@ -125,7 +125,7 @@ def small_configs(cpc, synth, dev, oracle_1thread):
     for w in cases:
         x = torch.from_numpy(w.x).to(dev)
         y = torch.from_numpy(w.y).to(dev)
-        ws = torch.empty(cpc.workspace_bytes(w.n, w.K, w.G, dtype=x.dtype, prec="fp64"), dtype=torch.uint8,
+        ws = torch.empty(cpc.workspace_bytes(w.n, w.K, w.G, dtype=x.dtype, offsets=w.offsets, prec="fp64"), dtype=torch.uint8,
                          device=dev)
         out = cpc.FitResult(torch.empty((w.K, 6), dtype=torch.float64, device=dev),
                             torch.empty((w.G, 5), dtype=torch.float64, device=dev))
@@ -203,7 +203,7 @@ def main():
     graph = not a.no_graph
 
     def make_step(prec):
-        ws = torch.empty(cpc.workspace_bytes(n, K, G, dtype=x.dtype, prec=prec), dtype=torch.uint8, device=dev)
+        ws = torch.empty(cpc.workspace_bytes(n, K, G, dtype=x.dtype, offsets=w.offsets, prec=prec), dtype=torch.uint8, device=dev)
         out = cpc.FitResult(torch.empty((K, 6), dtype=torch.float64, device=dev),
                             torch.empty((G, 5), dtype=torch.float64, device=dev))
 

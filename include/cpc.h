@@ -23,8 +23,9 @@
  *   - offsets / group_offsets / family tables are HOST arrays; they are
  *     copied into the workspace during the call and may be reused on return.
  *   - workspace is a caller-owned DEVICE buffer of at least the size reported
- *     by cpc_workspace_bytes(); the library allocates no device memory in any
- *     call except cpc_create().
+ *     by cpc_workspace_bytes_for() for the call's partition (or the upper
+ *     bound cpc_workspace_bytes()); the library allocates no device memory
+ *     in any call except cpc_create().
  *   - All outputs are DEVICE buffers owned by the caller. Work is enqueued on
  *     `stream` (a hipStream_t passed as void*; NULL = default stream) and is
  *     complete once the stream is synchronised.
@@ -137,8 +138,18 @@ int cpc_destroy(cpc_handle_t h);
 void cpc_default_options(cpc_options_t* opt);
 
 /* Workspace bytes that suffice for any call with at most n rows, K subsets
- * and G groups of the given storage type and options (an upper bound). */
+ * and G groups of the given storage type and options (an upper bound: it
+ * assumes every row may belong to a subset of more than 16384 rows). */
 size_t cpc_workspace_bytes(int64_t n, int64_t K, int64_t G, int32_t dtype, const cpc_options_t* opt);
+
+/* Workspace bytes a call needs for exactly this partition (eq. 14): offsets
+ * is the host array of K+1 subset bounds (offsets[K] = n), G the number of
+ * groups (1 for cpc_fit / cpc_rank / cpc_eval / cpc_variance). Per row
+ * about 28 bytes, plus 88 bytes per row of the subsets of more than 16384
+ * rows (the streaming path's sort and scan arrays). Returns 0 if offsets is
+ * NULL or not a partition. */
+size_t cpc_workspace_bytes_for(const int64_t* offsets, int64_t K, int64_t G, int32_t dtype,
+                               const cpc_options_t* opt);
 
 /* Fit every subset of one family and combine them (eq. 12-15).
  *   x, y     : device, n values each, type `dtype`

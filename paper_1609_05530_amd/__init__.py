@@ -96,9 +96,23 @@ def _stream(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def workspace_bytes(n: int, K: int, G: int = 1, dtype=torch.float64, **opt) -> int:
+def workspace_bytes(n: int, K: int, G: int = 1, dtype=torch.float64, offsets=None, **opt) -> int:
+    """Workspace bytes for a call: exact for the partition `offsets` when
+    given (cpc_workspace_bytes_for), else the upper bound over all partitions
+    of n rows into K subsets (cpc_workspace_bytes)."""
     o = _options(**opt)
-    return int(lib().cpc_workspace_bytes(int(n), int(K), int(G), 0 if dtype == torch.float64 else 1, ctypes.byref(o)))
+    dt = 0 if dtype == torch.float64 else 1
+    if offsets is not None:
+        off = _i64(offsets)
+        return _exact_bytes(off, int(G), dt, o)
+    return int(lib().cpc_workspace_bytes(int(n), int(K), int(G), dt, ctypes.byref(o)))
+
+
+def _exact_bytes(off: np.ndarray, G: int, dt: int, o: Options) -> int:
+    nbytes = int(lib().cpc_workspace_bytes_for(off.ctypes.data, off.shape[0] - 1, G, dt, ctypes.byref(o)))
+    if nbytes == 0:
+        raise ValueError("offsets are not a partition of the rows")
+    return nbytes
 
 
 def _workspace(nbytes: int, device, workspace: Optional[torch.Tensor]) -> torch.Tensor:
@@ -166,8 +180,7 @@ def fit_batched(x: torch.Tensor, y: torch.Tensor, offsets, group_offsets, famili
     o = _options(**opt)
     dt = _dtype_code(x)
     n = x.shape[0]
-    nbytes = int(lib().cpc_workspace_bytes(n, K, G, dt, ctypes.byref(o)))
-    ws = _workspace(nbytes, x.device, workspace)
+    ws = _workspace(_exact_bytes(offsets, G, dt, o), x.device, workspace)
     if out is None:
         out = FitResult(torch.empty((K, 6), dtype=torch.float64, device=x.device),
                         torch.empty((G, 5), dtype=torch.float64, device=x.device))
@@ -187,11 +200,11 @@ def rank(x: torch.Tensor, y: torch.Tensor, offsets, *, workspace=None, **opt):
     o = _options(**opt)
     dt = _dtype_code(x)
     n = x.shape[0]
-    ws = _workspace(int(lib().cpc_workspace_bytes(n, K, 1, dt, ctypes.byref(o))), x.device, workspace)
+    ws = _workspace(_exact_bytes(offsets, 1, dt, o), x.device, workspace)
     R1 = torch.empty(n, dtype=torch.int32, device=x.device)
     R2 = torch.empty(n, dtype=torch.int32, device=x.device)
     check(lib().cpc_rank(_handle(x.device), x.data_ptr(), y.data_ptr(), dt, n, offsets.ctypes.data, K,
-                         ctypes.byref(o), ws.data_ptr(), ws.numel(), R1.data_ptr(), R2.data_ptr(),
+                         ctypes.byref(o), ws.data_ptr(), ws.numel() * ws.element_size(), R1.data_ptr(), R2.data_ptr(),
                          _stream(x.device)))
     return R1, R2
 
@@ -206,10 +219,10 @@ def eval_subsets(R1: torch.Tensor, R2: torch.Tensor, offsets, family, theta: tor
     K = offsets.shape[0] - 1
     n = R1.shape[0]
     o = _options(**opt)
-    ws = _workspace(int(lib().cpc_workspace_bytes(n, K, 1, 0, ctypes.byref(o))), R1.device, workspace)
+    ws = _workspace(_exact_bytes(offsets, 1, 0, o), R1.device, workspace)
     out = torch.empty((K, 3), dtype=torch.float64, device=R1.device)
     check(lib().cpc_eval(_handle(R1.device), R1.data_ptr(), R2.data_ptr(), n, offsets.ctypes.data, K,
-                         _code(FAMILIES, family), theta.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                         _code(FAMILIES, family), theta.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel() * ws.element_size(),
                          out.data_ptr(), _stream(R1.device)))
     return out
 
@@ -224,10 +237,10 @@ def variance(R1: torch.Tensor, R2: torch.Tensor, offsets, family, theta: torch.T
     K = offsets.shape[0] - 1
     n = R1.shape[0]
     o = _options(**opt)
-    ws = _workspace(int(lib().cpc_workspace_bytes(n, K, 1, 0, ctypes.byref(o))), R1.device, workspace)
+    ws = _workspace(_exact_bytes(offsets, 1, 0, o), R1.device, workspace)
     out = torch.empty(K, dtype=torch.float64, device=R1.device)
     check(lib().cpc_variance(_handle(R1.device), R1.data_ptr(), R2.data_ptr(), n, offsets.ctypes.data, K,
-                             _code(FAMILIES, family), theta.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                             _code(FAMILIES, family), theta.data_ptr(), ctypes.byref(o), ws.data_ptr(), ws.numel() * ws.element_size(),
                              out.data_ptr(), _stream(R1.device)))
     return out
 

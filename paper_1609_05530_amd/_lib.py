@@ -37,6 +37,7 @@ SIGNATURES = {
     "cpc_destroy": (_I32, [_P]),
     "cpc_default_options": (None, [ctypes.POINTER(Options)]),
     "cpc_workspace_bytes": (_SZ, [_I64, _I64, _I64, _I32, ctypes.POINTER(Options)]),
+    "cpc_workspace_bytes_for": (_SZ, [_P, _I64, _I64, _I32, ctypes.POINTER(Options)]),
     "cpc_fit": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _I32, ctypes.POINTER(Options), _P, _SZ, _P, _P, _P]),
     "cpc_fit_batched": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P, _SZ,
                                _P, _P, _P]),

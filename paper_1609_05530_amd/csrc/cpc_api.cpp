@@ -117,9 +117,35 @@ struct Layout {
   size_t total;
 };
 
-int64_t max_tiles(int64_t n, int64_t K) { return n / kBigTile + K + 1; }
+// Rows and subsets of the streaming path (subsets above kResidentMaxRows).
+struct BigShare {
+  int64_t rows = 0, subsets = 0;
+};
+BigShare big_share(const int64_t* offsets, int64_t K) {
+  BigShare b;
+  for (int64_t m = 0; m < K; ++m) {
+    const int64_t rows = offsets[m + 1] - offsets[m];
+    if (rows > kResidentMaxRows) {
+      b.rows += rows;
+      b.subsets += 1;
+    }
+  }
+  return b;
+}
+// The most any partition of n rows into K subsets can put on the streaming path.
+BigShare big_bound(int64_t n, int64_t K) {
+  BigShare b;
+  b.rows = n;
+  b.subsets = std::min<int64_t>(K, n / (kResidentMaxRows + 1));
+  return b;
+}
 
-Layout layout(int64_t n, int64_t K, int64_t G) {
+int64_t max_tiles(int64_t rows, int64_t subsets) { return rows / kBigTile + subsets + 1; }
+
+// The per-row arrays of the workgroup path are indexed by row and span all
+// n rows; those of the streaming path are indexed by the compact position
+// of a row among the streaming path's rows and span only those.
+Layout layout(int64_t n, int64_t K, int64_t G, const BigShare& big) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -140,7 +166,8 @@ Layout layout(int64_t n, int64_t K, int64_t G) {
   L.l2 = take(2 * (size_t)n);
   L.s = take(8 * (size_t)n);
   L.g = take(8 * (size_t)n);
-  const int64_t T = max_tiles(n, K);
+  const int64_t T = max_tiles(big.rows, big.subsets);
+  const size_t nb = (size_t)big.rows;
   L.bsegs = take(sizeof(BigSeg) * (size_t)K);
   L.btiles = take(sizeof(BigTile) * (size_t)T);
   L.bxorder = take(sizeof(int64_t) * 8 * (size_t)T);
@@ -151,8 +178,8 @@ Layout layout(int64_t n, int64_t K, int64_t G) {
   L.bhist = take(256 * sizeof(uint32_t) * (size_t)T);
   L.bpart = take(5 * sizeof(double) * (size_t)T);
   L.btsum = take(2 * sizeof(double) * (size_t)T);
-  for (int i = 0; i < 12; ++i) L.brow32[i] = take(4 * (size_t)n);
-  for (int i = 0; i < 5; ++i) L.brow64[i] = take(8 * (size_t)n);
+  for (int i = 0; i < 12; ++i) L.brow32[i] = take(4 * nb);
+  for (int i = 0; i < 5; ++i) L.brow64[i] = take(8 * nb);
   L.total = off;
   return L;
 }
@@ -537,7 +564,7 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
             int64_t K, const int64_t* gofs, int64_t G, const std::vector<int32_t>& fam_of_subset,
             const Options& o, void* ws, size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb,
             hipStream_t s) {
-  const Layout L = layout(n, K, G);
+  const Layout L = layout(n, K, G, big_share(offsets, K));
   if (!ws) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < L.total)
     return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
@@ -757,7 +784,16 @@ size_t cpc_workspace_bytes(int64_t n, int64_t K, int64_t G, int32_t dtype, const
   (void)dtype;
   (void)opt;
   if (n < 0 || K < 0 || G < 0) return 0;
-  return layout(n, K, G < 1 ? 1 : G).total;
+  return layout(n, K, G < 1 ? 1 : G, big_bound(n, K)).total;
+}
+
+size_t cpc_workspace_bytes_for(const int64_t* offsets, int64_t K, int64_t G, int32_t dtype,
+                               const cpc_options_t* opt) {
+  (void)dtype;
+  (void)opt;
+  if (!offsets || K < 1 || G < 0) return 0;
+  if (check_offsets(offsets, K, offsets[K]) != CPC_SUCCESS) return 0;
+  return layout(offsets[K], K, G < 1 ? 1 : G, big_share(offsets, K)).total;
 }
 
 int cpc_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
@@ -816,7 +852,7 @@ int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_
   Options o;
   if (int rc = read_options(opt, o)) return rc;
   if (int rc = check_offsets(offsets, K, n)) return rc;
-  const Layout L = layout(n, K, 1);
+  const Layout L = layout(n, K, 1, big_share(offsets, K));
   if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < L.total) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
   std::vector<int32_t> fam((size_t)K, 0);
@@ -860,7 +896,7 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
   Options o;
   if (int rc = read_options(opt, o)) return rc;
   if (int rc = check_offsets(offsets, K, n)) return rc;
-  const Layout L = layout(n, K, 1);
+  const Layout L = layout(n, K, 1, big_share(offsets, K));
   if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < L.total) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
   std::vector<int32_t> fam((size_t)K, family);
@@ -918,7 +954,7 @@ int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, 
   Options o;
   if (int rc = read_options(opt, o)) return rc;
   if (int rc = check_offsets(offsets, K, n)) return rc;
-  const Layout L = layout(n, K, 1);
+  const Layout L = layout(n, K, 1, big_share(offsets, K));
   if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < L.total) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, L.total);
   std::vector<SubDesc> subs((size_t)K);

@@ -78,3 +78,28 @@ def test_probe_library_exports_its_header():
     # argument checks come before any device call
     assert P.cpc_probe_valu(0, 7, 16, ctypes.byref(r), ctypes.byref(ms)) == -1
     assert P.cpc_probe_valu(0, 0, 0, ctypes.byref(r), ctypes.byref(ms)) == -1
+
+
+def test_workspace_follows_the_partition(L):
+    """The exact workspace of a partition reserves the streaming path's
+    arrays (88 bytes per row) only for the rows of subsets above 16384 rows;
+    the upper bound assumes every row may be there."""
+    import numpy as np
+    from paper_1609_05530_amd._lib import Options
+    o = Options()
+    L.cpc_default_options(ctypes.byref(o))
+    n = 2_000_000
+    small = np.arange(0, n + 1, 10_000, dtype=np.int64)          # 200 subsets of 10000 rows
+    big = np.array([0, 1_000_000, n], dtype=np.int64)             # 2 subsets of 1e6 rows
+    mixed = np.array([0, 500_000] + list(range(510_000, n + 1, 10_000)), dtype=np.int64)
+    bound = L.cpc_workspace_bytes(n, 200, 1, 1, ctypes.byref(o))
+    e_small = L.cpc_workspace_bytes_for(small.ctypes.data, len(small) - 1, 1, 1, ctypes.byref(o))
+    e_big = L.cpc_workspace_bytes_for(big.ctypes.data, len(big) - 1, 1, 1, ctypes.byref(o))
+    e_mixed = L.cpc_workspace_bytes_for(mixed.ctypes.data, len(mixed) - 1, 1, 1, ctypes.byref(o))
+    assert 0 < e_small < e_mixed < e_big <= bound
+    assert e_small < 32 * n              # about 28 bytes per row without streaming subsets
+    assert e_big >= 116 * n              # the streaming arrays for every row
+    assert e_mixed - e_small >= 88 * 500_000
+    bad = np.array([0, 10, 5], dtype=np.int64)
+    assert L.cpc_workspace_bytes_for(bad.ctypes.data, 2, 1, 1, ctypes.byref(o)) == 0
+    assert L.cpc_workspace_bytes_for(None, 2, 1, 1, ctypes.byref(o)) == 0
