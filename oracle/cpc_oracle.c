@@ -646,3 +646,250 @@ void or_fit(const double* x, const double* y, const int64_t* offsets, int64_t K,
   or_combine(out, group_offsets, G, comb);
   free(fam);
 }
+
+/* ======================================================================== */
+/* Simulation inputs (Sec. 2.5: data simulated from the copula itself) from a
+ * counter-based generator, so that any row can be drawn independently and
+ * the GPU sampler can be compared with this one value by value.
+ *
+ * Philox4x32-10 (Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): a 4 x 32-bit counter and a 2 x 32-bit key,
+ * ten rounds of two 32 x 32 -> 64-bit multiplications (multipliers
+ * 0xD2511F53 and 0xCD9E8D57) with the key bumped by the Weyl constants
+ * 0x9E3779B9 and 0xBB67AE85 between rounds.                                 */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* A uniform on the open interval from two words: k = the 20 low bits of a
+ * above the 32 bits of b (52 bits), u = (k + 1/2) 2^-52 and 1 - u =
+ * (2^52 - k - 1/2) 2^-52, both exact.                                       */
+static void uniform_pair(uint32_t a, uint32_t b, double* u, double* omu) {
+  const uint64_t k = ((uint64_t)(a & 0xFFFFFu) << 32) | (uint64_t)b;
+  *u = ((double)k + 0.5) * 0x1p-52;
+  *omu = (4503599627370496.0 - (double)k - 0.5) * 0x1p-52;
+}
+
+/* The uniforms of row `row` of a stream keyed by `seed`: block `blk` is the
+ * generator at counter (row low word, row high word, blk, 0).               */
+static void row_uniforms(uint64_t seed, int64_t row, uint32_t blk, double u[2], double omu[2]) {
+  const uint32_t ctr[4] = {(uint32_t)(uint64_t)row, (uint32_t)((uint64_t)row >> 32), blk, 0u};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  or_philox4x32_10(ctr, key, w);
+  uniform_pair(w[0], w[1], &u[0], &omu[0]);
+  uniform_pair(w[2], w[3], &u[1], &omu[1]);
+}
+
+/* An exponential variate -log(u), from 1 - u where u is near 1. */
+static double exp_variate(double u, double omu) { return (u < 0.5) ? -log(u) : -log1p(-omu); }
+
+/* Phi^{-1}(exp(-t)) (a margin of the Marshall-Olkin construction): the upper
+ * tail through 1 - e^{-t} = -expm1(-t) when e^{-t} > 1/2; t is capped at
+ * 700 (e^{-700} ~ 1e-304) so that e^{-t} stays a normal double.             */
+static double qnorm_exp_neg(double t) {
+  if (t > 700.0) t = 700.0;
+  return or_qnorm(exp(-t), -expm1(-t));
+}
+
+/* Row i of n pairs (x, y) with N(0,1) margins whose copula is the family's
+ * (eq. 8, 10, 11) at theta; row0 + i is the generator row.
+ *  Gaussian: z1 = Phi^{-1}(u1), z2 = Phi^{-1}(u2), x = z1,
+ *            y = rho z1 + sqrt(1 - rho^2) z2 (Cholesky factor of the
+ *            correlation matrix).
+ *  Frank:    u, and v from dC/du (u, v) = w solved in closed form:
+ *            e^{-theta v} = ((1-w) e^{-theta u} + w e^{-theta}) / (w + (1-w) e^{-theta u}),
+ *            i.e. v = u - D / theta, 1 - v = (1 - u) + D / theta with
+ *            D = log1p(w expm1(-theta (1-u))) - log1p((1-w) expm1(-theta u))
+ *            (theta = 0: v = w); v and 1 - v are kept in [2^-1000, 1 - 2^-53].
+ *  Gumbel:   Marshall-Olkin: S positive stable with Laplace transform
+ *            exp(-s^alpha), alpha = 1/theta, by Kanter's representation
+ *            S = sin(alpha T) / sin(T)^(1/alpha) * (sin((1-alpha) T) / W)^((1-alpha)/alpha)
+ *            with T ~ U(0, pi), W ~ Exp(1) (formed in logarithms); then
+ *            U_j = exp(-(E_j / S)^alpha) with E_j ~ Exp(1).
+ *  The margin of a uniform takes the tail of the smaller of u and 1 - u.     */
+void or_sample(int32_t family, double theta, uint64_t seed, int64_t row0, int64_t n, double* x, double* y) {
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t row = row0 + i;
+    double u[2], omu[2];
+    row_uniforms(seed, row, 0u, u, omu);
+    if (family == OR_GAUSSIAN) {
+      const double z1 = or_qnorm(u[0], omu[0]), z2 = or_qnorm(u[1], omu[1]);
+      x[i] = z1;
+      y[i] = theta * z1 + sqrt((1.0 - theta) * (1.0 + theta)) * z2;
+    } else if (family == OR_FRANK) {
+      double v = u[1], omv = omu[1];
+      if (theta != 0.0) {
+        const double D = log1p(u[1] * expm1(-theta * omu[0])) - log1p(omu[1] * expm1(-theta * u[0]));
+        v = u[0] - D / theta;
+        omv = omu[0] + D / theta;
+      }
+      v = fmin(fmax(v, 0x1p-1000), 1.0 - 0x1p-53);
+      omv = fmin(fmax(omv, 0x1p-1000), 1.0 - 0x1p-53);
+      x[i] = or_qnorm(u[0], omu[0]);
+      y[i] = or_qnorm(v, omv);
+    } else {
+      double s[2], oms[2];
+      row_uniforms(seed, row, 1u, s, oms);
+      const double E1 = exp_variate(u[0], omu[0]), E2 = exp_variate(u[1], omu[1]);
+      const double alpha = 1.0 / theta;
+      double logS = 0.0;
+      if (theta != 1.0) {
+        const double T = M_PI * s[0];
+        const double W = exp_variate(s[1], oms[1]);
+        logS = log(sin(alpha * T)) - log(sin(T)) / alpha +
+               (1.0 - alpha) / alpha * (log(sin((1.0 - alpha) * T)) - log(W));
+      }
+      const double t1 = exp(alpha * (log(E1) - logS)), t2 = exp(alpha * (log(E2) - logS));
+      x[i] = qnorm_exp_neg(t1);
+      y[i] = qnorm_exp_neg(t2);
+    }
+  }
+}
+
+/* ======================================================================== */
+/* Sec. 2.6, eq. (19)-(20): distances between the copula densities at two
+ * parameter values, over the unit square, in normal-score coordinates
+ * u = Phi(s), v = Phi(t):  int int f(c(u, v)) du dv = int int f(c(Phi(s),
+ * Phi(t))) phi(s) phi(t) ds dt. The corners of the square move to infinity,
+ * where the transformed integrands decay, and the box |s|, |t| <= Lbox is
+ * integrated by composite Gauss-Legendre rules (m nodes on each of `panels`
+ * equal panels per axis; the nodes by Newton's method on the Legendre
+ * polynomial P_m). |c_a - c_b| has a kink where the densities cross: on each
+ * line s = const the inner integral of |c_a - c_b| is split at the crossings
+ * (located by bisection between sample points where the difference changes
+ * sign) and each piece integrated by the same rule. out[0] = int |c_a - c_b|,
+ * out[1] = int c_a, out[2] = int (c_a - c_b)^2, out[3] = int c_a^2, so that
+ * eq. (19) is out[0] / out[1] and eq. (20) is sqrt(out[2] / out[3]).        */
+static void gauss_legendre(int m, double* xn, double* wn) {
+  for (int i = 0; i < m; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (m + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) < 1e-16) break;
+    }
+    xn[i] = z;
+    wn[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+static double density_at(int32_t family, double theta, double u, double omu, double v, double omv) {
+  return exp(logc_value(family, theta, u, omu, v, omv));
+}
+
+typedef struct {
+  int32_t family;
+  double ta, tb, u, omu; /* the line s = const: u = Phi(s) */
+} dd_line;
+
+/* c_a - c_b at normal score t on the line */
+static double dd_diff(const dd_line* L, double t) {
+  const double v = Phi_cdf(t), omv = Phi_cdf(-t);
+  return density_at(L->family, L->ta, L->u, L->omu, v, omv) - density_at(L->family, L->tb, L->u, L->omu, v, omv);
+}
+
+/* int_a^b |c_a - c_b| phi(t) dt on the line by the m-point rule */
+static double dd_abs_piece(const dd_line* L, double a, double b, int m, const double* xn, const double* wn) {
+  double acc = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double t = 0.5 * (a + b) + 0.5 * (b - a) * xn[k];
+    acc += 0.5 * (b - a) * wn[k] * fabs(dd_diff(L, t)) * phi_pdf(t);
+  }
+  return acc;
+}
+
+void or_density_distance(int32_t family, double theta_a, double theta_b, double Lbox, int32_t panels, int32_t m,
+                         double out[4]) {
+  double xn[64], wn[64];
+  if (m > 64) m = 64;
+  gauss_legendre(m, xn, wn);
+  const int64_t N = (int64_t)panels * m;
+  double* s = (double*)malloc(sizeof(double) * (size_t)N);
+  double* w = (double*)malloc(sizeof(double) * (size_t)N);
+  double* u = (double*)malloc(sizeof(double) * (size_t)N);
+  double* omu = (double*)malloc(sizeof(double) * (size_t)N);
+  const double h = 2.0 * Lbox / panels;
+  for (int p = 0; p < panels; ++p)
+    for (int k = 0; k < m; ++k) {
+      const int64_t j = (int64_t)p * m + k;
+      s[j] = -Lbox + h * (p + 0.5 * (xn[k] + 1.0));
+      w[j] = 0.5 * h * wn[k] * phi_pdf(s[j]);
+      u[j] = Phi_cdf(s[j]);
+      omu[j] = Phi_cdf(-s[j]);
+    }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : acc[:4])
+  for (int64_t i = 0; i < N; ++i) {
+    const dd_line L = {family, theta_a, theta_b, u[i], omu[i]};
+    double row[4] = {0.0, 0.0, 0.0, 0.0};
+    double d[64 + 2], t[64 + 2];
+    for (int p = 0; p < panels; ++p) {
+      /* samples of the difference along the panel: its ends and the nodes */
+      const double a = -Lbox + h * p, b = a + h;
+      int ns = 0;
+      int change = 0;
+      t[ns] = a;
+      d[ns++] = (theta_b == theta_a) ? 0.0 : dd_diff(&L, a);
+      for (int k = 0; k < m; ++k) {
+        const int64_t j = (int64_t)p * m + k;
+        const double ca = density_at(family, theta_a, u[i], omu[i], u[j], omu[j]);
+        const double cb = (theta_b == theta_a) ? ca : density_at(family, theta_b, u[i], omu[i], u[j], omu[j]);
+        const double dd = ca - cb;
+        row[1] += ca * w[j];
+        row[2] += dd * dd * w[j];
+        row[3] += ca * ca * w[j];
+        t[ns] = s[j];
+        d[ns++] = dd;
+      }
+      t[ns] = b;
+      d[ns++] = (theta_b == theta_a) ? 0.0 : dd_diff(&L, b);
+      for (int q = 1; q < ns; ++q)
+        if ((d[q - 1] < 0.0 && d[q] > 0.0) || (d[q - 1] > 0.0 && d[q] < 0.0)) change = 1;
+      if (!change) {
+        for (int k = 0; k < m; ++k) row[0] += fabs(d[k + 1]) * w[(int64_t)p * m + k];
+        continue;
+      }
+      /* split the panel at every crossing and integrate the pieces */
+      double lo = a;
+      for (int q = 1; q < ns; ++q) {
+        if (!((d[q - 1] < 0.0 && d[q] > 0.0) || (d[q - 1] > 0.0 && d[q] < 0.0))) continue;
+        double x0 = t[q - 1], x1 = t[q], f0 = d[q - 1];
+        for (int it = 0; it < 200 && x1 - x0 > 1e-15 * (1.0 + fabs(x0)); ++it) {
+          const double xm = 0.5 * (x0 + x1), fm = dd_diff(&L, xm);
+          if ((fm < 0.0) == (f0 < 0.0)) { x0 = xm; f0 = fm; } else { x1 = xm; }
+        }
+        const double root = 0.5 * (x0 + x1);
+        row[0] += dd_abs_piece(&L, lo, root, m, xn, wn);
+        lo = root;
+      }
+      row[0] += dd_abs_piece(&L, lo, b, m, xn, wn);
+    }
+    for (int k = 0; k < 4; ++k) acc[k] += row[k] * w[i];
+  }
+  for (int k = 0; k < 4; ++k) out[k] = acc[k];
+  free(s); free(w); free(u); free(omu);
+}

@@ -88,6 +88,17 @@ void or_fit(const double* x, const double* y, const int64_t* offsets, int64_t K,
 
 int32_t or_num_threads(int32_t requested);
 
+/* Simulation inputs (Sec. 2.5) and evaluation metrics (Sec. 2.6). */
+/* Philox4x32-10 block of a counter and a key (Salmon et al., SC 2011). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Rows row0 .. row0+n-1 of the seeded stream of pairs with N(0,1) margins
+ * whose copula is the family's at theta. */
+void or_sample(int32_t family, double theta, uint64_t seed, int64_t row0, int64_t n, double* x, double* y);
+/* int |c_a - c_b|, int c_a, int (c_a - c_b)^2, int c_a^2 over the unit square
+ * (normal-score coordinates, |s|, |t| <= Lbox, composite Gauss-Legendre). */
+void or_density_distance(int32_t family, double theta_a, double theta_b, double Lbox, int32_t panels, int32_t m,
+                         double out[4]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,12 @@ def lib():
         L.or_fit.argtypes = [p, p, p, i64, p, i64, p, ctypes.POINTER(_Options), i32, p, p]
         L.or_num_threads.restype = i32
         L.or_num_threads.argtypes = [i32]
+        L.or_philox4x32_10.restype = None
+        L.or_philox4x32_10.argtypes = [p, p, p]
+        L.or_sample.restype = None
+        L.or_sample.argtypes = [i32, d, ctypes.c_uint64, i64, i64, p, p]
+        L.or_density_distance.restype = None
+        L.or_density_distance.argtypes = [i32, d, d, d, i32, i32, p]
         _lib = L
     return _lib
 
@@ -198,3 +204,48 @@ def combine(sub: np.ndarray, group_offsets) -> np.ndarray:
 
 def num_threads(requested: int = 0) -> int:
     return lib().or_num_threads(int(requested))
+
+
+# --------------------------------------------------------------------------
+# Simulation inputs and the evaluation metrics of Sec. 2.5-2.6.
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block of a 4-word counter and a 2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def sample(family, theta: float, seed: int, row0: int, n: int):
+    """Rows row0 .. row0+n-1 of the seeded stream of pairs with N(0,1)
+    margins and the family's copula at theta (the GPU sampler's definition)."""
+    x = np.empty(n, dtype=np.float64)
+    y = np.empty(n, dtype=np.float64)
+    lib().or_sample(_fam(family), float(theta), ctypes.c_uint64(int(seed)), int(row0), int(n), _ptr(x), _ptr(y))
+    return x, y
+
+
+def density_distance(family, theta_a: float, theta_b: float, box: float = 20.0, panels: int = 64,
+                     nodes: int = 16) -> np.ndarray:
+    """[int |c_a - c_b|, int c_a, int (c_a - c_b)^2, int c_a^2] over the unit
+    square (eq. 19 = [0]/[1], eq. 20 = sqrt([2]/[3])), in normal-score
+    coordinates over |s|, |t| <= box."""
+    out = np.empty(4, dtype=np.float64)
+    lib().or_density_distance(_fam(family), float(theta_a), float(theta_b), float(box), int(panels), int(nodes),
+                              _ptr(out))
+    return out
+
+
+def replicate_summary(comb_theta, comb_status, full_theta, full_status) -> np.ndarray:
+    """Sec. 2.6 over the replicates whose combined (eq. 16) and full-data
+    estimates both have status 0: [eq. (17), eq. (18), bias, MSE, count]."""
+    ct = np.asarray(comb_theta, dtype=np.float64)
+    ft = np.asarray(full_theta, dtype=np.float64)
+    use = (np.asarray(comb_status) == 0) & (np.asarray(full_status) == 0)
+    s = int(use.sum())
+    mc = float(np.sum(ct[use]) / s)
+    mf = float(np.sum(ft[use]) / s)
+    mse = float(np.sum((ct[use] - ft[use]) ** 2) / s)
+    return np.array([mc, mf, mc - mf, mse, float(s)])
