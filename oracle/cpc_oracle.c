@@ -256,9 +256,18 @@ static double asimpson_debye(double a, double b, double fa, double fm, double fb
 }
 double or_debye(int32_t k, double x) {
   if (x == 0.0) return 1.0;
-  double fa = debye_f(0.0, k), fb = debye_f(x, k), fm = debye_f(0.5 * x, k);
-  double whole = x / 6.0 * (fa + 4.0 * fm + fb);
-  double integral = asimpson_debye(0.0, x, fa, fm, fb, whole, 1e-15 * fabs(x) + 1e-300, k, 50);
+  /* the interval is cut into pieces of length at most 4 before the adaptive
+   * rule sees it: over [0, x] at once, the first samples of a long interval
+   * (x ~ 200) all fall where t^k / (e^t - 1) has died away and the rule stops
+   * on an estimate near zero */
+  const int pieces = (int)ceil(fabs(x) / 4.0);
+  double integral = 0.0;
+  for (int p = 0; p < pieces; ++p) {
+    const double a = x * p / pieces, b = x * (p + 1) / pieces;
+    double fa = debye_f(a, k), fb = debye_f(b, k), fm = debye_f(0.5 * (a + b), k);
+    double whole = (b - a) / 6.0 * (fa + 4.0 * fm + fb);
+    integral += asimpson_debye(a, b, fa, fm, fb, whole, 1e-16 * fabs(b - a) + 1e-300, k, 50);
+  }
   return (double)k / pow(x, (double)k) * integral;
 }
 

@@ -34,7 +34,7 @@ def test_printed_dependence_values(row):
 
 def test_debye_against_quadrature():
     for k in (1, 2):
-        for x in (-20.0, -3.0, 0.5, 5.0, 40.0):
+        for x in (-200.0, -20.0, -3.0, 0.5, 5.0, 40.0, 150.0, 200.0):
             ref = k / x**k * float(mpmath.quad(lambda t: t**k / mpmath.expm1(t) if t != 0 else (1 if k == 1 else 0), [0, x]))
             assert O.debye(k, x) == pytest.approx(ref, rel=1e-12)
 
