@@ -173,6 +173,30 @@ int cpc_fit_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype,
                     const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
                     size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
 
+/* Allocation-free form of cpc_fit_batched, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same arguments without the workspace, which is
+ * a static device array of the library (64 MiB per device, held from the
+ * library's first use of that device until the process ends). The call
+ * allocates nothing, never synchronises (no autotuning trials: a launch
+ * shape not yet chosen by an earlier cpc_fit / cpc_fit_batched on the handle
+ * takes the built-in one; the streaming path enqueues its whole Newton pass
+ * budget) and rejects CPC_FLAG_GRAPH (CPC_E_OPTIONS).
+ *   - A partition that needs more than 64 MiB of workspace
+ *     (cpc_workspace_bytes_for: about 28 bytes per row, + 88 per row of
+ *     subsets above 16384 rows, so ~2.3 M rows without such subsets) is
+ *     rejected with CPC_E_WORKSPACE before anything is enqueued.
+ *   - Every call on a device shares that device's array, which keeps the last
+ *     call's contents (nothing in it needs to start at zero). Calls that
+ *     overlap on one device (other streams, other threads, other handles)
+ *     race on it: serialise them.
+ *   - CPC_E_HIP if the array's device address could not be looked up.
+ */
+int cpc_fit_batched_noalloc(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+                            const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                            const int32_t* family_per_group, const cpc_options_t* opt,
+                            cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
+
 /* Ranks of eq. (12) within each subset, as doubled integers R = 2 r (so
  * average ties stay integral): u = R / (2 (n_m + 1)).
  *   R1, R2 : device, n values each, row order (same indexing as x, y).

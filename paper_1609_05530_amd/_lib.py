@@ -41,6 +41,8 @@ SIGNATURES = {
     "cpc_fit": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _I32, ctypes.POINTER(Options), _P, _SZ, _P, _P, _P]),
     "cpc_fit_batched": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P, _SZ,
                                _P, _P, _P]),
+    "cpc_fit_batched_noalloc": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P,
+                                       _P, _P]),
     "cpc_rank": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, ctypes.POINTER(Options), _P, _SZ, _P, _P, _P]),
     "cpc_eval": (_I32, [_P, _P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P]),
     "cpc_variance": (_I32, [_P, _P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P]),

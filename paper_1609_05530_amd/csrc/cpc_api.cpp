@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -40,6 +41,35 @@ struct cpc_context {
 };
 
 static constexpr int kMagic = 0x43504331;
+
+// Scratch of the allocation-free entry point (cpc_fit_batched_noalloc): the
+// workspace of such a call lives in this array. Each device the library runs
+// on holds its own copy, at its own address, until the process ends. Host
+// code never passes the array's name to a kernel (on the host it stands for
+// a host-side shadow); it uses the device address that cpc_create looks up
+// once per device with that device current.
+static constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+
+namespace {
+// Device address of `scratch` per device (nullptr until looked up) and the
+// error of a failed lookup.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Looks up the device's copy of `scratch` once (the device is current).
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  if (e == hipSuccess) g_scratch_ptr[device] = p;
+}
+}  // namespace
 
 namespace {
 
@@ -460,7 +490,7 @@ int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* 
                   int64_t G, const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph,
                   hipStream_t s);
 int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
-                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, hipStream_t s);
+                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, hipStream_t s, bool host_sync);
 
 // Autotuner: the rank kernel's launch shape per size class, chosen by timing
 // each candidate shape on the call's own subsets (the rank kernel is exact
@@ -512,8 +542,10 @@ RankParams rank_params(const Carved& c, const void* x, const void* y, const Opti
   return rp;
 }
 
+// With trials = false (a call that must not synchronise) a signature without
+// a recorded decision takes the built-in shape and records nothing.
 int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, const void* y, int kw,
-                       const Options& o, hipStream_t s) {
+                       const Options& o, hipStream_t s, bool trials) {
   Tuner& t = tuner_of(h);
   for (Bucket& b : P.rank_buckets) {
     b.shape = kRankDefaultShape[b.cls];
@@ -530,6 +562,7 @@ int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, 
       b.shape = it->second;
       continue;
     }
+    if (!trials) continue;
     RankParams rp = rank_params(c, x, y, o);
     rp.order = c.order_rank + b.first;
     float best = 0.0f;
@@ -560,10 +593,13 @@ int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, 
 }
 
 // The full fit path for validated arguments.
+// noalloc: the workspace is the static scratch and the call must neither
+// synchronise nor build a graph (no autotuning trials, no host wait in the
+// streaming path's Newton loop).
 int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
             int64_t K, const int64_t* gofs, int64_t G, const std::vector<int32_t>& fam_of_subset,
             const Options& o, void* ws, size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb,
-            hipStream_t s) {
+            hipStream_t s, bool noalloc = false) {
   const Layout L = layout(n, K, G, big_share(offsets, K));
   if (!ws) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < L.total)
@@ -587,9 +623,9 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
   rc = upload_tables(h, P, c, P.gofs.data(), G, s);
   if (rc) return rc;
   set_big(c, P, o.n_min);
-  rc = choose_rank_shapes(h, P, c, x, y, dtype == CPC_F64 ? 2 : 1, o, s);
+  rc = choose_rank_shapes(h, P, c, x, y, dtype == CPC_F64 ? 2 : 1, o, s, !noalloc);
   if (rc) return rc;
-  if (!graph) return enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, s);
+  if (!graph) return enqueue_fit(h, P, c, x, y, dtype, G, o, out, comb, s, !noalloc);
 
   // capture on the handle's stream once the uploads on `s` are done: one
   // graph, or one per phase when the phases are timed
@@ -686,13 +722,15 @@ int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* 
   }
 }
 
-// Eager launch of every phase, with the phase events when asked for.
+// Eager launch of every phase, with the phase events when asked for. Without
+// host_sync the streaming path enqueues its whole Newton pass budget (as in
+// graph capture) instead of waiting on its convergence counter.
 int enqueue_fit(cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype, int64_t G,
-                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, hipStream_t s) {
+                const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, hipStream_t s, bool host_sync) {
   const bool timed = (o.flags & CPC_FLAG_PHASE_TIMES) != 0;
   for (int ph = 0; ph < kPhases; ++ph) {
     if (timed) HIP_OK(hipEventRecord(h->ev[ph], s));
-    const int rc = enqueue_phase(ph, h, P, c, x, y, dtype, G, o, out, comb, false, s);
+    const int rc = enqueue_phase(ph, h, P, c, x, y, dtype, G, o, out, comb, !host_sync, s);
     if (rc) return rc;
   }
   if (timed) {
@@ -725,6 +763,7 @@ int cpc_create(int device, cpc_handle_t* out) {
   HIP_OK(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(CPC_E_SIZE, "device %d out of range (%d devices)", device, count);
   HIP_OK(hipSetDevice(device));
+  scratch_setup(device);
   cpc_context* h = new cpc_context();
   h->device = device;
   h->magic = kMagic;
@@ -814,10 +853,15 @@ int cpc_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
                  (hipStream_t)stream);
 }
 
-int cpc_fit_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
-                    const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
-                    const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
-                    size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream) {
+}  // extern "C"
+
+namespace {
+// Host checks of a batched fit's arguments; fills the options and the family
+// of every subset.
+int check_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
+                  int64_t K, const int64_t* group_offsets, int64_t G, const int32_t* family_per_group,
+                  const cpc_options_t* opt, const cpc_subset_result_t* out, const cpc_combined_t* comb, Options& o,
+                  std::vector<int32_t>& fam) {
   if (int rc = check_handle(h)) return rc;
   if (!x || !y || !offsets || !group_offsets || !family_per_group || !out || !comb)
     return fail(CPC_E_NULL, "a required pointer is NULL");
@@ -825,20 +869,60 @@ int cpc_fit_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype,
   if (K < 1) return fail(CPC_E_SIZE, "K < 1");
   if (G < 1) return fail(CPC_E_SIZE, "G < 1");
   if (dtype != CPC_F64 && dtype != CPC_F32) return fail(CPC_E_ENUM, "unknown dtype %d", dtype);
-  Options o;
   if (int rc = read_options(opt, o)) return rc;
   if (int rc = check_offsets(offsets, K, n)) return rc;
   if (group_offsets[0] != 0 || group_offsets[G] != K)
     return fail(CPC_E_OFFSETS, "group_offsets must run from 0 to K");
-  std::vector<int32_t> fam((size_t)K);
+  fam.assign((size_t)K, 0);
   for (int64_t g = 0; g < G; ++g) {
     if (group_offsets[g + 1] < group_offsets[g]) return fail(CPC_E_OFFSETS, "group_offsets decrease at %lld", (long long)g);
     if (family_per_group[g] < 0 || family_per_group[g] > 2)
       return fail(CPC_E_ENUM, "unknown family %d for group %lld", family_per_group[g], (long long)g);
     for (int64_t m = group_offsets[g]; m < group_offsets[g + 1]; ++m) fam[m] = family_per_group[g];
   }
+  return CPC_SUCCESS;
+}
+}  // namespace
+
+extern "C" {
+
+int cpc_fit_batched(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+                    const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                    const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
+                    size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream) {
+  Options o;
+  std::vector<int32_t> fam;
+  if (int rc = check_batched(h, x, y, dtype, n, offsets, K, group_offsets, G, family_per_group, opt, out, comb, o, fam))
+    return rc;
   return run_fit(h, x, y, dtype, n, offsets, K, group_offsets, G, fam, o, workspace, ws_bytes, out, comb,
                  (hipStream_t)stream);
+}
+
+int cpc_fit_batched_noalloc(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+                            const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                            const int32_t* family_per_group, const cpc_options_t* opt, cpc_subset_result_t* out,
+                            cpc_combined_t* comb, void* stream) {
+  Options o;
+  std::vector<int32_t> fam;
+  if (int rc = check_batched(h, x, y, dtype, n, offsets, K, group_offsets, G, family_per_group, opt, out, comb, o, fam))
+    return rc;
+  if (o.flags & CPC_FLAG_GRAPH)
+    return fail(CPC_E_OPTIONS, "CPC_FLAG_GRAPH builds a graph (an allocation); capture the call instead");
+  if (h->device >= kMaxDevices) return fail(CPC_E_UNSUPPORTED, "device %d: no scratch slot", h->device);
+  void* ws = nullptr;
+  hipError_t err = hipSuccess;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ws = g_scratch_ptr[h->device];
+    err = g_scratch_err[h->device];
+  }
+  if (!ws) return fail(CPC_E_HIP, "scratch of device %d unavailable: %s", h->device, hipGetErrorString(err));
+  const size_t need = layout(n, K, G, big_share(offsets, K)).total;
+  if (need > kScratchBytes)
+    return fail(CPC_E_WORKSPACE, "the call needs %zu bytes of scratch, the static scratch holds %zu", need,
+                kScratchBytes);
+  return run_fit(h, x, y, dtype, n, offsets, K, group_offsets, G, fam, o, ws, kScratchBytes, out, comb,
+                 (hipStream_t)stream, true);
 }
 
 int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
