@@ -259,14 +259,16 @@ double or_debye(int32_t k, double x) {
   /* the interval is cut into pieces of length at most 4 before the adaptive
    * rule sees it: over [0, x] at once, the first samples of a long interval
    * (x ~ 200) all fall where t^k / (e^t - 1) has died away and the rule stops
-   * on an estimate near zero */
+   * on an estimate near zero. The integrand has one sign on each piece, so
+   * the target error is relative to the piece's integral (for x < 0 it grows
+   * like |t|^k, and an absolute target falls below its rounding) */
   const int pieces = (int)ceil(fabs(x) / 4.0);
   double integral = 0.0;
   for (int p = 0; p < pieces; ++p) {
     const double a = x * p / pieces, b = x * (p + 1) / pieces;
     double fa = debye_f(a, k), fb = debye_f(b, k), fm = debye_f(0.5 * (a + b), k);
     double whole = (b - a) / 6.0 * (fa + 4.0 * fm + fb);
-    integral += asimpson_debye(a, b, fa, fm, fb, whole, 1e-16 * fabs(b - a) + 1e-300, k, 50);
+    integral += asimpson_debye(a, b, fa, fm, fb, whole, 1e-15 * fabs(whole) + 1e-300, k, 50);
   }
   return (double)k / pow(x, (double)k) * integral;
 }
@@ -901,4 +903,112 @@ void or_density_distance(int32_t family, double theta_a, double theta_b, double 
   }
   for (int k = 0; k < 4; ++k) out[k] = acc[k];
   free(s); free(w); free(u); free(omu);
+}
+
+/* ======================================================================== */
+/* The inversion of Spearman's rho (Sec. 2.3 names it beside the pseudo-
+ * likelihood): rho_S of the subset's ranks, theta with rho_S(theta) = rho_S
+ * hat (closed form for the Gaussian, bisection on the Debye-function form
+ * for Frank and on the quadrature form for Gumbel), and the asymptotic
+ * variance of this moment estimator by the same plug-in sandwich as the
+ * pseudo-likelihood's (Genest, Ghoudi & Rivest 1995): with
+ * J(u, v) = 12 (u - 1/2)(v - 1/2), psi_i = J_i + W1(u_i) + W2(v_i),
+ * W1(u_i) = (1/n) sum over u_l >= u_i of dJ/du (u_l, v_l), likewise W2, and
+ * sigma^2 = var(psi) / (n rho_S'(theta)^2).                                 */
+
+/* rho_S hat from doubled ranks: 12 / (n (n^2 - 1)) sum (r1 - (n+1)/2)(r2 - (n+1)/2) */
+double or_spearman(const int64_t* R1, const int64_t* R2, int64_t n) {
+  long double s = 0.0L;
+  for (int64_t i = 0; i < n; ++i) s += (long double)((R1[i] - (n + 1)) * (R2[i] - (n + 1)));
+  const double dn = (double)n;
+  return 3.0 * (double)s / (dn * (dn * dn - 1.0));
+}
+
+/* d rho_S / d theta by a central difference of or_rho_s (closed form for the
+ * Gaussian) */
+static double rho_s_slope(int32_t f, double th) {
+  if (f == OR_GAUSSIAN) return 3.0 / (M_PI * sqrt(1.0 - 0.25 * th * th));
+  const double h = 1e-4 * (1.0 + fabs(th));
+  double a = th - h, b = th + h;
+  if (f == OR_GUMBEL && a < 1.0) { a = 1.0; b = 1.0 + 2.0 * h; }
+  return (or_rho_s(f, b) - or_rho_s(f, a)) / (b - a);
+}
+
+/* theta with rho_S(theta) = r: status 0, 1 (Gumbel at theta = 1, r <= 0) or
+ * 2 (at the family's search box edge) */
+double or_spearman_theta(int32_t f, double r, int32_t* status) {
+  *status = OR_OK;
+  if (f == OR_GAUSSIAN) {
+    const double th = 2.0 * sin(M_PI * r / 6.0);
+    if (fabs(th) >= 1.0 - 1e-9) { *status = OR_BOUNDARY_BOX; return th > 0 ? 1.0 - 1e-9 : -(1.0 - 1e-9); }
+    return th;
+  }
+  double lo = box_lo(f), hi = box_hi(f);
+  if (f == OR_GUMBEL && r <= 0.0) { *status = OR_BOUNDARY_NATURAL; return 1.0; }
+  if (r <= or_rho_s(f, lo)) { *status = OR_BOUNDARY_BOX; return lo; }
+  if (r >= or_rho_s(f, hi)) { *status = OR_BOUNDARY_BOX; return hi; }
+  for (int it = 0; it < 200 && hi - lo > 1e-12 * (1.0 + fabs(lo)); ++it) {
+    const double m = 0.5 * (lo + hi);
+    if (or_rho_s(f, m) < r) lo = m; else hi = m;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* Variance of the Spearman-inversion estimate at theta (from the doubled
+ * ranks; the suffix sums by a sort of the rows by rank, ties taking the
+ * group's sum over u_l >= u_i). Returns var(psi) in *nu. */
+double or_spearman_var(const int64_t* R1, const int64_t* R2, int64_t n, int32_t f, double theta, double* nu) {
+  const double den = 2.0 * (n + 1.0);
+  double* g1 = (double*)malloc(sizeof(double) * (size_t)n);
+  double* g2 = (double*)malloc(sizeof(double) * (size_t)n);
+  double* W1 = (double*)malloc(sizeof(double) * (size_t)n);
+  double* W2 = (double*)malloc(sizeof(double) * (size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    g1[i] = 12.0 * ((double)R2[i] / den - 0.5); /* dJ/du = 12 (v - 1/2) */
+    g2[i] = 12.0 * ((double)R1[i] / den - 0.5); /* dJ/dv = 12 (u - 1/2) */
+  }
+  suffix_by_rank(R1, g1, n, W1);
+  suffix_by_rank(R2, g2, n, W2);
+  double sp = 0.0, sq = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double J = 12.0 * ((double)R1[i] / den - 0.5) * ((double)R2[i] / den - 0.5);
+    const double psi = J + W1[i] + W2[i]; /* (the suffix sums are already means) */
+    sp += psi;
+    sq += psi * psi;
+  }
+  free(g1); free(g2); free(W1); free(W2);
+  const double m = sp / n;
+  *nu = sq / n - m * m;
+  const double b = rho_s_slope(f, theta);
+  return *nu / (n * b * b);
+}
+
+/* The Spearman-inversion estimate of one subset from its doubled ranks:
+ * out->theta, out->var, out->loglik = rho_S hat, out->score = rho_S(theta) -
+ * rho_S hat, out->status (DEGENERATE below n_min rows or for a margin of one
+ * value). */
+void or_spearman_fit_ranks(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, int64_t n_min,
+                           or_subset* out) {
+  out->theta = NAN; out->var = NAN; out->loglik = NAN; out->score = NAN;
+  out->n = n; out->iters = 0; out->status = OR_OK;
+  if (n < (n_min < 2 ? 2 : n_min)) { out->status = OR_DEGENERATE; return; }
+  int same1 = 1, same2 = 1;
+  for (int64_t i = 1; i < n; ++i) {
+    if (R1[i] != R1[0]) same1 = 0;
+    if (R2[i] != R2[0]) same2 = 0;
+  }
+  if (same1 || same2) { out->status = OR_DEGENERATE; return; }
+  const double r = or_spearman(R1, R2, n);
+  int32_t st;
+  const double th = or_spearman_theta(family, r, &st);
+  out->theta = th;
+  out->status = st;
+  out->loglik = r;
+  out->score = or_rho_s(family, th) - r;
+  if (st == OR_OK || st == OR_BOUNDARY_NATURAL) {
+    double nu;
+    const double v = or_spearman_var(R1, R2, n, family, th, &nu);
+    out->var = v;
+    if (!(v > 0.0) || !isfinite(v)) out->status = OR_BADVAR;
+  }
 }
