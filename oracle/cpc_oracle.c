@@ -945,13 +945,31 @@ double or_spearman_theta(int32_t f, double r, int32_t* status) {
   }
   double lo = box_lo(f), hi = box_hi(f);
   if (f == OR_GUMBEL && r <= 0.0) { *status = OR_BOUNDARY_NATURAL; return 1.0; }
-  if (r <= or_rho_s(f, lo)) { *status = OR_BOUNDARY_BOX; return lo; }
-  if (r >= or_rho_s(f, hi)) { *status = OR_BOUNDARY_BOX; return hi; }
-  for (int it = 0; it < 200 && hi - lo > 1e-12 * (1.0 + fabs(lo)); ++it) {
-    const double m = 0.5 * (lo + hi);
-    if (or_rho_s(f, m) < r) lo = m; else hi = m;
+  double flo = or_rho_s(f, lo) - r, fhi = or_rho_s(f, hi) - r;
+  if (flo >= 0.0) { *status = OR_BOUNDARY_BOX; return lo; }
+  if (fhi <= 0.0) { *status = OR_BOUNDARY_BOX; return hi; }
+  /* rho_S increases in theta: the root stays bracketed by [lo, hi];
+   * regula falsi with the Illinois halving of the retained end, bisection
+   * where the secant point leaves the bracket */
+  double m = lo, prev = hi;
+  int side = 0;
+  for (int it = 0; it < 200; ++it) {
+    m = (lo * fhi - hi * flo) / (fhi - flo);
+    if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
+    const double fm = or_rho_s(f, m) - r;
+    if (fm == 0.0 || fabs(m - prev) <= 1e-13 * (1.0 + fabs(m)) || hi - lo <= 1e-12 * (1.0 + fabs(lo))) break;
+    prev = m;
+    if (fm < 0.0) {
+      lo = m; flo = fm;
+      if (side == -1) fhi *= 0.5;
+      side = -1;
+    } else {
+      hi = m; fhi = fm;
+      if (side == 1) flo *= 0.5;
+      side = 1;
+    }
   }
-  return 0.5 * (lo + hi);
+  return m;
 }
 
 /* Variance of the Spearman-inversion estimate at theta (from the doubled

@@ -99,6 +99,17 @@ void or_sample(int32_t family, double theta, uint64_t seed, int64_t row0, int64_
 void or_density_distance(int32_t family, double theta_a, double theta_b, double Lbox, int32_t panels, int32_t m,
                          double out[4]);
 
+/* The inversion of Spearman's rho as an estimator (Sec. 2.3). */
+/* rho_S hat of doubled ranks */
+double or_spearman(const int64_t* R1, const int64_t* R2, int64_t n);
+/* theta with rho_S(theta) = r; status OK, BOUNDARY_NATURAL or BOUNDARY_BOX */
+double or_spearman_theta(int32_t family, double r, int32_t* status);
+/* variance of the estimate at theta (plug-in sandwich); var(psi) in *nu */
+double or_spearman_var(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, double theta, double* nu);
+/* one subset from its doubled ranks (loglik = rho_S hat, score = rho_S(theta) - rho_S hat) */
+void or_spearman_fit_ranks(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, int64_t n_min,
+                           or_subset* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,6 +97,14 @@ def lib():
         L.or_sample.argtypes = [i32, d, ctypes.c_uint64, i64, i64, p, p]
         L.or_density_distance.restype = None
         L.or_density_distance.argtypes = [i32, d, d, d, i32, i32, p]
+        L.or_spearman.restype = d
+        L.or_spearman.argtypes = [p, p, i64]
+        L.or_spearman_theta.restype = d
+        L.or_spearman_theta.argtypes = [i32, d, p]
+        L.or_spearman_var.restype = d
+        L.or_spearman_var.argtypes = [p, p, i64, i32, d, p]
+        L.or_spearman_fit_ranks.restype = None
+        L.or_spearman_fit_ranks.argtypes = [p, p, i64, i32, i64, p]
         _lib = L
     return _lib
 
@@ -249,3 +257,51 @@ def replicate_summary(comb_theta, comb_status, full_theta, full_status) -> np.nd
     mf = float(np.sum(ft[use]) / s)
     mse = float(np.sum((ct[use] - ft[use]) ** 2) / s)
     return np.array([mc, mf, mc - mf, mse, float(s)])
+
+
+# --------------------------------------------------------------------------
+# The inversion of Spearman's rho as an estimator (Sec. 2.3).
+
+def spearman(R1, R2) -> float:
+    """rho_S hat from doubled ranks."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    return lib().or_spearman(_ptr(R1), _ptr(R2), R1.shape[0])
+
+
+def spearman_theta(family, r: float):
+    """theta with rho_S(theta) = r, and the status (0, 1 natural boundary, 2 box edge)."""
+    st = ctypes.c_int32()
+    th = lib().or_spearman_theta(_fam(family), float(r), ctypes.byref(st))
+    return th, st.value
+
+
+def spearman_var(R1, R2, family, theta: float):
+    """(variance of the estimate, var(psi)) at theta."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    nu = ctypes.c_double()
+    v = lib().or_spearman_var(_ptr(R1), _ptr(R2), R1.shape[0], _fam(family), float(theta), ctypes.byref(nu))
+    return v, nu.value
+
+
+def spearman_fit_ranks(R1, R2, offsets, family, group_offsets=None, n_min=2):
+    """Per subset from doubled ranks, and the combination of eq. (15) per group."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    K = offsets.shape[0] - 1
+    if group_offsets is None:
+        group_offsets = np.array([0, K], dtype=np.int64)
+    group_offsets = np.ascontiguousarray(group_offsets, dtype=np.int64)
+    G = group_offsets.shape[0] - 1
+    fams = [family] * G if isinstance(family, (str, int, np.integer)) else list(family)
+    sub = np.zeros(K, dtype=SUBSET_DTYPE)
+    L = lib()
+    for g in range(G):
+        for m in range(group_offsets[g], group_offsets[g + 1]):
+            a, b = offsets[m], offsets[m + 1]
+            one = np.zeros(1, dtype=SUBSET_DTYPE)
+            L.or_spearman_fit_ranks(_ptr(R1[a:b]), _ptr(R2[a:b]), b - a, _fam(fams[g]), int(n_min), _ptr(one))
+            sub[m] = one[0]
+    return sub, combine(sub, group_offsets)
