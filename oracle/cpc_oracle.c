@@ -929,9 +929,13 @@ double or_spearman(const int64_t* R1, const int64_t* R2, int64_t n) {
 static double rho_s_slope(int32_t f, double th) {
   if (f == OR_GAUSSIAN) return 3.0 / (M_PI * sqrt(1.0 - 0.25 * th * th));
   const double h = 1e-4 * (1.0 + fabs(th));
-  double a = th - h, b = th + h;
-  if (f == OR_GUMBEL && a < 1.0) { a = 1.0; b = 1.0 + 2.0 * h; }
-  return (or_rho_s(f, b) - or_rho_s(f, a)) / (b - a);
+  if (f == OR_GUMBEL && th - h < 1.0) {
+    /* at the edge of the parameter space: the one-sided derivative, by the
+     * second-order forward difference (-3 f(a) + 4 f(a + h) - f(a + 2h)) / 2h */
+    const double a = th;
+    return (-3.0 * or_rho_s(f, a) + 4.0 * or_rho_s(f, a + h) - or_rho_s(f, a + 2.0 * h)) / (2.0 * h);
+  }
+  return (or_rho_s(f, th + h) - or_rho_s(f, th - h)) / (2.0 * h);
 }
 
 /* theta with rho_S(theta) = r: status 0, 1 (Gumbel at theta = 1, r <= 0) or

@@ -55,6 +55,26 @@ def test_variance_under_independence():
     assert n * v == pytest.approx((math.pi / 3.0) ** 2 * nu, rel=1e-12)  # (d theta / d rho_S)^2 at 0
 
 
+@pytest.mark.parametrize("fam,th,slope", [
+    # Gumbel at theta = 1: a(w) = 1 and d a / d theta = w log w + (1 - w) log(1 - w), so
+    # d rho_S / d theta = -24/8 int_0^1 (w log w + (1 - w) log(1 - w)) dw = 3/2 (one-sided)
+    ("gumbel", 1.0, 1.5),
+    # Frank near independence: rho_S = theta/6 - theta^3/450 + ...
+    ("frank", 0.0, 1.0 / 6.0),
+    ("frank", 0.5, 1.0 / 6.0 - 0.25 / 150.0 + 0.0625 / 4704.0),
+])
+def test_variance_slope_closed_forms(fam, th, slope):
+    """The variance divides var(psi) by n rho_S'(theta)^2; at these points
+    rho_S' has a closed form. The oracle differences rho_S, itself integrated
+    to ~1e-11, over steps of 1e-4: 2e-6 relative (a first-order difference at
+    Gumbel's edge is off by 4e-4)."""
+    rng = np.random.default_rng(12)
+    n = 500
+    R1 = O.ranks(rng.standard_normal(n)); R2 = O.ranks(rng.standard_normal(n))
+    v, nu = O.spearman_var(R1, R2, fam, th)
+    assert math.sqrt(nu / (n * v)) == pytest.approx(slope, rel=2e-6)
+
+
 def test_variance_brute_force_with_ties():
     rng = np.random.default_rng(9)
     n = 40
