@@ -220,6 +220,78 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
                  const cpc_options_t* opt, void* workspace, size_t ws_bytes, double* var,
                  void* stream);
 
+/* Simulation input of Sec. 2.5 drawn on the device: rows row0 .. row0+n-1
+ * of a stream of pairs (x, y) with N(0,1) margins whose copula is `family`
+ * at theta (eq. 8, 10, 11), written to the device arrays x, y (n values of
+ * type dtype: FP64, or the FP64 draw rounded to FP32).
+ *   Generator: Philox4x32-10 (Salmon et al., SC 2011) at counter (row low
+ *   word, row high word, block, 0) with key (seed low word, seed high word);
+ *   each block gives two uniforms u = (k + 1/2) 2^-52 from 52 of its bits.
+ *   Row r of a stream depends only on (family, theta, seed, r), so a
+ *   replicate study draws replicate s as rows [s N, (s + 1) N).
+ *   Gaussian: Cholesky factor of the correlation matrix applied to two
+ *   N(0,1) draws; Frank: conditional inversion of dC/du in closed form;
+ *   Gumbel: Marshall-Olkin with a positive stable frailty drawn by Kanter's
+ *   representation. CPC_E_OPTIONS if theta is outside the family's range
+ *   (Gaussian |rho| < 1, Frank finite, Gumbel theta >= 1). */
+int cpc_sample(cpc_handle_t h, int32_t family, double theta, uint64_t seed, int64_t row0, int64_t n,
+               int32_t dtype, void* x, void* y, void* stream);
+
+/* Distances of Sec. 2.6 between the densities c_a = c(.; theta_a[p]) and
+ * c_b = c(.; theta_b[p]) of one family, for p = 0 .. P-1 (device arrays):
+ *   out[4p + 0] = int |c_a - c_b|,  out[4p + 1] = int c_a,
+ *   out[4p + 2] = int (c_a - c_b)^2, out[4p + 3] = int c_a^2
+ * over the unit square, so that eq. (19) is out[4p] / out[4p + 1] and
+ * eq. (20) is sqrt(out[4p + 2] / out[4p + 3]). Integrated in normal-score
+ * coordinates u = Phi(s), v = Phi(t) over |s|, |t| <= box with `panels`
+ * equal panels per axis and the 8-point Gauss-Legendre rule on each, the
+ * inner integral of |c_a - c_b| split where the densities cross. box = 20
+ * holds the squared Gaussian density to 1e-9 up to |rho| = 0.9 (its L2 mass
+ * reaches far along the diagonal). The Gumbel density is not square
+ * integrable at (1, 1): its out[4p + 2], out[4p + 3] grow with box and
+ * eq. (20) is the ratio over the box; box = 8.3 (u, v within 1e-16 of the
+ * square's edges) keeps its band along the diagonal resolved by 256 panels
+ * up to theta = 5. workspace: device, at least
+ * 32 * P * panels bytes. out: device, 4P doubles. */
+int cpc_density_distance(cpc_handle_t h, int32_t family, int64_t P, const double* theta_a,
+                         const double* theta_b, double box, int32_t panels, void* workspace,
+                         size_t ws_bytes, double* out, void* stream);
+
+/* Sec. 2.5-2.6 over S replicates: combined[s] from the subsets of replicate
+ * s (eq. 16, a cpc_fit_batched group) and full[s] from its full data (a
+ * group of one subset), device arrays. Replicates whose two results both
+ * have status 0 enter: out[0] = eq. (17), out[1] = eq. (18), out[2] = the
+ * estimated bias out[0] - out[1], out[3] = the estimated MSE (mean squared
+ * difference of the two estimates), out[4] = replicates used (device, 5
+ * doubles). */
+int cpc_replicate_summary(cpc_handle_t h, int64_t S, const cpc_combined_t* combined,
+                          const cpc_combined_t* full, double* out, void* stream);
+
+/* Workspace bytes of cpc_spearman_fit for n rows, K subsets and G groups. */
+size_t cpc_spearman_workspace_bytes(int64_t n, int64_t K, int64_t G);
+
+/* The inversion of Spearman's rho as the estimator of each subset (Sec. 2.3
+ * names it beside the pseudo-likelihood), combined per group by eq. (15):
+ *   rho_S hat = 12 / (n (n^2 - 1)) sum (r1 - (n+1)/2)(r2 - (n+1)/2) from the
+ *   doubled ranks R1, R2 (device, n each, as made by cpc_rank; any subset
+ *   size), theta with rho_S(theta) = rho_S hat (Gaussian 2 sin(pi rho_S / 6);
+ *   Frank through its Debye-function form; Gumbel through its Pickands
+ *   function, rho_S = 12 int_0^1 (1 + a(w))^-2 dw - 3), and the variance of
+ *   the estimate by the plug-in sandwich of the moment equation
+ *   12 (u - 1/2)(v - 1/2) = rho_S(theta): var(psi) / (n rho_S'(theta)^2) with
+ *   psi_i = J_i + W1(u_i) + W2(v_i) (W as in the pseudo-likelihood's variance).
+ * out (device, K): theta, var, loglik = rho_S hat, score = rho_S(theta) -
+ * rho_S hat, n, iters (Newton steps), status (DEGENERATE for fewer than
+ * n_min rows or a margin of one value; Gumbel with rho_S hat <= 0 gives
+ * theta = 1, BOUNDARY_NATURAL; beyond the search box BOUNDARY_BOX).
+ * comb (device, G): eq. (15) over the OK / BOUNDARY_NATURAL subsets of each
+ * group. Of opt only n_min is used. workspace: device, at least
+ * cpc_spearman_workspace_bytes(n, K, G). */
+int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n,
+                     const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                     const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
+                     size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
+
 /* Durations (milliseconds) of the phases of the handle's last cpc_fit /
  * cpc_fit_batched call made with CPC_FLAG_PHASE_TIMES: ms[0] ranks (eq. 12),
  * ms[1] maximisation of eq. (13), ms[2] variance (Sec. 2.3), ms[3] combine

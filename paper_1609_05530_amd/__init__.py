@@ -27,7 +27,7 @@ STATUS = {0: "OK", 1: "BOUNDARY_NATURAL", 2: "BOUNDARY_BOX", 3: "DEGENERATE", 4:
           6: "BADVAR"}
 
 __all__ = ["fit", "fit_batched", "rank", "eval_subsets", "variance", "LogLik", "Score", "FitResult",
-           "CpcError", "workspace_bytes", "FAMILIES", "STATUS"]
+           "CpcError", "workspace_bytes", "sample", "density_distance", "replicate_summary", "spearman_fit", "FAMILIES", "STATUS"]
 
 
 def _code(table, v):
@@ -278,3 +278,101 @@ class Score(torch.autograd.Function):
     def backward(ctx, g):
         (hess,) = ctx.saved_tensors
         return g * hess, None, None, None, None, None
+
+
+# --------------------------------------------------------------------------
+# The simulation study of Sec. 2.5-2.6 (inputs drawn on the device, metrics)
+
+def _device(device) -> torch.device:
+    if device is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    d = torch.device(device)
+    return torch.device("cuda", d.index if d.index is not None else torch.cuda.current_device())
+
+
+def sample(family, theta: float, n: int, *, seed: int = 0, row0: int = 0, dtype=torch.float64, device=None):
+    """Rows row0 .. row0+n-1 of the seeded stream of pairs with N(0, 1)
+    margins and the family's copula at theta (Sec. 2.5), drawn on the GPU."""
+    dev = _device(device)
+    x = torch.empty(int(n), dtype=dtype, device=dev)
+    y = torch.empty(int(n), dtype=dtype, device=dev)
+    check(lib().cpc_sample(_handle(dev), _code(FAMILIES, family), float(theta), ctypes.c_uint64(int(seed)),
+                           int(row0), int(n), _dtype_code(x), x.data_ptr(), y.data_ptr(), _stream(dev)))
+    return x, y
+
+
+def _theta_vec(t, dev) -> torch.Tensor:
+    if isinstance(t, torch.Tensor):
+        return t.to(device=dev, dtype=torch.float64).reshape(-1).contiguous()
+    return torch.as_tensor(np.atleast_1d(np.asarray(t, dtype=np.float64)), device=dev)
+
+
+# Normal-score box of the density distances per family: 20 holds the
+# squared Gaussian density to 1e-9 up to |rho| = 0.9; the Gumbel density's
+# square is not integrable at (1, 1), its integrals grow with the box, and
+# over |s|, |t| <= 8.3 (u, v within 1e-16 of the square's edges) the rule
+# resolves it.
+DISTANCE_BOX = {"gaussian": 20.0, "frank": 20.0, "gumbel": 8.3}
+
+
+def density_distance(family, theta_a, theta_b, *, panels: int = 256, box: Optional[float] = None,
+                     device=None) -> torch.Tensor:
+    """(P, 4) tensor per parameter pair: int |c_a - c_b|, int c_a,
+    int (c_a - c_b)^2, int c_a^2 over the unit square (eq. 19 = [:, 0] / [:, 1],
+    eq. 20 = sqrt([:, 2] / [:, 3])), in normal-score coordinates over
+    |s|, |t| <= box (default DISTANCE_BOX[family])."""
+    if box is None:
+        box = DISTANCE_BOX[family if isinstance(family, str) else [k for k, v in FAMILIES.items() if v == family][0]]
+    dev = _device(device if device is not None else (theta_a.device if isinstance(theta_a, torch.Tensor) else None))
+    ta = _theta_vec(theta_a, dev)
+    tb = _theta_vec(theta_b, dev)
+    if ta.numel() != tb.numel():
+        raise ValueError("theta_a and theta_b must have the same length")
+    P = ta.numel()
+    ws = torch.empty(32 * P * int(panels), dtype=torch.uint8, device=dev)
+    out = torch.empty((P, 4), dtype=torch.float64, device=dev)
+    check(lib().cpc_density_distance(_handle(dev), _code(FAMILIES, family), P, ta.data_ptr(), tb.data_ptr(),
+                                     float(box), int(panels), ws.data_ptr(), ws.numel(), out.data_ptr(),
+                                     _stream(dev)))
+    return out
+
+
+def replicate_summary(combined: torch.Tensor, full: torch.Tensor) -> torch.Tensor:
+    """[eq. 17, eq. 18, bias, MSE, replicates used] from the per-replicate
+    combined results (eq. 16) and full-data results ((S, 5) float64 views of
+    cpc_combined_t, e.g. FitResult.raw_comb)."""
+    combined = _dev(combined.contiguous(), "combined")
+    full = _dev(full.contiguous(), "full")
+    if combined.shape != full.shape or combined.dim() != 2 or combined.shape[1] != 5:
+        raise ValueError("combined and full must be (S, 5) views of cpc_combined_t")
+    out = torch.empty(5, dtype=torch.float64, device=combined.device)
+    check(lib().cpc_replicate_summary(_handle(combined.device), combined.shape[0], combined.data_ptr(),
+                                      full.data_ptr(), out.data_ptr(), _stream(combined.device)))
+    return out
+
+
+def spearman_fit(R1: torch.Tensor, R2: torch.Tensor, offsets, families, group_offsets=None, *, n_min: int = 2,
+                 workspace: Optional[torch.Tensor] = None) -> FitResult:
+    """The inversion of Spearman's rho per subset from doubled ranks (as made
+    by rank()), combined per group by eq. (15). ``families``: one family, or
+    one per group."""
+    R1 = _dev(R1, "R1")
+    R2 = _dev(R2, "R2")
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    gofs = _i64(group_offsets if group_offsets is not None else [0, K])
+    G = gofs.shape[0] - 1
+    if isinstance(families, (str, int)):
+        families = [families] * G
+    fams = np.ascontiguousarray([_code(FAMILIES, f) for f in families], dtype=np.int32)
+    n = R1.shape[0]
+    o = _options(n_min=n_min)
+    nbytes = int(lib().cpc_spearman_workspace_bytes(n, K, G))
+    ws = _workspace(nbytes, R1.device, workspace)
+    out = FitResult(torch.empty((K, 6), dtype=torch.float64, device=R1.device),
+                    torch.empty((G, 5), dtype=torch.float64, device=R1.device))
+    check(lib().cpc_spearman_fit(_handle(R1.device), R1.data_ptr(), R2.data_ptr(), n, offsets.ctypes.data, K,
+                                 gofs.ctypes.data, G, fams.ctypes.data, ctypes.byref(o), ws.data_ptr(),
+                                 ws.numel() * ws.element_size(), out.raw.data_ptr(), out.raw_comb.data_ptr(),
+                                 _stream(R1.device)))
+    return out

@@ -46,6 +46,12 @@ SIGNATURES = {
     "cpc_rank": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, ctypes.POINTER(Options), _P, _SZ, _P, _P, _P]),
     "cpc_eval": (_I32, [_P, _P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P]),
     "cpc_variance": (_I32, [_P, _P, _P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P]),
+    "cpc_sample": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_uint64, _I64, _I64, _I32, _P, _P, _P]),
+    "cpc_density_distance": (_I32, [_P, _I32, _I64, _P, _P, ctypes.c_double, _I32, _P, _SZ, _P, _P]),
+    "cpc_replicate_summary": (_I32, [_P, _I64, _P, _P, _P, _P]),
+    "cpc_spearman_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
+    "cpc_spearman_fit": (_I32, [_P, _P, _P, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P,
+                                _P]),
     "cpc_phase_times": (_I32, [_P, ctypes.POINTER(ctypes.c_float)]),
     "cpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cpc_last_error": (ctypes.c_char_p, []),

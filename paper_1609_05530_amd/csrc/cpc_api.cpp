@@ -1057,6 +1057,113 @@ int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, 
   return CPC_SUCCESS;
 }
 
+int cpc_sample(cpc_handle_t h, int32_t family, double theta, uint64_t seed, int64_t row0, int64_t n, int32_t dtype,
+               void* x, void* y, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (n < 0 || row0 < 0) return fail(CPC_E_SIZE, "n and row0 must be >= 0");
+  if (n > 0 && (!x || !y)) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (dtype != CPC_F64 && dtype != CPC_F32) return fail(CPC_E_ENUM, "unknown dtype %d", dtype);
+  if (family < 0 || family > 2) return fail(CPC_E_ENUM, "unknown family %d", family);
+  const bool ok = family == CPC_GAUSSIAN ? (theta > -1.0 && theta < 1.0)
+                                         : (family == CPC_FRANK ? std::isfinite(theta) : (theta >= 1.0 && std::isfinite(theta)));
+  if (!ok) return fail(CPC_E_OPTIONS, "theta = %g is outside the family's parameter range", theta);
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(launch_sample(family, theta, seed, row0, n, dtype == CPC_F32 ? 1 : 0, x, y, (hipStream_t)stream));
+  return CPC_SUCCESS;
+}
+
+int cpc_density_distance(cpc_handle_t h, int32_t family, int64_t P, const double* theta_a, const double* theta_b,
+                         double box, int32_t panels, void* workspace, size_t ws_bytes, double* out, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!theta_a || !theta_b || !out) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (family < 0 || family > 2) return fail(CPC_E_ENUM, "unknown family %d", family);
+  if (P < 1 || P > 65535) return fail(CPC_E_SIZE, "P must be in [1, 65535] (got %lld)", (long long)P);
+  if (panels < 1 || panels > 65535) return fail(CPC_E_SIZE, "panels must be in [1, 65535] (got %d)", panels);
+  if (!(box > 0.0) || !(box <= 40.0)) return fail(CPC_E_OPTIONS, "box must be in (0, 40] (got %g)", box);
+  const size_t need = sizeof(double) * 4 * (size_t)P * (size_t)panels;
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(launch_density_distance(family, P, theta_a, theta_b, box, panels, (double*)workspace, out,
+                                 (hipStream_t)stream));
+  return CPC_SUCCESS;
+}
+
+int cpc_replicate_summary(cpc_handle_t h, int64_t S, const cpc_combined_t* combined, const cpc_combined_t* full,
+                          double* out, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!combined || !full || !out) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (S < 1) return fail(CPC_E_SIZE, "S < 1");
+  HIP_OK(hipSetDevice(h->device));
+  HIP_OK(launch_replicate_summary(S, (const CombinedOut*)combined, (const CombinedOut*)full, out,
+                                  (hipStream_t)stream));
+  return CPC_SUCCESS;
+}
+
+size_t cpc_spearman_workspace_bytes(int64_t n, int64_t K, int64_t G) {
+  if (n < 0 || K < 1 || G < 1) return 0;
+  return align_up(sizeof(SubDesc) * (size_t)K) + align_up(sizeof(int64_t) * (size_t)(G + 1)) +
+         2 * align_up(sizeof(long long) * 2 * (size_t)(n + K));
+}
+
+int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets,
+                     int64_t K, const int64_t* group_offsets, int64_t G, const int32_t* family_per_group,
+                     const cpc_options_t* opt, void* workspace, size_t ws_bytes, cpc_subset_result_t* out,
+                     cpc_combined_t* comb, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!R1 || !R2 || !offsets || !group_offsets || !family_per_group || !out || !comb)
+    return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1 || G < 1) return fail(CPC_E_SIZE, "K and G must be >= 1");
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  if (group_offsets[0] != 0 || group_offsets[G] != K) return fail(CPC_E_OFFSETS, "group_offsets must run from 0 to K");
+  std::vector<SubDesc> subs((size_t)K);
+  for (int64_t g = 0; g < G; ++g) {
+    if (group_offsets[g + 1] < group_offsets[g]) return fail(CPC_E_OFFSETS, "group_offsets decrease at %lld", (long long)g);
+    if (family_per_group[g] < 0 || family_per_group[g] > 2)
+      return fail(CPC_E_ENUM, "unknown family %d for group %lld", family_per_group[g], (long long)g);
+    for (int64_t m = group_offsets[g]; m < group_offsets[g + 1]; ++m) {
+      subs[m].begin = offsets[m];
+      subs[m].n = (int32_t)(offsets[m + 1] - offsets[m]);
+      subs[m].family = (int16_t)family_per_group[g];
+      subs[m].group = 0;
+    }
+  }
+  const size_t need = cpc_spearman_workspace_bytes(n, K, G);
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+  unsigned char* b = (unsigned char*)workspace;
+  SubDesc* dsubs = (SubDesc*)b;
+  b += align_up(sizeof(SubDesc) * (size_t)K);
+  int64_t* dgofs = (int64_t*)b;
+  b += align_up(sizeof(int64_t) * (size_t)(G + 1));
+  long long* H1 = (long long*)b;
+  b += align_up(sizeof(long long) * 2 * (size_t)(n + K));
+  long long* H2 = (long long*)b;
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  touch_workspace(h, workspace);
+  // the host tables stay alive in the handle until the next call (the copies are asynchronous)
+  Plan& P = plan_of(h);
+  P.subs = subs;
+  P.gofs.assign(group_offsets, group_offsets + G + 1);
+  HIP_OK(hipMemcpyAsync(dsubs, P.subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dgofs, P.gofs.data(), sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
+  // one launch per run of groups of one family (subsets in order)
+  for (int64_t g = 0; g < G;) {
+    int64_t h2 = g;
+    while (h2 < G && family_per_group[h2] == family_per_group[g]) ++h2;
+    const int64_t m0 = group_offsets[g], m1 = group_offsets[h2];
+    if (m1 > m0)
+      HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, H1, H2, (ResultOut*)out, s));
+    g = h2;
+  }
+  HIP_OK(launch_combine((const ResultOut*)out, dgofs, G, (CombinedOut*)comb, s));
+  return CPC_SUCCESS;
+}
+
 int cpc_phase_times(cpc_handle_t h, float* ms) {
   if (int rc = check_handle(h)) return rc;
   if (!ms) return fail(CPC_E_NULL, "ms is NULL");

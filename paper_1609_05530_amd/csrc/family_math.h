@@ -87,9 +87,9 @@ CPC_HD PObs<T> pobs(uint32_t R, uint32_t twon1, T inv_twon1) {
 // doubled rank R with p = R / twon1; the central variable q = p - 1/2 and the
 // tail variable min(p, 1-p) are formed from integers, so the tails keep full
 // relative accuracy.
-CPC_HD double qnorm_ppnd16(int64_t R, int64_t twon1) {
-  const double inv = 1.0 / (double)twon1;
-  const double q = (double)(2 * R - twon1) * 0.5 * inv;  // p - 1/2
+// PPND16 from the central variable q = p - 1/2 and the tail probability
+// min(p, 1 - p) (each formed exactly by the caller).
+CPC_HD double qnorm_ppnd16_qt(double q, double tail) {
   if (fabs(q) <= 0.425) {
     const double r = 0.180625 - q * q;
     const double num = (((((((2.5090809287301226727e3 * r + 3.3430575583588128105e4) * r +
@@ -102,8 +102,7 @@ CPC_HD double qnorm_ppnd16(int64_t R, int64_t twon1) {
                           4.2313330701600911252e1) * r + 1.0);
     return q * num / den;
   }
-  const int64_t m = (2 * R < twon1) ? R : (twon1 - R);
-  double r = sqrt(-log((double)m * inv));
+  double r = sqrt(-log(tail));
   double z;
   if (r <= 5.0) {
     r -= 1.6;
@@ -127,6 +126,17 @@ CPC_HD double qnorm_ppnd16(int64_t R, int64_t twon1) {
           5.99832206555887937690e-1) * r + 1.0);
   }
   return (q < 0.0) ? -z : z;
+}
+CPC_HD double qnorm_ppnd16(int64_t R, int64_t twon1) {
+  const double inv = 1.0 / (double)twon1;
+  const double q = (double)(2 * R - twon1) * 0.5 * inv;  // p - 1/2
+  const int64_t m = (2 * R < twon1) ? R : (twon1 - R);
+  return qnorm_ppnd16_qt(q, (double)m * inv);
+}
+// Phi^{-1}(p) given p and 1 - p (each exact), from the smaller tail.
+CPC_HD double qnorm_p(double p, double omp) {
+  if (p == omp) return 0.0;
+  return p < omp ? qnorm_ppnd16_qt(p - 0.5, p) : qnorm_ppnd16_qt(0.5 - omp, omp);
 }
 
 CPC_HD float qnorm_ppnd7(int64_t R, int64_t twon1) {

@@ -1,0 +1,313 @@
+// k_moment.hip — the inversion of Spearman's rho as an estimator of the
+// copula parameter (Sec. 2.3 of arXiv:1609.05530 names it beside the
+// pseudo-likelihood), per subset from its doubled ranks (eq. 12), combined
+// by eq. (15) like the pseudo-likelihood estimates.
+//
+// One workgroup per subset, any size:
+//   - rho_S hat = 12 / (n (n^2 - 1)) sum (r1 - (n+1)/2)(r2 - (n+1)/2), the sum
+//     in exact 64-bit integers;
+//   - theta hat solves rho_S(theta) = rho_S hat: Gaussian in closed form
+//     (rho = 2 sin(pi rho_S / 6)); Frank rho_S = 1 - 12 (D1 - D2) / theta with
+//     Debye functions D_k; Gumbel, an extreme-value copula with Pickands
+//     function a(w) = (w^theta + (1 - w)^theta)^(1/theta), has
+//     int int C = int_0^1 (1 + a(w))^-2 dw, so rho_S = 12 int_0^1
+//     (1 + a(w))^-2 dw - 3. The integrals are taken by the workgroup (one
+//     Gauss-Legendre node per thread) inside a safeguarded Newton iteration;
+//   - the asymptotic variance by the plug-in sandwich of the moment
+//     equation J(u, v) = 12 (u - 1/2)(v - 1/2) = rho_S(theta):
+//     psi_i = J_i + W1(u_i) + W2(v_i) with W1(u_i) = (1/n) sum over
+//     u_l >= u_i of dJ/du (u_l, v_l) (a tie group takes the whole group),
+//     sigma^2 = var(psi) / (n rho_S'(theta)^2). dJ/du = 12 (v - 1/2) is a
+//     multiple of the integer r2 - (n+1)/2, so the suffix sums are exact
+//     64-bit integer sums over a histogram indexed by the doubled rank.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace cpc {
+
+namespace {
+
+constexpr int MT = 256;  // threads per workgroup = quadrature nodes per evaluation
+
+// 8-point Gauss-Legendre rule on [-1, 1]
+__constant__ double kMx[4] = {0.1834346424956498049, 0.5255324099163289858, 0.7966664774136267396,
+                              0.9602898564975362317};
+__constant__ double kMw[4] = {0.3626837833783619830, 0.3137066458778872873, 0.2223810344533744706,
+                              0.1012285362903762592};
+
+// Node `j` (0 .. MT-1) of 32 equal panels of [a, b] with 8 nodes each.
+__device__ __forceinline__ void quad_node(int j, double a, double b, double& x, double& w) {
+  const int panel = j >> 3, k = j & 7;
+  const int m = k < 4 ? 3 - k : k - 4;
+  const double xi = k < 4 ? -kMx[m] : kMx[m];
+  const double h = (b - a) / 32.0;
+  x = a + h * (panel + 0.5 * (xi + 1.0));
+  w = 0.5 * h * kMw[m];
+}
+
+// This thread's share of rho_S(theta) + 3 (Gumbel) or of the Debye
+// integrals (Frank), and of their theta-derivatives.
+template <int FAM>
+__device__ __forceinline__ void rho_terms(double th, double& f0, double& f1, double& f2, double& f3) {
+  f0 = f1 = f2 = f3 = 0.0;
+  if constexpr (FAM == FAM_GUMBEL) {
+    // 12 int_0^1 (1 + a)^-2 dw = 24 int_0^{1/2} (1 + a)^-2 dw (a(w) = a(1 - w))
+    double w, wt;
+    quad_node(threadIdx.x, 0.0, 0.5, w, wt);
+    const double lw = log(w), lv = log1p(-w);  // lw <= lv on (0, 1/2]
+    const double q = exp(th * (lw - lv));
+    const double l1q = log1p(q);
+    const double la = lv + l1q / th;  // log a
+    const double a = exp(la);
+    const double dla = -l1q / (th * th) + (q * (lw - lv)) / (th * (1.0 + q));  // d log a / d theta
+    const double ia = 1.0 / (1.0 + a);
+    f0 = 24.0 * wt * ia * ia;
+    f1 = -48.0 * wt * ia * ia * ia * a * dla;
+  } else if constexpr (FAM == FAM_FRANK) {
+    // int_0^A t^k / (e^t - 1) dt, k = 1, 2, over [0, min(A, 60)] (the rest is
+    // below e^-60 of it)
+    const double A = fabs(th);
+    double t, wt;
+    quad_node(threadIdx.x, 0.0, fmin(A, 60.0), t, wt);
+    const double g = t / expm1(t);
+    f2 = wt * g;
+    f3 = wt * g * t;
+  }
+}
+
+struct MomParams {
+  const uint32_t* R1;
+  const uint32_t* R2;
+  const SubDesc* subs;
+  int64_t n_min;
+  long long* H1;  // subset m (m = base + block) owns 2n + 2 entries from 2 (begin + m)
+  long long* H2;
+  int64_t base;   // index of the launch's first subset
+  ResultOut* out;
+};
+
+template <int FAM>
+__global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
+  constexpr int W = MT / WAVE;
+  __shared__ double red[W * 4];
+  __shared__ long long redl[W];
+  __shared__ unsigned int mm[4];
+  __shared__ double bc[4];  // broadcast: status, iterate, stop flag, slope
+  const int sid = blockIdx.x, t = threadIdx.x;
+  const SubDesc sd = P.subs[sid];
+  const int64_t n = sd.n, o = sd.begin;
+  ResultOut r;
+  r.theta = NAN; r.var = NAN; r.loglik = NAN; r.score = NAN;
+  r.n = n; r.iters = 0; r.status = ST_OK;
+  if (n < P.n_min || n < 2) {
+    if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; }
+    return;
+  }
+  const uint32_t* R1 = P.R1 + o;
+  const uint32_t* R2 = P.R2 + o;
+  const long long n1 = n + 1;
+
+  // rho_S hat (exact integer sum) and whether a margin has a single value
+  if (t == 0) { mm[0] = ~0u; mm[1] = 0u; mm[2] = ~0u; mm[3] = 0u; }
+  __syncthreads();
+  long long s = 0;
+  uint32_t a0 = ~0u, a1 = 0u, b0 = ~0u, b1 = 0u;
+  for (int64_t i = t; i < n; i += MT) {
+    const uint32_t x = R1[i], y = R2[i];
+    s += ((long long)x - n1) * ((long long)y - n1);
+    a0 = min(a0, x); a1 = max(a1, x); b0 = min(b0, y); b1 = max(b1, y);
+  }
+  atomicMin(&mm[0], a0); atomicMax(&mm[1], a1); atomicMin(&mm[2], b0); atomicMax(&mm[3], b1);
+  const long long S = block_sum_ll<W>(s, redl);
+  if (mm[0] == mm[1] || mm[2] == mm[3]) {  // uniform (after the barrier in block_sum_ll)
+    if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; }
+    return;
+  }
+  const double dn = (double)n;
+  double rho = 0.0;
+  if (t == 0) {
+    rho = 3.0 * (double)S / (dn * (dn * dn - 1.0));
+    bc[0] = rho;
+  }
+  __syncthreads();
+  rho = bc[0];
+
+  // theta with rho_S(theta) = rho
+  double th = 0.0, slope = 0.0, fit = 0.0;
+  int it = 0, status = ST_OK;
+  if constexpr (FAM == FAM_GAUSSIAN) {
+    th = 2.0 * sin(3.14159265358979323846 * rho / 6.0);
+    const double edge = 1.0 - 1e-9;
+    if (fabs(th) >= edge) { status = ST_BOUNDARY_BOX; th = th > 0.0 ? edge : -edge; }
+    slope = 3.0 / (3.14159265358979323846 * sqrt(1.0 - 0.25 * th * th));
+    fit = 6.0 / 3.14159265358979323846 * asin(0.5 * th);
+  } else {
+    // safeguarded Newton inside the family's box; the workgroup evaluates
+    // rho_S and its slope at each iterate, thread 0 takes the step and
+    // broadcasts it with the stopping decision (so every thread leaves the
+    // loop together)
+    constexpr double BLO = FAM == FAM_FRANK ? -200.0 : 1.0, BHI = FAM == FAM_FRANK ? 200.0 : 100.0;
+    double lo = BLO, hi = BHI;  // the bracket (thread 0's copy is the one used)
+    if (FAM == FAM_GUMBEL && rho <= 0.0) {
+      status = ST_BOUNDARY_NATURAL;
+      th = 1.0;
+    } else {
+      th = FAM == FAM_FRANK ? fmin(fmax(6.0 * rho / sqrt(fmax(1.0 - rho * rho, 1e-12)), -150.0), 150.0)
+                            : fmin(1.0 / (1.0 - 2.0 / 3.14159265358979323846 *
+                                                   asin(fmin(2.0 * sin(3.14159265358979323846 * rho / 6.0), 1.0))),
+                                   80.0);
+      if (!(th > BLO && th < BHI)) th = 0.5 * (BLO + BHI);
+      for (it = 1; it <= 100; ++it) {
+        double f0, f1, f2, f3;
+        rho_terms<FAM>(th, f0, f1, f2, f3);
+        double v[4] = {f0, f1, f2, f3};
+        block_sum<W, 4>(v, red);
+        if (t == 0) {
+          double val, der;
+          if constexpr (FAM == FAM_GUMBEL) {
+            val = v[0] - 3.0;
+            der = v[1];
+          } else {
+            const double A = fabs(th);
+            if (A < 1e-2) {
+              const double t2 = th * th;
+              val = th * (1.0 / 6.0 - t2 / 450.0 + t2 * t2 / 23520.0);
+              der = 1.0 / 6.0 - t2 / 150.0 + t2 * t2 / 4704.0;
+            } else {
+              const double D1 = v[2] / A, D2 = 2.0 * v[3] / (A * A);
+              const double e = 1.0 / expm1(A);
+              const double dD1 = -D1 / A + e, dD2 = -2.0 * D2 / A + 2.0 * e;
+              const double ra = 1.0 - 12.0 * (D1 - D2) / A;
+              val = th < 0.0 ? -ra : ra;
+              der = 12.0 * (D1 - D2) / (A * A) - 12.0 * (dD1 - dD2) / A;  // even in theta
+            }
+          }
+          const double g = val - rho;  // increasing in theta
+          int st = ST_OK;
+          double done = 0.0, tn = th;
+          if (g != 0.0) {  // (an exact root stops at th itself)
+            if (g < 0.0) lo = th; else hi = th;
+            tn = (der > 0.0) ? th - g / der : NAN;
+            if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+          }
+          if (g == 0.0 || fabs(tn - th) <= 1e-12 * (1.0 + fabs(th))) {
+            done = 1.0;
+          } else if (tn - BLO <= 1e-9 * (1.0 + fabs(BLO))) {
+            done = 1.0;
+            tn = BLO;
+            st = FAM == FAM_GUMBEL ? ST_BOUNDARY_NATURAL : ST_BOUNDARY_BOX;
+          } else if (BHI - tn <= 1e-9 * (1.0 + fabs(BHI))) {
+            done = 1.0;
+            tn = BHI;
+            st = ST_BOUNDARY_BOX;
+          }
+          bc[1] = tn;
+          bc[2] = done;
+          bc[3] = der;
+          bc[0] = (double)st;
+          fit = val;
+        }
+        __syncthreads();
+        th = bc[1];
+        const bool done = bc[2] != 0.0;
+        slope = bc[3];
+        status = (int)bc[0];
+        __syncthreads();  // bc is written again in the next iteration
+        if (done) break;
+      }
+      if (it > 100) status = ST_NOCONV;
+    }
+    if (status == ST_BOUNDARY_NATURAL) {  // the variance needs the slope at theta = 1
+      double f0, f1, f2, f3;
+      rho_terms<FAM>(1.0, f0, f1, f2, f3);
+      double v[4] = {f0, f1, f2, f3};
+      block_sum<W, 4>(v, red);
+      if (t == 0) {
+        bc[3] = v[1];
+        fit = v[0] - 3.0;
+      }
+      __syncthreads();
+      slope = bc[3];
+    }
+  }
+
+  // variance (OK and at the natural boundary)
+  double var = NAN;
+  if (status == ST_OK || status == ST_BOUNDARY_NATURAL) {
+    long long* H1 = P.H1 + 2 * (o + P.base + sid);
+    long long* H2 = P.H2 + 2 * (o + P.base + sid);
+    const int64_t NH = 2 * n + 2;  // doubled ranks 1 .. 2n+1
+    for (int64_t k = t; k < NH; k += MT) { H1[k] = 0; H2[k] = 0; }
+    __syncthreads();
+    for (int64_t i = t; i < n; i += MT) {
+      const uint32_t x = R1[i], y = R2[i];
+      atomicAdd((unsigned long long*)&H1[x], (unsigned long long)((long long)y - n1));
+      atomicAdd((unsigned long long*)&H2[y], (unsigned long long)((long long)x - n1));
+    }
+    __syncthreads();
+    // suffix sums over the doubled rank: thread t takes the block of
+    // consecutive entries [t*C, (t+1)*C), then adds the totals of the blocks
+    // above it
+    const int64_t C = (NH + MT - 1) / MT;
+    const int64_t k0 = t * C, k1 = min(k0 + C, NH);
+    long long t1 = 0, t2 = 0;
+    for (int64_t k = k1 - 1; k >= k0; --k) {
+      t1 += H1[k]; H1[k] = t1;
+      t2 += H2[k]; H2[k] = t2;
+    }
+    __shared__ long long tot[2][MT];
+    tot[0][t] = t1;
+    tot[1][t] = t2;
+    __syncthreads();
+    long long c1 = 0, c2 = 0;
+    for (int u = t + 1; u < MT; ++u) { c1 += tot[0][u]; c2 += tot[1][u]; }
+    for (int64_t k = k0; k < k1; ++k) { H1[k] += c1; H2[k] += c2; }
+    __syncthreads();
+    const double inv1 = 1.0 / (double)n1;
+    const double wsc = 6.0 / (dn * (double)n1);
+    KSum<double> sp, sq;
+    for (int64_t i = t; i < n; i += MT) {
+      const uint32_t x = R1[i], y = R2[i];
+      const double J = 3.0 * (double)((long long)x - n1) * (double)((long long)y - n1) * inv1 * inv1;
+      const double psi = J + wsc * ((double)H1[x] + (double)H2[y]);
+      sp.add(psi);
+      sq.add(psi * psi);
+    }
+    double v[2] = {sp.value(), sq.value()};
+    block_sum<W, 2>(v, red);
+    if (t == 0) {
+      const double m = v[0] / dn;
+      const double nu = v[1] / dn - m * m;
+      var = nu / (dn * slope * slope);
+    }
+  }
+  if (t == 0) {
+    r.theta = th;
+    r.var = var;
+    r.loglik = rho;
+    r.score = fit - rho;
+    r.iters = it;
+    r.status = status;
+    if ((status == ST_OK || status == ST_BOUNDARY_NATURAL) && !(var > 0.0 && isfinite(var))) r.status = ST_BADVAR;
+    P.out[sid] = r;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
+                           int64_t K, int64_t n_min, long long* H1, long long* H2, ResultOut* out, hipStream_t s) {
+  MomParams p;
+  p.R1 = R1; p.R2 = R2; p.subs = subs + base; p.n_min = n_min; p.H1 = H1; p.H2 = H2; p.base = base;
+  p.out = out + base;
+  if (K <= 0) return hipSuccess;
+  switch (fam) {
+    case FAM_GAUSSIAN: hipLaunchKernelGGL(k_spearman<FAM_GAUSSIAN>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+    case FAM_FRANK: hipLaunchKernelGGL(k_spearman<FAM_FRANK>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+    default: hipLaunchKernelGGL(k_spearman<FAM_GUMBEL>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cpc

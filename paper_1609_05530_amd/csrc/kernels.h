@@ -150,4 +150,23 @@ struct CombinedOut {  // identical layout to cpc_combined_t
 hipError_t launch_combine(const ResultOut* sub, const int64_t* group_offsets, int64_t G,
                           CombinedOut* comb, hipStream_t s);
 
+// Simulation inputs (Sec. 2.5): rows row0 .. row0 + n - 1 of the family's
+// copula with N(0, 1) margins, counter-based (k_sample.hip).
+hipError_t launch_sample(int fam, double theta, uint64_t seed, int64_t row0, int64_t n, int f32, void* x, void* y,
+                         hipStream_t s);
+
+// Evaluation metrics of Sec. 2.6 (k_study.hip): density distances of
+// eq. (19)-(20) for P parameter pairs (part: 4 * P * panels doubles), and
+// the replicate summary of eq. (17), (18), bias and MSE.
+hipError_t launch_density_distance(int fam, int64_t P, const double* theta_a, const double* theta_b, double L,
+                                   int panels, double* part, double* out, hipStream_t s);
+hipError_t launch_replicate_summary(int64_t S, const CombinedOut* comb, const CombinedOut* full, double* out,
+                                    hipStream_t s);
+
+// Spearman-inversion estimates per subset from doubled ranks (k_moment.hip);
+// H1, H2: 2 (n + K) int64 each.
+// subsets base .. base + K - 1 of `subs`, results to out[base ..].
+hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
+                           int64_t K, int64_t n_min, long long* H1, long long* H2, ResultOut* out, hipStream_t s);
+
 }  // namespace cpc
