@@ -117,6 +117,49 @@ def test_ranks_bit_exact(dtype, ties):
         assert np.array_equal(R2[a:b], O.ranks(y[a:b], ties)), (m, RANK_SIZES[m])
 
 
+@pytest.mark.parametrize("ties", ["average", "first"])
+def test_ranks_bit_exact_margin_shapes(ties):
+    """FP32 margins of many shapes on subsets of 2049..16384 rows (the radix
+    passes whose digits vary differ with the data): normal, lognormal
+    (sigma 3), Cauchy, uniform, values near 1e-30, a normal with a few
+    outliers at 1e30, sign-symmetric values with exact zeros, a margin of
+    two values and a heavily tied one; the second margin is a permutation
+    of the first."""
+    rng = np.random.default_rng(41)
+    sizes = [2049, 3000, 5000, 8192, 8193, 12000, 16384, 16000, 9000, 4100]
+    xs, ys = [], []
+    for i, m in enumerate(sizes):
+        kind = i % 8
+        g = rng.standard_normal(m)
+        if kind == 1:
+            v = np.exp(3.0 * g)
+        elif kind == 2:
+            v = rng.standard_cauchy(m)
+        elif kind == 3:
+            v = rng.uniform(size=m)
+        elif kind == 4:
+            v = 1e-30 * g
+        elif kind == 5:
+            v = g.copy(); v[:5] = 1e30 * np.sign(g[:5])
+        elif kind == 6:
+            v = np.round(g * 1e3) / 1e3; v[::97] = 0.0; v[1::97] = -0.0
+        elif kind == 7:
+            v = np.where(g > 0, 1.0, 2.0) if i == 7 else np.round(g * 2) / 2
+        else:
+            v = g
+        xs.append(v)
+        ys.append(rng.permutation(v))
+    x = np.concatenate(xs).astype(np.float32).astype(np.float64)
+    y = np.concatenate(ys).astype(np.float32).astype(np.float64)
+    off = synth.offsets_from_sizes(np.array(sizes))
+    R1, R2 = cpc().rank(dev(x, torch.float32), dev(y, torch.float32), off, ties=ties)
+    R1 = R1.cpu().numpy().astype(np.int64); R2 = R2.cpu().numpy().astype(np.int64)
+    for m in range(len(sizes)):
+        a, b = off[m], off[m + 1]
+        assert np.array_equal(R1[a:b], O.ranks(x[a:b], ties)), (m, sizes[m])
+        assert np.array_equal(R2[a:b], O.ranks(y[a:b], ties)), (m, sizes[m])
+
+
 def test_ranks_permutation_invariant_average():
     rng = np.random.default_rng(5)
     x = np.round(rng.standard_normal(5000) * 8) / 8
