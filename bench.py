@@ -47,6 +47,10 @@ RANK_BYTES_PER_ROW = 4 + 4 + 2 + 2
 # the rank kernel's sources (body, launch shapes and shape tables)
 RANK_SOURCES = ["paper_1609_05530_amd/csrc/rank_wg.h", "paper_1609_05530_amd/csrc/block_rank.h",
                 "paper_1609_05530_amd/csrc/k_rank.hip", "paper_1609_05530_amd/csrc/rank_shapes.h"]
+# the fit and variance kernels' sources (bodies and the device math they use)
+FIT_VAR_SOURCES = ["paper_1609_05530_amd/csrc/k_fit.hip", "paper_1609_05530_amd/csrc/k_var.hip",
+                   "paper_1609_05530_amd/csrc/family_math.h", "paper_1609_05530_amd/csrc/row_eval.h",
+                   "paper_1609_05530_amd/csrc/solver.h", "paper_1609_05530_amd/csrc/cpc_device.h"]
 
 
 def parse():
@@ -65,17 +69,23 @@ def parse():
     ap.add_argument("--profile", action="store_true", help="short run for a profiler (no oracle, no checks)")
     ap.add_argument("--no-small-configs", action="store_true",
                     help="skip the GPU times of the n=1e4 and n=1e6 FP64 workloads")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the n=1e8, replicate-batch and Gumbel legs")
     ap.add_argument("--oracle-1thread", action="store_true",
                     help="also time the oracle on one thread on the n=1e4 and n=1e6 workloads (minutes)")
     return ap.parse_args()
 
 
-def rank_source_hash() -> str:
+def source_hash(paths) -> str:
     h = hashlib.sha256()
-    for p in RANK_SOURCES:
+    for p in paths:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def rank_source_hash() -> str:
+    return source_hash(RANK_SOURCES)
 
 
 def valu_probe():
@@ -178,6 +188,177 @@ def measured_rank_traffic():
         if m_hash and m_bytes and m_hash.group(1) == rank_source_hash():
             return float(m_bytes.group(1))
     return None
+
+
+def measured_fit_var_counters():
+    """VALU instruction counts per step of the fit and variance kernels from
+    the committed rocprofv3 PMC summary of the default workload, if it was
+    taken on the current sources (else None)."""
+    keys = ("valu", "trans_f32", "trans_f64", "f64")
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*fit_var*valu*.md")):
+        with open(path) as f:
+            text = f.read()
+        m_hash = re.search(r"fit_var_source_sha256_16:\s*([0-9a-f]+)", text)
+        if not m_hash or m_hash.group(1) != source_hash(FIT_VAR_SOURCES):
+            continue
+        out = {}
+        for ph in ("fit", "var"):
+            for k in keys:
+                m = re.search(rf"{ph}_{k}_insts_per_step:\s*([0-9.eE+]+)", text)
+                if not m:
+                    break
+                out[(ph, k)] = float(m.group(1))
+        if len(out) == 2 * len(keys):
+            return out
+    return None
+
+
+def issued_slots(c, phase, trans_slots):
+    """Issued VALU lane-slots of one phase: 64 per wave instruction, an FP32
+    transcendental weighted by its measured slot cost, FP64 FMA/MUL/ADD 2
+    (half-rate), FP64 transcendentals 8."""
+    v, t, t64, f64 = (c[(phase, k)] for k in ("valu", "trans_f32", "trans_f64", "f64"))
+    return 64.0 * ((v - t - t64 - f64) + trans_slots * t + 2.0 * f64 + 8.0 * t64)
+
+
+# FP32-compensated parity tolerances the GPU tests hold every estimate to
+# (relative to max(|theta|, floor)); FP64 path: 1e-6 relative (floor 1e-3).
+TOLERANCES = {
+    "fp32c": {"frank": {"rel": 1e-5, "floor": 0.1}, "gumbel": {"rel": 1e-5, "floor": 0.1},
+              "gaussian": {"rel": 1e-6, "floor": 1e-2}},
+    "fp64": {"all": {"rel": 1e-6, "floor": 1e-3}},
+}
+
+
+def _fit_timed(cpc, x, y, offsets, gofs, fams, prec, reps, dev, torch):
+    """Median ms of `reps` graph replays of one batched fit (inputs resident)."""
+    K, G = len(offsets) - 1, len(gofs) - 1
+    ws = torch.empty(cpc.workspace_bytes(x.shape[0], K, G, dtype=x.dtype, offsets=offsets, prec=prec),
+                     dtype=torch.uint8, device=dev)
+    out = cpc.FitResult(torch.empty((K, 6), dtype=torch.float64, device=dev),
+                        torch.empty((G, 5), dtype=torch.float64, device=dev))
+
+    def step():
+        cpc.fit_batched(x, y, offsets, gofs, fams, workspace=ws, out=out, prec=prec, graph=True)
+    step()
+    step()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record()
+    for i in range(reps):
+        step()
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    ms = float(np.median([evs[i].elapsed_time(evs[i + 1]) for i in range(reps)]))
+    del ws
+    return ms, out
+
+
+def _oracle_err(O, xs, ys, offsets, picks, fam_of, theta_gpu, status_gpu):
+    """Max relative error of the GPU estimates on the picked subsets against
+    the oracle run on the same rows (FP32 values widened)."""
+    sub_x = [xs[offsets[m]:offsets[m + 1]].astype(np.float64) for m in picks]
+    sub_y = [ys[offsets[m]:offsets[m + 1]].astype(np.float64) for m in picks]
+    import synth
+    off = synth.offsets_from_sizes(np.array([len(v) for v in sub_x]))
+    gofs = np.arange(len(picks) + 1, dtype=np.int64)
+    sub, _ = O.fit(np.concatenate(sub_x), np.concatenate(sub_y), off, [fam_of[m] for m in picks], gofs)
+    ok = (sub["status"] == 0) & (status_gpu[picks] == 0)
+    floor = np.array([0.1 if fam_of[m] == "frank" else (1e-2 if fam_of[m] == "gaussian" else 0.1) for m in picks])
+    rel = np.abs(theta_gpu[picks][ok] - sub["theta"][ok]) / np.maximum(np.abs(sub["theta"][ok]), floor[ok])
+    return {"subsets_checked": int(ok.sum()), "theta_max_rel": float(rel.max(initial=0.0)),
+            "status_match": bool(np.array_equal(sub["status"], status_gpu[picks]))}
+
+
+def leg_gumbel_c5_shape(cpc, synth, O, dev, torch):
+    """Gumbel theta = 2 at the shape of the headline workload: n = 1e7 FP32
+    pairs (drawn on the GPU), K = 1000 subsets of U[5000, 15000] rows."""
+    n, K = 10_000_000, 1000
+    t0 = time.perf_counter()
+    x, y = cpc.sample("gumbel", 2.0, n, seed=7002, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    gen = time.perf_counter() - t0
+    off = synth.uniform_size_offsets(n, K, 5000.0, 15000.0, np.random.default_rng(7003))
+    gofs = np.array([0, K], dtype=np.int64)
+    ms, out = _fit_timed(cpc, x, y, off, gofs, ["gumbel"], "fp32c", 10, dev, torch)
+    ms64, out64 = _fit_timed(cpc, x, y, off, gofs, ["gumbel"], "fp64", 5, dev, torch)
+    th, st = out.theta.cpu().numpy(), out.status.cpu().numpy()
+    picks = list(range(0, K, K // 32))
+    err = _oracle_err(O, x.cpu().numpy(), y.cpu().numpy(), off, picks, ["gumbel"] * K, th, st)
+    return {"workload": "gumbel theta=2, n=1e7 FP32 (GPU sampler), K=1000 U[5000,15000]",
+            "ms_per_fit": ms, "subset_fits_per_s": K / (ms / 1e3), "fp64_ms": ms64,
+            "speedup_fp32c_over_fp64": ms64 / ms, "gen_s": gen, "err_vs_oracle": err,
+            "newton_passes_mean": float(np.mean(out.iters.cpu().numpy()[st == 0]))}
+
+
+def leg_config3(cpc, synth, O, dev, torch):
+    """1000 replicates x 1e5 pairs, family r mod 3 with Kendall tau ~
+    U[0.1, 0.8], K = 50 Dirichlet(1) subsets each (about 50,000 fits, one
+    graph replay); replicates drawn on the GPU sampler."""
+    R, n, K = 1000, 100_000, 50
+    fams = ["gaussian", "frank", "gumbel"]
+    x = torch.empty(R * n, dtype=torch.float32, device=dev)
+    y = torch.empty(R * n, dtype=torch.float32, device=dev)
+    offs, gofs, fam_g = [0], [0], []
+    t0 = time.perf_counter()
+    for r in range(R):
+        rng = np.random.default_rng(3000 + r)
+        fam = fams[r % 3]
+        th = synth.theta_from_tau(fam, rng.uniform(0.1, 0.8))
+        xr, yr = cpc.sample(fam, th, n, seed=9_000_000 + r, dtype=torch.float32, device=dev)
+        x[r * n:(r + 1) * n] = xr
+        y[r * n:(r + 1) * n] = yr
+        o = synth.dirichlet_offsets(n, K, rng)
+        offs.extend((o[1:] + r * n).tolist())
+        gofs.append(gofs[-1] + K)
+        fam_g.append(fam)
+    torch.cuda.synchronize()
+    gen = time.perf_counter() - t0
+    offs = np.array(offs, dtype=np.int64)
+    gofs = np.array(gofs, dtype=np.int64)
+    ms, out = _fit_timed(cpc, x, y, offs, gofs, fam_g, "fp32c", 10, dev, torch)
+    th, st = out.theta.cpu().numpy(), out.status.cpu().numpy()
+    fam_of = [fam_g[m // K] for m in range(R * K)]
+    sizes = np.diff(offs)
+    picks = sorted(set([int(np.argmax(sizes))] + list(range(7, R * K, (R * K) // 30))))
+    err = _oracle_err(O, x.cpu().numpy(), y.cpu().numpy(), offs, picks, fam_of, th, st)
+    return {"workload": "1000 replicates x n=1e5 FP32 (GPU sampler), K=50 Dirichlet(1), family r mod 3",
+            "subsets": R * K, "ms_per_fit": ms, "subset_fits_per_s": R * K / (ms / 1e3), "gen_s": gen,
+            "status_counts": {str(int(s)): int(np.sum(st == s)) for s in np.unique(st)}, "err_vs_oracle": err}
+
+
+def leg_config4(cpc, synth, O, dev, torch):
+    """n = 1e8 FP32 pairs per family (Gumbel theta = 3, Frank theta = -8) drawn
+    on the GPU, K = 1000 equal subsets: FP32c and FP64 times and errors."""
+    n, K = 100_000_000, 1000
+    res = []
+    for fam, th in synth.CONFIG4:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, y = cpc.sample(fam, th, n, seed=4000 + synth.FAMILY_CODES[fam], dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        gen = time.perf_counter() - t0
+        off = synth.equal_offsets(n, K)
+        gofs = np.array([0, K], dtype=np.int64)
+        ms, out = _fit_timed(cpc, x, y, off, gofs, [fam], "fp32c", 3, dev, torch)
+        th32, st = out.theta.cpu().numpy(), out.status.cpu().numpy()
+        c32 = float(out.combined_theta.cpu().numpy()[0])
+        ms64, out64 = _fit_timed(cpc, x, y, off, gofs, [fam], "fp64", 3, dev, torch)
+        th64 = out64.theta.cpu().numpy()
+        c64 = float(out64.combined_theta.cpu().numpy()[0])
+        picks = list(range(0, K, K // 8))
+        xs, ys = x.cpu().numpy(), y.cpu().numpy()
+        err32 = _oracle_err(O, xs, ys, off, picks, [fam] * K, th32, st)
+        err64 = _oracle_err(O, xs, ys, off, picks, [fam] * K, th64, out64.status.cpu().numpy())
+        res.append({"workload": f"{fam} theta={th:g}, n=1e8 FP32 (GPU sampler), K=1000 x 1e5",
+                    "fp32c_ms": ms, "fp64_ms": ms64, "speedup_fp32c_over_fp64": ms64 / ms,
+                    "rows_per_s_fp32c": n / (ms / 1e3), "sampler_s": gen, "sampler_rows_per_s": n / gen,
+                    "combined_fp32c": c32, "combined_fp64": c64,
+                    "combined_rel_fp32c_vs_fp64": abs(c32 - c64) / abs(c64),
+                    "err_vs_oracle_fp32c": err32, "err_vs_oracle_fp64": err64})
+        del x, y, out, out64
+        torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -317,7 +498,26 @@ def main():
     }
 
     if not a.profile:
-        line["valu_probe"] = valu_probe()
+        probe = valu_probe()
+        line["valu_probe"] = probe
+        counters = measured_fit_var_counters() if (a.prec == "fp32c" and graph and a.n == 10_000_000
+                                                    and a.K == 1000 and a.settings == "all") else None
+        if counters is not None:
+            # issued VALU slots per step from the committed counter profile of
+            # this workload, over the fit and variance phase times just measured
+            w_trans = probe["slots_per_op"]["exp2"] if probe else 3.2
+            for ph, key, ms in (("fit", "roofline_fit", phases[1]), ("var", "roofline_var", phases[2])):
+                sl = issued_slots(counters, ph, w_trans)
+                rate = sl / (ms / 1e3) if ms > 0 else 0.0
+                issued = {"lane_slots_per_step": sl, "achieved": rate / 1e12, "peak": PEAK_LANE_SLOTS / 1e12,
+                          "unit": "T VALU lane-slots/s", "frac": rate / PEAK_LANE_SLOTS,
+                          "valu_wave_insts_per_step": counters[(ph, "valu")],
+                          "trans_f32_lane_ops_per_s": 64.0 * counters[(ph, "trans_f32")] / (ms / 1e3) if ms > 0 else 0.0,
+                          "source": "rocprofv3 PMC counts of the committed profile x measured phase time"}
+                if key == "roofline_fit":
+                    line[key]["issued"] = issued
+                else:
+                    line[key] = {"kernel": "k_var_wg (GGR variance, Sec. 2.3)", "bound": "alu", **issued}
     if not a.profile and not a.no_small_configs:
         line["small_configs_fp64"] = small_configs(cpc, synth, dev, a.oracle_1thread)
 
@@ -365,6 +565,20 @@ def main():
         if theta64 is not None:
             rel64 = rel_err(theta64)
             line["fp64_path"]["theta_max_rel_vs_oracle"] = float(rel64.max(initial=0))
+        # the combination (eq. 15) of the sampled subsets per setting, GPU vs oracle
+        xs_d = torch.from_numpy(np.concatenate(xs).astype(np.float32)).to(dev)
+        ys_d = torch.from_numpy(np.concatenate(ys).astype(np.float32)).to(dev)
+        samp = cpc.fit_batched(xs_d, ys_d, off, gofs, fams, prec=a.prec)
+        _, comb_o = O.fit(np.concatenate(xs), np.concatenate(ys), off, fams, gofs, nthreads=nt)
+        cg = samp.combined_theta.cpu().numpy()
+        cfl = np.array([0.1 if f == "frank" else 1e-2 for f in fams])
+        line["err_vs_oracle"]["combined_max_rel"] = float(np.max(np.abs(cg - comb_o["theta"]) /
+                                                                 np.maximum(np.abs(comb_o["theta"]), cfl)))
+        line["err_vs_oracle"]["tolerance"] = TOLERANCES[a.prec]
+        w1 = synth.config1(1)
+        t1 = time.perf_counter()
+        O.fit(w1.x, w1.y, w1.offsets, w1.families, w1.group_offsets, nthreads=1)
+        line["oracle_1thread_s_config1_K1"] = time.perf_counter() - t1
         line["cpu_baseline"] = {
             "value": len(pick) / cpu_s,
             "unit": "subset-fits/s",
@@ -374,6 +588,13 @@ def main():
             "sample": f"{len(pick)} subsets ({a.cpu_sample} per setting, {int(sizes.sum())} rows), FP64 oracle, "
                       f"OpenMP over subsets, {cpu_s:.1f} s",
         }
+    if not a.profile and not a.no_legs:
+        import oracle.oracle as O
+        for name, fn in (("gumbel_c5_shape", leg_gumbel_c5_shape), ("config3", leg_config3),
+                         ("config4", leg_config4)):
+            t0 = time.perf_counter()
+            line[name] = fn(cpc, synth, O, dev, torch)
+            print(f"[leg] {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
