@@ -52,7 +52,8 @@ struct RankLds {
   __device__ static __forceinline__ int vx(int p) { return PAD ? p + (p / E) * VPAD : p; }
   static constexpr int SMALL = 3 * W + W * KW + 8;  // red, wmax, wmin, wl, andor (+ non-finite flag)
   static constexpr int MAIN = ALIAS ? (CNT > XW ? CNT : XW) + SMALL : CNT + XW;
-  static_assert(ALIAS || CNT >= 2 * W + W * KW, "tie-phase arrays fit in the counters");
+  // tie phase (not aliased): wmax, wmin, wl and the per-wave tie flags in the counters
+  static_assert(ALIAS || CNT >= 3 * W + W * KW, "tie-phase arrays fit in the counters");
   alignas(16) uint32_t main[MAIN];  // 16-byte vector reads of keys, payloads, counters
   __device__ __forceinline__ uint32_t* cnt() { return main; }
   __device__ __forceinline__ uint32_t* xk() { return ALIAS ? main : main + CNT; }
