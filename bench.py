@@ -129,8 +129,8 @@ def small_configs(cpc, synth, dev, oracle_1thread):
     oracle's one-thread wall time (host arrays to results) on each, all of
     them run side by side on host threads, and the GPU's error against it."""
     import torch
-    cases = [synth.config1(K) for K in (1, 10)]
-    cases += [synth.config2(f, K) for f in ("gaussian", "frank", "gumbel") for K in (1, 10, 100)]
+    cases = [synth.gaussian_1e4(K) for K in (1, 10)]
+    cases += [synth.one_million_rows(f, K) for f in ("gaussian", "frank", "gumbel") for K in (1, 10, 100)]
     rows = []
     for w in cases:
         x = torch.from_numpy(w.x).to(dev)
@@ -270,7 +270,7 @@ def _oracle_err(O, xs, ys, offsets, picks, fam_of, theta_gpu, status_gpu):
             "status_match": bool(np.array_equal(sub["status"], status_gpu[picks]))}
 
 
-def leg_gumbel_c5_shape(cpc, synth, O, dev, torch):
+def leg_gumbel_headline_shape(cpc, synth, O, dev, torch):
     """Gumbel theta = 2 at the shape of the headline workload: n = 1e7 FP32
     pairs (drawn on the GPU), K = 1000 subsets of U[5000, 15000] rows."""
     n, K = 10_000_000, 1000
@@ -291,7 +291,7 @@ def leg_gumbel_c5_shape(cpc, synth, O, dev, torch):
             "newton_passes_mean": float(np.mean(out.iters.cpu().numpy()[st == 0]))}
 
 
-def leg_config3(cpc, synth, O, dev, torch):
+def leg_replicate_batch(cpc, synth, O, dev, torch):
     """1000 replicates x 1e5 pairs, family r mod 3 with Kendall tau ~
     U[0.1, 0.8], K = 50 Dirichlet(1) subsets each (about 50,000 fits, one
     graph replay); replicates drawn on the GPU sampler."""
@@ -327,12 +327,12 @@ def leg_config3(cpc, synth, O, dev, torch):
             "status_counts": {str(int(s)): int(np.sum(st == s)) for s in np.unique(st)}, "err_vs_oracle": err}
 
 
-def leg_config4(cpc, synth, O, dev, torch):
+def leg_hundred_million_rows(cpc, synth, O, dev, torch):
     """n = 1e8 FP32 pairs per family (Gumbel theta = 3, Frank theta = -8) drawn
     on the GPU, K = 1000 equal subsets: FP32c and FP64 times and errors."""
     n, K = 100_000_000, 1000
     res = []
-    for fam, th in synth.CONFIG4:
+    for fam, th in synth.HUNDRED_MILLION_SETTINGS:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         x, y = cpc.sample(fam, th, n, seed=4000 + synth.FAMILY_CODES[fam], dtype=torch.float32, device=dev)
@@ -372,9 +372,9 @@ def main():
     import paper_1609_05530_amd as cpc
     import synth
 
-    settings = synth.CONFIG5 if a.settings == "all" else [synth.CONFIG5[int(i)] for i in a.settings.split(",")]
+    settings = synth.NINE_SETTINGS if a.settings == "all" else [synth.NINE_SETTINGS[int(i)] for i in a.settings.split(",")]
     t0 = time.time()
-    w = synth.config5(settings=settings, n=a.n, K=a.K)
+    w = synth.nine_settings(settings=settings, n=a.n, K=a.K)
     gen_s = time.time() - t0
     dev = torch.device("cuda:0")
     x = torch.from_numpy(w.x).to(dev)
@@ -575,10 +575,10 @@ def main():
         line["err_vs_oracle"]["combined_max_rel"] = float(np.max(np.abs(cg - comb_o["theta"]) /
                                                                  np.maximum(np.abs(comb_o["theta"]), cfl)))
         line["err_vs_oracle"]["tolerance"] = TOLERANCES[a.prec]
-        w1 = synth.config1(1)
+        w1 = synth.gaussian_1e4(1)
         t1 = time.perf_counter()
         O.fit(w1.x, w1.y, w1.offsets, w1.families, w1.group_offsets, nthreads=1)
-        line["oracle_1thread_s_config1_K1"] = time.perf_counter() - t1
+        line["oracle_1thread_s_gaussian_1e4_K1"] = time.perf_counter() - t1
         line["cpu_baseline"] = {
             "value": len(pick) / cpu_s,
             "unit": "subset-fits/s",
@@ -590,8 +590,8 @@ def main():
         }
     if not a.profile and not a.no_legs:
         import oracle.oracle as O
-        for name, fn in (("gumbel_c5_shape", leg_gumbel_c5_shape), ("config3", leg_config3),
-                         ("config4", leg_config4)):
+        for name, fn in (("gumbel_theta2_1e7_k1000", leg_gumbel_headline_shape), ("replicate_batch_1000x1e5", leg_replicate_batch),
+                         ("rows_1e8", leg_hundred_million_rows)):
             t0 = time.perf_counter()
             line[name] = fn(cpc, synth, O, dev, torch)
             print(f"[leg] {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

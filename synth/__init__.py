@@ -205,7 +205,7 @@ def _concat(name, parts, dtype):
                     np.array(gofs, dtype=np.int64), fams, ths, seeds)
 
 
-def config1(K: int) -> Workload:
+def gaussian_1e4(K: int) -> Workload:
     """n = 10,000 Gaussian pairs, rho = 0.5, seed 0, K in {1, 10}, FP64."""
     g = np.random.default_rng(0).standard_normal((2, 10_000))
     x = g[0]
@@ -214,19 +214,19 @@ def config1(K: int) -> Workload:
                    np.float64)
 
 
-CONFIG2_THETA = {"gaussian": 0.7, "frank": 5.0, "gumbel": 2.0}
+MILLION_ROW_THETA = {"gaussian": 0.7, "frank": 5.0, "gumbel": 2.0}
 
 
-def config2(family: str, K: int, n: int = 1_000_000) -> Workload:
+def one_million_rows(family: str, K: int, n: int = 1_000_000) -> Workload:
     """n = 1e6 pairs of one family (Gaussian 0.7, Frank 5, Gumbel 2), K equal subsets, FP64."""
     seed = 2000 + FAMILY_CODES[family]
-    th = CONFIG2_THETA[family]
+    th = MILLION_ROW_THETA[family]
     x, y = copula_pairs(family, th, n, seed)
     return _concat(f"{family} theta={th} n={n} K={K} fp64", [(x, y, equal_offsets(n, K), family, th, seed)],
                    np.float64)
 
 
-def config3(replicates: int = 1000, n: int = 100_000, K: int = 50, seed0: int = 3000) -> Workload:
+def replicate_batch(replicates: int = 1000, n: int = 100_000, K: int = 50, seed0: int = 3000) -> Workload:
     """Replicates of n pairs, family = r mod 3, Kendall tau ~ U[0.1, 0.8],
     K Dirichlet(1) subsets per replicate; FP32 storage. Replicates are drawn
     on a thread pool; each has its own seeds, so the result does not depend on
@@ -247,10 +247,10 @@ def config3(replicates: int = 1000, n: int = 100_000, K: int = 50, seed0: int = 
     return _concat(f"{replicates} replicates x n={n}, K={K} Dirichlet(1) fp32", parts, np.float32)
 
 
-CONFIG4 = [("gumbel", 3.0), ("frank", -8.0)]
+HUNDRED_MILLION_SETTINGS = [("gumbel", 3.0), ("frank", -8.0)]
 
 
-def config4(family: str, theta: float, n: int = 100_000_000, K: int = 1000) -> Workload:
+def hundred_million_rows(family: str, theta: float, n: int = 100_000_000, K: int = 1000) -> Workload:
     """One family at n pairs in FP32 storage, K equal subsets."""
     seed = 4000 + FAMILY_CODES[family]
     x, y = _chunked_pairs(family, theta, n, seed, np.float32)
@@ -258,11 +258,11 @@ def config4(family: str, theta: float, n: int = 100_000_000, K: int = 1000) -> W
                    np.float32)
 
 
-CONFIG5 = [("frank", -10.0), ("frank", -1.0), ("frank", 0.01), ("frank", 1.0), ("frank", 10.0),
+NINE_SETTINGS = [("frank", -10.0), ("frank", -1.0), ("frank", 0.01), ("frank", 1.0), ("frank", 10.0),
            ("frank", 30.0), ("gaussian", -0.95), ("gaussian", 0.0), ("gaussian", 0.95)]
 
 
-def config5(settings: Sequence = CONFIG5, n: int = 10_000_000, K: int = 1000, lo: float = 5000.0,
+def nine_settings(settings: Sequence = NINE_SETTINGS, n: int = 10_000_000, K: int = 1000, lo: float = 5000.0,
             hi: float = 15000.0) -> Workload:
     """Each setting: n pairs in FP32, K subsets with sizes ~ U[lo, hi] renormalised to n."""
     parts = []

@@ -211,7 +211,7 @@ def test_fit_parity(fam, th, prec, storage):
 
 @pytest.mark.parametrize("K", [1, 10])
 def test_gaussian_rho05_n1e4_seed0(K):
-    w = synth.config1(K)
+    w = synth.gaussian_1e4(K)
     sub, comb = O.fit(w.x, w.y, w.offsets, "gaussian")
     res = to_np(cpc().fit(dev(w.x, torch.float64), dev(w.y, torch.float64), w.offsets, "gaussian", prec="fp64"))
     compare(res, sub, comb, "fp64", "gaussian", f"gaussian rho=0.5 n=1e4 K={K}")
@@ -342,7 +342,7 @@ def test_autograd_loglik_and_score():
 
 
 def test_bitwise_deterministic():
-    w = synth.config5(settings=[("frank", 10.0), ("gaussian", 0.5)], n=200_000, K=20, lo=5000, hi=15000)
+    w = synth.nine_settings(settings=[("frank", 10.0), ("gaussian", 0.5)], n=200_000, K=20, lo=5000, hi=15000)
     fams = w.families
     a = to_np(cpc().fit_batched(dev(w.x, torch.float32), dev(w.y, torch.float32), w.offsets, w.group_offsets,
                                 fams, prec="fp32c"))
@@ -457,11 +457,11 @@ def test_big_statuses():
 
 
 @pytest.mark.parametrize("fam", ["gaussian", "frank", "gumbel"])
-def test_config2_full_size(fam):
+def test_one_million_rows_full_size(fam):
     """n = 1e6 per family, FP64, K in {1, 10, 100}: ranks of sampled rows by
     brute force, the estimate as the root of the oracle's score, and oracle
     parity on sampled subsets."""
-    w1 = synth.config2(fam, 1)
+    w1 = synth.one_million_rows(fam, 1)
     x, y = w1.x, w1.y
     n = x.shape[0]
     rng = np.random.default_rng(9)
@@ -484,7 +484,7 @@ def test_config2_full_size(fam):
         assert d[:, 2].sum() < 0
         step = abs(d[:, 1].sum() / d[:, 2].sum())
         assert step <= 1e-6 * max(abs(res["theta"][m]), 1e-3), (fam, K, step)
-        print(f"[config2] {fam} K={K}: theta[0]={res['theta'][0]:.10f} newton residual step {step:.2e} "
+        print(f"[1e6 rows] {fam} K={K}: theta[0]={res['theta'][0]:.10f} newton residual step {step:.2e} "
               f"combined {res['combined_theta'][0]:.10f}", flush=True)
         if K == 100:
             pick = [0, 57]
@@ -701,12 +701,12 @@ def test_autotuned_shapes_give_identical_results(tmp_path, monkeypatch):
 
 def test_fp32c_matches_fp64_on_every_subset():
     m = cpc()
-    w = synth.config5(n=1_000_000, K=100)
+    w = synth.nine_settings(n=1_000_000, K=100)
     x, y = dev(w.x, torch.float32), dev(w.y, torch.float32)
     a = to_np(m.fit_batched(x, y, w.offsets, w.group_offsets, w.families, prec="fp32c"))
     b = to_np(m.fit_batched(x, y, w.offsets, w.group_offsets, w.families, prec="fp64"))
     assert np.array_equal(a["status"], b["status"])
-    for g, (fam, th) in enumerate(synth.CONFIG5):
+    for g, (fam, th) in enumerate(synth.NINE_SETTINGS):
         s = slice(int(w.group_offsets[g]), int(w.group_offsets[g + 1]))
         rt, floor = theta_tol("fp32c", fam)
         rel = np.abs(a["theta"][s] - b["theta"][s]) / np.maximum(np.abs(b["theta"][s]), floor)
@@ -747,7 +747,7 @@ def test_adjoint_drives_newton_on_benchmark_settings(fam, th):
     driven only by the autograd derivatives reaches the FP64 batched fit's
     estimate."""
     import paper_1609_05530_amd as m
-    w = synth.config5(settings=[(fam, th)], n=30000, K=3)
+    w = synth.nine_settings(settings=[(fam, th)], n=30000, K=3)
     off = w.offsets
     R1, R2 = m.rank(dev(w.x, torch.float32), dev(w.y, torch.float32), off)
     r1 = R1.cpu().numpy().astype(np.int64)

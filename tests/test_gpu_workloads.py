@@ -92,9 +92,9 @@ def family_of_subsets(w):
     return fam_of
 
 
-def test_config5_full_size_bench_launch():
+def test_nine_settings_full_size_bench_launch():
     m = cpc()
-    w = synth.config5()
+    w = synth.nine_settings()
     x, y = dev(w.x, torch.float32), dev(w.y, torch.float32)
     ws = torch.empty(m.workspace_bytes(w.n, w.K, w.G, dtype=torch.float32, prec="fp32c"), dtype=torch.uint8,
                      device="cuda")
@@ -115,14 +115,14 @@ def test_config5_full_size_bench_launch():
     for gi in range(w.G):
         a, b = int(w.group_offsets[gi]), int(w.group_offsets[gi + 1])
         pick += [a, (a + b) // 2, b - 1]
-    check_against_oracle(g, w, pick, fam_of, "fp32c", "config5")
+    check_against_oracle(g, w, pick, fam_of, "fp32c", "nine_settings")
 
 
-@pytest.mark.parametrize("fam,th", synth.CONFIG4)
-def test_config4_full_size(fam, th):
+@pytest.mark.parametrize("fam,th", synth.HUNDRED_MILLION_SETTINGS)
+def test_hundred_million_rows_full_size(fam, th):
     m = cpc()
     t0 = time.time()
-    w = synth.config4(fam, th)
+    w = synth.hundred_million_rows(fam, th)
     gen = time.time() - t0
     x, y = dev(w.x, torch.float32), dev(w.y, torch.float32)
     fam_of = family_of_subsets(w)
@@ -143,20 +143,20 @@ def test_config4_full_size(fam, th):
         tc, nu = combine_closed_form(g, w.group_offsets)
         assert np.allclose(g["combined_theta"], tc, rtol=1e-12, atol=0)
         assert nu[0] == w.K
-        check_against_oracle(g, w, pick, fam_of, prec, f"config4 {fam} {prec}")
+        check_against_oracle(g, w, pick, fam_of, prec, f"hundred_million_rows {fam} {prec}")
         se = float(np.sqrt(g["combined_var"][0]))
         assert abs(g["combined_theta"][0] - th) <= 6 * se, (prec, g["combined_theta"][0], th, se)
-        print(f"[config4] {fam} theta={th} {prec}: combined {g['combined_theta'][0]:.6f} (se {se:.2e}), "
+        print(f"[1e8 rows] {fam} theta={th} {prec}: combined {g['combined_theta'][0]:.6f} (se {se:.2e}), "
               f"mean Newton passes {g['iters'].mean():.2f}, {times[prec]:.1f} ms", flush=True)
         del ws
-    print(f"[config4] {fam}: n={w.n} K={w.K}, FP32c {times['fp32c']:.1f} ms, FP64 {times['fp64']:.1f} ms, "
+    print(f"[1e8 rows] {fam}: n={w.n} K={w.K}, FP32c {times['fp32c']:.1f} ms, FP64 {times['fp64']:.1f} ms, "
           f"speed-up {times['fp64'] / times['fp32c']:.2f}x (generation {gen:.1f} s)", flush=True)
 
 
-def test_config3_full_size():
+def test_replicate_batch_full_size():
     m = cpc()
     t0 = time.time()
-    w = synth.config3()
+    w = synth.replicate_batch()
     gen = time.time() - t0
     assert w.K == 50_000 and w.G == 1000
     x, y = dev(w.x, torch.float32), dev(w.y, torch.float32)
@@ -188,7 +188,7 @@ def test_config3_full_size():
     pick = sorted(set(rng.choice(fitted, 30, replace=False).tolist()
                       + np.argsort(sizes)[-4:].tolist()                       # largest (streaming path)
                       + fitted[np.argsort(sizes[fitted])[:6]].tolist()))      # smallest fitted
-    check_against_oracle(g, w, pick, fam_of, "fp32c", "config3")
-    print(f"[config3] K={w.K} subsets (sizes {sizes.min()}..{sizes.max()}), G={w.G}: "
+    check_against_oracle(g, w, pick, fam_of, "fp32c", "replicate_batch")
+    print(f"[replicate batch] K={w.K} subsets (sizes {sizes.min()}..{sizes.max()}), G={w.G}: "
           f"statuses {dict(zip(*np.unique(st, return_counts=True)))}, {ms:.1f} ms per graph replay "
           f"({w.K / (ms / 1e3):.0f} subset-fits/s; generation {gen:.1f} s)", flush=True)
