@@ -1034,3 +1034,145 @@ void or_spearman_fit_ranks(const int64_t* R1, const int64_t* R2, int64_t n, int3
     if (!(v > 0.0) || !isfinite(v)) out->status = OR_BADVAR;
   }
 }
+
+/* ======================================================================== */
+/* The inversion of Kendall's tau (Sec. 2.3 names it with Spearman's rho):
+ * tau hat = (concordant - discordant pairs) / (n (n - 1) / 2), a pair tied
+ * in either margin counting as neither; theta with tau(theta) = tau hat
+ * (closed forms for the Gaussian, sin(pi tau / 2), and for Gumbel,
+ * 1 / (1 - tau); for Frank the Debye form of tau solved by regula falsi);
+ * tau hat is a U-statistic of degree two with kernel
+ * sign(r1_i - r1_l) sign(r2_i - r2_l), so var(tau hat) ~ 4 var(k1) / n with
+ * k1_i = S_i / (n - 1), S_i = sum over l != i of that kernel, and the
+ * estimate's variance is var(tau hat) / tau'(theta)^2.                      */
+
+static int sgn64(int64_t d) { return (d > 0) - (d < 0); }
+
+/* S_i of every row, by all pairs */
+void or_kendall_rows(const int64_t* R1, const int64_t* R2, int64_t n, int64_t* S) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t s = 0;
+    for (int64_t l = 0; l < n; ++l) s += sgn64(R1[i] - R1[l]) * sgn64(R2[i] - R2[l]);
+    S[i] = s;
+  }
+}
+
+/* tau hat of doubled ranks (all pairs) */
+double or_kendall(const int64_t* R1, const int64_t* R2, int64_t n) {
+  if (n < 2) return NAN;
+  int64_t* S = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  or_kendall_rows(R1, R2, n, S);
+  int64_t t = 0;
+  for (int64_t i = 0; i < n; ++i) t += S[i];
+  free(S);
+  return (double)t / ((double)n * (double)(n - 1));
+}
+
+/* d tau / d theta: Gaussian 2 / (pi sqrt(1 - theta^2)); Gumbel 1 / theta^2;
+ * Frank, from tau = 1 - (4 / theta)(1 - D1(theta)) and
+ * D1'(x) = -D1(x) / x + 1 / (e^x - 1): 4 (1 - D1) / theta^2 + 4 D1' / theta,
+ * by its series 1/9 - theta^2 / 300 + theta^4 / 10584 below |theta| = 1e-2 */
+double or_tau_slope(int32_t f, double th) {
+  if (f == OR_GAUSSIAN) return 2.0 / (M_PI * sqrt(1.0 - th * th));
+  if (f == OR_GUMBEL) return 1.0 / (th * th);
+  if (fabs(th) < 1e-2) {
+    const double t2 = th * th;
+    return 1.0 / 9.0 - t2 / 300.0 + t2 * t2 / 10584.0;
+  }
+  const double d1 = or_debye(1, th);
+  const double dd1 = -d1 / th + 1.0 / expm1(th);
+  return 4.0 * (1.0 - d1) / (th * th) + 4.0 * dd1 / th;
+}
+
+/* theta with tau(theta) = t: status 0, 1 (Gumbel at theta = 1, t <= 0) or 2
+ * (at the family's search box edge) */
+double or_kendall_theta(int32_t f, double t, int32_t* status) {
+  *status = OR_OK;
+  const double lo0 = box_lo(f), hi0 = box_hi(f);
+  if (f == OR_GAUSSIAN) {
+    const double th = sin(0.5 * M_PI * t);
+    if (th <= lo0) { *status = OR_BOUNDARY_BOX; return lo0; }
+    if (th >= hi0) { *status = OR_BOUNDARY_BOX; return hi0; }
+    return th;
+  }
+  if (f == OR_GUMBEL) {
+    if (t <= 0.0) { *status = OR_BOUNDARY_NATURAL; return 1.0; }
+    if (t >= 1.0 - 1.0 / hi0) { *status = OR_BOUNDARY_BOX; return hi0; }
+    return 1.0 / (1.0 - t);
+  }
+  double lo = lo0, hi = hi0;
+  double flo = or_tau(f, lo) - t, fhi = or_tau(f, hi) - t;
+  if (flo >= 0.0) { *status = OR_BOUNDARY_BOX; return lo; }
+  if (fhi <= 0.0) { *status = OR_BOUNDARY_BOX; return hi; }
+  /* tau increases in theta: regula falsi with the Illinois halving, bisection
+   * where the secant point leaves the bracket */
+  double m = lo, prev = hi;
+  int side = 0;
+  for (int it = 0; it < 200; ++it) {
+    m = (lo * fhi - hi * flo) / (fhi - flo);
+    if (!(m > lo && m < hi)) m = 0.5 * (lo + hi);
+    const double fm = or_tau(f, m) - t;
+    if (fm == 0.0 || fabs(m - prev) <= 1e-13 * (1.0 + fabs(m)) || hi - lo <= 1e-12 * (1.0 + fabs(lo))) break;
+    prev = m;
+    if (fm < 0.0) {
+      lo = m; flo = fm;
+      if (side == -1) fhi *= 0.5;
+      side = -1;
+    } else {
+      hi = m; fhi = fm;
+      if (side == 1) flo *= 0.5;
+      side = 1;
+    }
+  }
+  return m;
+}
+
+/* Variance of the Kendall-inversion estimate at theta; var(k1) in *zeta and
+ * tau hat in *tau_hat */
+double or_kendall_var(const int64_t* R1, const int64_t* R2, int64_t n, int32_t f, double theta, double* zeta,
+                      double* tau_hat) {
+  int64_t* S = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
+  or_kendall_rows(R1, R2, n, S);
+  int64_t tot = 0;
+  for (int64_t i = 0; i < n; ++i) tot += S[i];
+  const double th = (double)tot / ((double)n * (double)(n - 1));
+  double q = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    const double k1 = (double)S[i] / (double)(n - 1) - th;
+    q += k1 * k1;
+  }
+  free(S);
+  *tau_hat = th;
+  *zeta = q / (double)n;
+  const double b = or_tau_slope(f, theta);
+  return 4.0 * *zeta / ((double)n * b * b);
+}
+
+/* One subset from its doubled ranks: out->loglik = tau hat, out->score =
+ * tau(theta) - tau hat (statuses as for Spearman's rho) */
+void or_kendall_fit_ranks(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, int64_t n_min,
+                          or_subset* out) {
+  out->theta = NAN; out->var = NAN; out->loglik = NAN; out->score = NAN;
+  out->n = n; out->iters = 0; out->status = OR_OK;
+  if (n < (n_min < 2 ? 2 : n_min)) { out->status = OR_DEGENERATE; return; }
+  int same1 = 1, same2 = 1;
+  for (int64_t i = 1; i < n; ++i) {
+    if (R1[i] != R1[0]) same1 = 0;
+    if (R2[i] != R2[0]) same2 = 0;
+  }
+  if (same1 || same2) { out->status = OR_DEGENERATE; return; }
+  const double t = or_kendall(R1, R2, n);
+  int32_t st;
+  const double th = or_kendall_theta(family, t, &st);
+  out->theta = th;
+  out->status = st;
+  out->loglik = t;
+  out->score = or_tau(family, th) - t;
+  if (st == OR_OK || st == OR_BOUNDARY_NATURAL) {
+    double zeta, t2;
+    const double v = or_kendall_var(R1, R2, n, family, th, &zeta, &t2);
+    out->var = v;
+    if (!(v > 0.0) || !isfinite(v)) out->status = OR_BADVAR;
+  }
+}

@@ -110,6 +110,23 @@ double or_spearman_var(const int64_t* R1, const int64_t* R2, int64_t n, int32_t 
 void or_spearman_fit_ranks(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, int64_t n_min,
                            or_subset* out);
 
+/* The inversion of Kendall's tau as an estimator (Sec. 2.3). */
+/* S_i = sum over l != i of sign(r1_i - r1_l) sign(r2_i - r2_l), all pairs */
+void or_kendall_rows(const int64_t* R1, const int64_t* R2, int64_t n, int64_t* S);
+/* tau hat of doubled ranks (ties count as neither concordant nor discordant) */
+double or_kendall(const int64_t* R1, const int64_t* R2, int64_t n);
+/* d tau / d theta */
+double or_tau_slope(int32_t family, double theta);
+/* theta with tau(theta) = t; status OK, BOUNDARY_NATURAL or BOUNDARY_BOX */
+double or_kendall_theta(int32_t family, double t, int32_t* status);
+/* variance of the estimate at theta (4 var(k1) / (n tau'^2)); var(k1) in
+ * *zeta, tau hat in *tau_hat */
+double or_kendall_var(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, double theta, double* zeta,
+                      double* tau_hat);
+/* one subset from its doubled ranks (loglik = tau hat, score = tau(theta) - tau hat) */
+void or_kendall_fit_ranks(const int64_t* R1, const int64_t* R2, int64_t n, int32_t family, int64_t n_min,
+                          or_subset* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,6 +105,18 @@ def lib():
         L.or_spearman_var.argtypes = [p, p, i64, i32, d, p]
         L.or_spearman_fit_ranks.restype = None
         L.or_spearman_fit_ranks.argtypes = [p, p, i64, i32, i64, p]
+        L.or_kendall_rows.restype = None
+        L.or_kendall_rows.argtypes = [p, p, i64, p]
+        L.or_kendall.restype = d
+        L.or_kendall.argtypes = [p, p, i64]
+        L.or_tau_slope.restype = d
+        L.or_tau_slope.argtypes = [i32, d]
+        L.or_kendall_theta.restype = d
+        L.or_kendall_theta.argtypes = [i32, d, p]
+        L.or_kendall_var.restype = d
+        L.or_kendall_var.argtypes = [p, p, i64, i32, d, p, p]
+        L.or_kendall_fit_ranks.restype = None
+        L.or_kendall_fit_ranks.argtypes = [p, p, i64, i32, i64, p]
         _lib = L
     return _lib
 
@@ -303,5 +315,67 @@ def spearman_fit_ranks(R1, R2, offsets, family, group_offsets=None, n_min=2):
             a, b = offsets[m], offsets[m + 1]
             one = np.zeros(1, dtype=SUBSET_DTYPE)
             L.or_spearman_fit_ranks(_ptr(R1[a:b]), _ptr(R2[a:b]), b - a, _fam(fams[g]), int(n_min), _ptr(one))
+            sub[m] = one[0]
+    return sub, combine(sub, group_offsets)
+
+
+# --------------------------------------------------------------------------
+# The inversion of Kendall's tau as an estimator (Sec. 2.3).
+
+def kendall_rows(R1, R2) -> np.ndarray:
+    """S_i = sum over l != i of sign(r1_i - r1_l) sign(r2_i - r2_l)."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    S = np.zeros(R1.shape[0], dtype=np.int64)
+    lib().or_kendall_rows(_ptr(R1), _ptr(R2), R1.shape[0], _ptr(S))
+    return S
+
+
+def kendall(R1, R2) -> float:
+    """tau hat from doubled ranks."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    return lib().or_kendall(_ptr(R1), _ptr(R2), R1.shape[0])
+
+
+def tau_slope(family, theta: float) -> float:
+    return lib().or_tau_slope(_fam(family), float(theta))
+
+
+def kendall_theta(family, t: float):
+    """theta with tau(theta) = t, and the status (0, 1 natural boundary, 2 box edge)."""
+    st = ctypes.c_int32()
+    th = lib().or_kendall_theta(_fam(family), float(t), ctypes.byref(st))
+    return th, st.value
+
+
+def kendall_var(R1, R2, family, theta: float):
+    """(variance of the estimate, var(k1), tau hat) at theta."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    zeta, t = ctypes.c_double(), ctypes.c_double()
+    v = lib().or_kendall_var(_ptr(R1), _ptr(R2), R1.shape[0], _fam(family), float(theta), ctypes.byref(zeta),
+                             ctypes.byref(t))
+    return v, zeta.value, t.value
+
+
+def kendall_fit_ranks(R1, R2, offsets, family, group_offsets=None, n_min=2):
+    """Per subset from doubled ranks, and the combination of eq. (15) per group."""
+    R1 = np.ascontiguousarray(R1, dtype=np.int64)
+    R2 = np.ascontiguousarray(R2, dtype=np.int64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    K = offsets.shape[0] - 1
+    if group_offsets is None:
+        group_offsets = np.array([0, K], dtype=np.int64)
+    group_offsets = np.ascontiguousarray(group_offsets, dtype=np.int64)
+    G = group_offsets.shape[0] - 1
+    fams = [family] * G if isinstance(family, (str, int, np.integer)) else list(family)
+    sub = np.zeros(K, dtype=SUBSET_DTYPE)
+    L = lib()
+    for g in range(G):
+        for m in range(group_offsets[g], group_offsets[g + 1]):
+            a, b = offsets[m], offsets[m + 1]
+            one = np.zeros(1, dtype=SUBSET_DTYPE)
+            L.or_kendall_fit_ranks(_ptr(R1[a:b]), _ptr(R2[a:b]), b - a, _fam(fams[g]), int(n_min), _ptr(one))
             sub[m] = one[0]
     return sub, combine(sub, group_offsets)
