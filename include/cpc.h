@@ -292,6 +292,57 @@ int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int
                      const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
                      size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
 
+/* Workspace bytes of cpc_kendall_fit for n rows, K subsets and G groups. */
+size_t cpc_kendall_workspace_bytes(int64_t n, int64_t K, int64_t G);
+
+/* The inversion of Kendall's tau as the estimator of each subset (Sec. 2.3
+ * names it beside Spearman's rho), combined per group by eq. (15):
+ *   tau hat = (concordant - discordant pairs) / (n (n - 1) / 2) of the
+ *   doubled ranks R1, R2 (device, n each, as made by cpc_rank; a pair tied in
+ *   either margin counts as neither), theta with tau(theta) = tau hat
+ *   (Gaussian sin(pi tau / 2), Gumbel 1 / (1 - tau), Frank through
+ *   tau = 1 - 4 (1 - D1(theta)) / theta with the Debye function D1), and the
+ *   variance of the estimate as that of a U-statistic of degree two:
+ *   4 var(S_i / (n - 1)) / (n tau'(theta)^2) with
+ *   S_i = sum_l sign(r1_i - r1_l) sign(r2_i - r2_l).
+ * Subsets of at most 2^20 rows (CPC_E_UNSUPPORTED beyond). out, comb,
+ * statuses and opt as for cpc_spearman_fit, with loglik = tau hat and
+ * score = tau(theta) - tau hat. workspace: device, at least
+ * cpc_kendall_workspace_bytes(n, K, G). */
+int cpc_kendall_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n,
+                    const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+                    const int32_t* family_per_group, const cpc_options_t* opt, void* workspace,
+                    size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
+
+/* Workspace bytes of cpc_gaussk_fit for n rows of k margins, K subsets and
+ * G groups (0 for k outside 2..8). */
+size_t cpc_gaussk_workspace_bytes(int64_t n, int32_t k, int64_t K, int64_t G);
+
+/* The k-dimensional Gaussian copula of eq. (7), C(u; R) =
+ * Phi_R(Phi^-1(u_1), ..., Phi^-1(u_k)), fitted by maximum pseudo-likelihood
+ * on every subset (the multi-parameter extension Sec. 4 leaves as future
+ * work), with 2 <= k <= 8 (CPC_E_UNSUPPORTED above):
+ *   R: device, k columns of n doubled ranks (column j at R + j n, as made by
+ *   cpc_rank for each margin); per subset the normal scores
+ *   z = Phi^-1(R / (2 (n + 1))), the Gram matrix G = sum z z', and the
+ *   p = k (k - 1) / 2 correlations r_jl (j < l, order (0,1), (0,2), ...,
+ *   (k-2,k-1)) maximising -(n/2) log det R - (1/2) tr((R^-1 - I) G) (Newton
+ *   from the normalised Gram matrix); each correlation's variance from the
+ *   rank-based sandwich J^-1 Omega J^-1 / n (J the mean outer product of the
+ *   per-row scores, Omega the covariance of the scores plus their rank
+ *   corrections, as in the one-parameter variance).
+ * out (device, p K entries, parameter-major: entry q K + m is parameter q of
+ * subset m): theta = r_q, var, loglik (of the subset), score (dl/dr_q), n,
+ * iters, status (DEGENERATE for fewer than max(n_min, k + 1) rows or a
+ * margin of one value; BOUNDARY_BOX when the normalised Gram matrix is not
+ * positive definite; NOCONV; BADVAR). comb (device, p G entries, entry
+ * q G + g): eq. (15) per parameter over the OK subsets of group g. Of opt
+ * only n_min is used. workspace: device, at least
+ * cpc_gaussk_workspace_bytes(n, k, K, G). */
+int cpc_gaussk_fit(cpc_handle_t h, const uint32_t* R, int64_t n, int32_t k, const int64_t* offsets, int64_t K,
+                   const int64_t* group_offsets, int64_t G, const cpc_options_t* opt, void* workspace,
+                   size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);
+
 /* Durations (milliseconds) of the phases of the handle's last cpc_fit /
  * cpc_fit_batched call made with CPC_FLAG_PHASE_TIMES: ms[0] ranks (eq. 12),
  * ms[1] maximisation of eq. (13), ms[2] variance (Sec. 2.3), ms[3] combine

@@ -27,7 +27,8 @@ STATUS = {0: "OK", 1: "BOUNDARY_NATURAL", 2: "BOUNDARY_BOX", 3: "DEGENERATE", 4:
           6: "BADVAR"}
 
 __all__ = ["fit", "fit_batched", "rank", "eval_subsets", "variance", "LogLik", "Score", "FitResult",
-           "CpcError", "workspace_bytes", "sample", "density_distance", "replicate_summary", "spearman_fit", "FAMILIES", "STATUS"]
+           "CpcError", "workspace_bytes", "sample", "density_distance", "replicate_summary", "spearman_fit",
+           "kendall_fit", "rank_margins", "gaussk_fit", "FAMILIES", "STATUS"]
 
 
 def _code(table, v):
@@ -375,4 +376,74 @@ def spearman_fit(R1: torch.Tensor, R2: torch.Tensor, offsets, families, group_of
                                  gofs.ctypes.data, G, fams.ctypes.data, ctypes.byref(o), ws.data_ptr(),
                                  ws.numel() * ws.element_size(), out.raw.data_ptr(), out.raw_comb.data_ptr(),
                                  _stream(R1.device)))
+    return out
+
+
+def kendall_fit(R1: torch.Tensor, R2: torch.Tensor, offsets, families, group_offsets=None, *, n_min: int = 2,
+                 workspace: Optional[torch.Tensor] = None) -> FitResult:
+    """The inversion of Kendall's tau per subset (at most 2^20 rows) from
+    doubled ranks (as made by rank()), combined per group by eq. (15).
+    ``families``: one family, or one per group."""
+    R1 = _dev(R1, "R1")
+    R2 = _dev(R2, "R2")
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    gofs = _i64(group_offsets if group_offsets is not None else [0, K])
+    G = gofs.shape[0] - 1
+    if isinstance(families, (str, int)):
+        families = [families] * G
+    fams = np.ascontiguousarray([_code(FAMILIES, f) for f in families], dtype=np.int32)
+    n = R1.shape[0]
+    o = _options(n_min=n_min)
+    nbytes = int(lib().cpc_kendall_workspace_bytes(n, K, G))
+    ws = _workspace(nbytes, R1.device, workspace)
+    out = FitResult(torch.empty((K, 6), dtype=torch.float64, device=R1.device),
+                    torch.empty((G, 5), dtype=torch.float64, device=R1.device))
+    check(lib().cpc_kendall_fit(_handle(R1.device), R1.data_ptr(), R2.data_ptr(), n, offsets.ctypes.data, K,
+                                gofs.ctypes.data, G, fams.ctypes.data, ctypes.byref(o), ws.data_ptr(),
+                                ws.numel() * ws.element_size(), out.raw.data_ptr(), out.raw_comb.data_ptr(),
+                                _stream(R1.device)))
+    return out
+
+
+def rank_margins(X: torch.Tensor, offsets, **opt) -> torch.Tensor:
+    """Doubled ranks (eq. 12) of every margin of X (k x n, one margin per row)
+    within each subset: (k, n) int32, two margins per cpc_rank call."""
+    X = _dev(X, "X")
+    if X.dim() != 2:
+        raise ValueError("X must be k x n")
+    k = X.shape[0]
+    R = torch.empty(X.shape, dtype=torch.int32, device=X.device)
+    for j in range(0, k, 2):
+        a, b = rank(X[j].contiguous(), X[min(j + 1, k - 1)].contiguous(), offsets, **opt)
+        R[j].copy_(a)
+        if j + 1 < k:
+            R[j + 1].copy_(b)
+    return R
+
+
+def gaussk_fit(R: torch.Tensor, offsets, group_offsets=None, *, n_min: int = 2,
+               workspace: Optional[torch.Tensor] = None) -> FitResult:
+    """The k-dimensional Gaussian copula of eq. (7) by pseudo-likelihood per
+    subset from doubled ranks R (k x n int32, as made by rank_margins;
+    2 <= k <= 8), combined per group and parameter by eq. (15). The result is
+    parameter-major: entry q K + m is correlation q (order (0,1), (0,2), ...,
+    (k-2,k-1)) of subset m; combined entry q G + g."""
+    R = _dev(R, "R")
+    if R.dim() != 2:
+        raise ValueError("R must be k x n")
+    k, n = int(R.shape[0]), int(R.shape[1])
+    p = k * (k - 1) // 2
+    offsets = _i64(offsets)
+    K = offsets.shape[0] - 1
+    gofs = _i64(group_offsets if group_offsets is not None else [0, K])
+    G = gofs.shape[0] - 1
+    o = _options(n_min=n_min)
+    nbytes = int(lib().cpc_gaussk_workspace_bytes(n, k, K, G))
+    ws = _workspace(max(nbytes, 1), R.device, workspace)
+    out = FitResult(torch.empty((max(p, 1) * K, 6), dtype=torch.float64, device=R.device),
+                    torch.empty((max(p, 1) * G, 5), dtype=torch.float64, device=R.device))
+    check(lib().cpc_gaussk_fit(_handle(R.device), R.data_ptr(), n, k, offsets.ctypes.data, K, gofs.ctypes.data, G,
+                               ctypes.byref(o), ws.data_ptr(), ws.numel() * ws.element_size(), out.raw.data_ptr(),
+                               out.raw_comb.data_ptr(), _stream(R.device)))
     return out

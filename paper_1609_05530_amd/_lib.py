@@ -52,6 +52,11 @@ SIGNATURES = {
     "cpc_spearman_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
     "cpc_spearman_fit": (_I32, [_P, _P, _P, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P,
                                 _P]),
+    "cpc_kendall_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
+    "cpc_kendall_fit": (_I32, [_P, _P, _P, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P,
+                               _P]),
+    "cpc_gaussk_workspace_bytes": (_SZ, [_I64, _I32, _I64, _I64]),
+    "cpc_gaussk_fit": (_I32, [_P, _P, _I64, _I32, _P, _I64, _P, _I64, ctypes.POINTER(Options), _P, _SZ, _P, _P, _P]),
     "cpc_phase_times": (_I32, [_P, ctypes.POINTER(ctypes.c_float)]),
     "cpc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "cpc_last_error": (ctypes.c_char_p, []),

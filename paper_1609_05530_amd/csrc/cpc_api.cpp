@@ -1106,10 +1106,21 @@ size_t cpc_spearman_workspace_bytes(int64_t n, int64_t K, int64_t G) {
          2 * align_up(sizeof(long long) * 2 * (size_t)(n + K));
 }
 
-int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets,
-                     int64_t K, const int64_t* group_offsets, int64_t G, const int32_t* family_per_group,
-                     const cpc_options_t* opt, void* workspace, size_t ws_bytes, cpc_subset_result_t* out,
-                     cpc_combined_t* comb, void* stream) {
+size_t cpc_kendall_workspace_bytes(int64_t n, int64_t K, int64_t G) {
+  if (n < 0 || K < 1 || G < 1) return 0;
+  return align_up(sizeof(SubDesc) * (size_t)K) + align_up(sizeof(int64_t) * (size_t)(G + 1)) +
+         2 * align_up(sizeof(unsigned long long) * (size_t)n) + align_up(sizeof(int) * (size_t)n);
+}
+
+namespace {
+
+constexpr int64_t kKendallMaxRows = int64_t(1) << 20;
+
+// cpc_spearman_fit (kendall = false) and cpc_kendall_fit (kendall = true)
+int moment_fit(bool kendall, cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n,
+               const int64_t* offsets, int64_t K, const int64_t* group_offsets, int64_t G,
+               const int32_t* family_per_group, const cpc_options_t* opt, void* workspace, size_t ws_bytes,
+               cpc_subset_result_t* out, cpc_combined_t* comb, void* stream) {
   if (int rc = check_handle(h)) return rc;
   if (!R1 || !R2 || !offsets || !group_offsets || !family_per_group || !out || !comb)
     return fail(CPC_E_NULL, "a required pointer is NULL");
@@ -1125,13 +1136,17 @@ int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int
     if (family_per_group[g] < 0 || family_per_group[g] > 2)
       return fail(CPC_E_ENUM, "unknown family %d for group %lld", family_per_group[g], (long long)g);
     for (int64_t m = group_offsets[g]; m < group_offsets[g + 1]; ++m) {
+      const int64_t nm = offsets[m + 1] - offsets[m];
+      if (kendall && nm > kKendallMaxRows)
+        return fail(CPC_E_UNSUPPORTED, "subset %lld has %lld rows; the Kendall estimator takes at most %lld",
+                    (long long)m, (long long)nm, (long long)kKendallMaxRows);
       subs[m].begin = offsets[m];
-      subs[m].n = (int32_t)(offsets[m + 1] - offsets[m]);
+      subs[m].n = (int32_t)nm;
       subs[m].family = (int16_t)family_per_group[g];
       subs[m].group = 0;
     }
   }
-  const size_t need = cpc_spearman_workspace_bytes(n, K, G);
+  const size_t need = kendall ? cpc_kendall_workspace_bytes(n, K, G) : cpc_spearman_workspace_bytes(n, K, G);
   if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
   if (ws_bytes < need) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
   unsigned char* b = (unsigned char*)workspace;
@@ -1139,9 +1154,22 @@ int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int
   b += align_up(sizeof(SubDesc) * (size_t)K);
   int64_t* dgofs = (int64_t*)b;
   b += align_up(sizeof(int64_t) * (size_t)(G + 1));
-  long long* H1 = (long long*)b;
-  b += align_up(sizeof(long long) * 2 * (size_t)(n + K));
-  long long* H2 = (long long*)b;
+  long long* H1 = nullptr;
+  long long* H2 = nullptr;
+  unsigned long long* W0 = nullptr;
+  unsigned long long* W1 = nullptr;
+  int* C = nullptr;
+  if (kendall) {
+    W0 = (unsigned long long*)b;
+    b += align_up(sizeof(unsigned long long) * (size_t)n);
+    W1 = (unsigned long long*)b;
+    b += align_up(sizeof(unsigned long long) * (size_t)n);
+    C = (int*)b;
+  } else {
+    H1 = (long long*)b;
+    b += align_up(sizeof(long long) * 2 * (size_t)(n + K));
+    H2 = (long long*)b;
+  }
   HIP_OK(hipSetDevice(h->device));
   hipStream_t s = (hipStream_t)stream;
   touch_workspace(h, workspace);
@@ -1156,11 +1184,98 @@ int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int
     int64_t h2 = g;
     while (h2 < G && family_per_group[h2] == family_per_group[g]) ++h2;
     const int64_t m0 = group_offsets[g], m1 = group_offsets[h2];
-    if (m1 > m0)
-      HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, H1, H2, (ResultOut*)out, s));
+    if (m1 > m0) {
+      if (kendall)
+        HIP_OK(launch_kendall(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, W0, W1, C,
+                              (ResultOut*)out, s));
+      else
+        HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, H1, H2, (ResultOut*)out, s));
+    }
     g = h2;
   }
   HIP_OK(launch_combine((const ResultOut*)out, dgofs, G, (CombinedOut*)comb, s));
+  return CPC_SUCCESS;
+}
+
+}  // namespace
+
+int cpc_spearman_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets,
+                     int64_t K, const int64_t* group_offsets, int64_t G, const int32_t* family_per_group,
+                     const cpc_options_t* opt, void* workspace, size_t ws_bytes, cpc_subset_result_t* out,
+                     cpc_combined_t* comb, void* stream) {
+  return moment_fit(false, h, R1, R2, n, offsets, K, group_offsets, G, family_per_group, opt, workspace, ws_bytes,
+                    out, comb, stream);
+}
+
+int cpc_kendall_fit(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets,
+                    int64_t K, const int64_t* group_offsets, int64_t G, const int32_t* family_per_group,
+                    const cpc_options_t* opt, void* workspace, size_t ws_bytes, cpc_subset_result_t* out,
+                    cpc_combined_t* comb, void* stream) {
+  return moment_fit(true, h, R1, R2, n, offsets, K, group_offsets, G, family_per_group, opt, workspace, ws_bytes,
+                    out, comb, stream);
+}
+
+size_t cpc_gaussk_workspace_bytes(int64_t n, int32_t k, int64_t K, int64_t G) {
+  if (n < 0 || k < 2 || k > 8 || K < 1 || G < 1) return 0;
+  const int64_t p = (int64_t)k * (k - 1) / 2;
+  return align_up(sizeof(SubDesc) * (size_t)K) + align_up(sizeof(int64_t) * (size_t)(p * G + 1)) +
+         align_up(sizeof(double) * (size_t)n * (size_t)k) + align_up(sizeof(double) * (size_t)n * (size_t)gaussk_ldx(k)) +
+         align_up(sizeof(double) * (size_t)(2 * n + 2 * K) * (size_t)k);
+}
+
+int cpc_gaussk_fit(cpc_handle_t h, const uint32_t* R, int64_t n, int32_t k, const int64_t* offsets, int64_t K,
+                   const int64_t* group_offsets, int64_t G, const cpc_options_t* opt, void* workspace, size_t ws_bytes,
+                   cpc_subset_result_t* out, cpc_combined_t* comb, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!R || !offsets || !group_offsets || !out || !comb) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (K < 1 || G < 1) return fail(CPC_E_SIZE, "K and G must be >= 1");
+  if (k < 2) return fail(CPC_E_SIZE, "k = %d: at least two margins", (int)k);
+  if (k > 8) return fail(CPC_E_UNSUPPORTED, "k = %d: at most 8 margins", (int)k);
+  Options o;
+  if (int rc = read_options(opt, o)) return rc;
+  if (int rc = check_offsets(offsets, K, n)) return rc;
+  if (group_offsets[0] != 0 || group_offsets[G] != K) return fail(CPC_E_OFFSETS, "group_offsets must run from 0 to K");
+  for (int64_t g = 0; g < G; ++g)
+    if (group_offsets[g + 1] < group_offsets[g]) return fail(CPC_E_OFFSETS, "group_offsets decrease at %lld", (long long)g);
+  const size_t need = cpc_gaussk_workspace_bytes(n, k, K, G);
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+  const int64_t p = (int64_t)k * (k - 1) / 2;
+  std::vector<SubDesc> subs((size_t)K);
+  for (int64_t m = 0; m < K; ++m) {
+    subs[m].begin = offsets[m];
+    subs[m].n = (int32_t)(offsets[m + 1] - offsets[m]);
+    subs[m].family = (int16_t)FAM_GAUSSIAN;
+    subs[m].group = 0;
+  }
+  // eq. (15) per parameter and group: group (q, g) spans the entries
+  // q K + group_offsets[g] .. q K + group_offsets[g + 1] of the parameter-major results
+  std::vector<int64_t> gofs((size_t)(p * G + 1));
+  for (int64_t q = 0; q < p; ++q)
+    for (int64_t g = 0; g < G; ++g) gofs[(size_t)(q * G + g)] = q * K + group_offsets[g];
+  gofs[(size_t)(p * G)] = p * K;
+  unsigned char* b = (unsigned char*)workspace;
+  SubDesc* dsubs = (SubDesc*)b;
+  b += align_up(sizeof(SubDesc) * (size_t)K);
+  int64_t* dgofs = (int64_t*)b;
+  b += align_up(sizeof(int64_t) * (size_t)(p * G + 1));
+  double* Z = (double*)b;
+  b += align_up(sizeof(double) * (size_t)n * (size_t)k);
+  double* X = (double*)b;
+  b += align_up(sizeof(double) * (size_t)n * (size_t)gaussk_ldx(k));
+  double* B = (double*)b;
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  touch_workspace(h, workspace);
+  // the host tables stay alive in the handle until the next call (the copies are asynchronous)
+  Plan& P = plan_of(h);
+  P.subs = subs;
+  P.gofs = gofs;
+  HIP_OK(hipMemcpyAsync(dsubs, P.subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(dgofs, P.gofs.data(), sizeof(int64_t) * P.gofs.size(), hipMemcpyHostToDevice, s));
+  HIP_OK(launch_gaussk(R, n, k, dsubs, K, o.n_min, Z, X, B, (ResultOut*)out, s));
+  HIP_OK(launch_combine((const ResultOut*)out, dgofs, p * G, (CombinedOut*)comb, s));
   return CPC_SUCCESS;
 }
 

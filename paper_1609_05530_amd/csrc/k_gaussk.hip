@@ -1,0 +1,510 @@
+// k_gaussk.hip — the k-dimensional Gaussian copula of eq. (7) of
+// arXiv:1609.05530 (C(u; R) = Phi_R(Phi^-1(u_1), ..., Phi^-1(u_k))) fitted by
+// maximum pseudo-likelihood on every subset: the multi-parameter extension
+// the paper leaves as future work. Parameters: the p = k (k - 1) / 2
+// correlations r_jl (j < l) in the order (0,1), (0,2), ..., (k-2,k-1).
+//
+// One workgroup of 256 threads per subset (k <= 8, any subset size):
+//   1. normal scores z_ij = Phi^-1(R_ij / (2 (n + 1))) of the doubled ranks;
+//   2. the Gram matrix G = sum_i z_i z_i' on the FP64 matrix cores
+//      (16 x 16 x 4 MFMA, four rows per instruction, the k margins padded to
+//      16; each wave takes every fourth block of rows);
+//   3. l(R) = -(n/2) log det R - (1/2) tr((R^-1 - I) G) is maximised by
+//      Newton on the p correlations (thread 0, everything in LDS): with
+//      P = R^-1, M = P G P, dl/dr_jl = -n P_jl + M_jl and
+//      d2l/dr_jl dr_st = n (P_js P_tl + P_jt P_sl)
+//                        - (P_js M_tl + P_jt M_sl + M_js P_tl + M_jt P_sl),
+//      from the normalised Gram matrix, a step halved until R stays positive
+//      definite, to max |step| <= 1e-12 (1 + max |r|);
+//   4. the sandwich variance: per row the scores s_i,jl = -P_jl + y_ij y_il
+//      (y_i = P z_i) and psi_i = s_i + sum_m W_m(u_im), W_m(u_im) the mean over
+//      the rows with u_lm >= u_im of ds_l/du_m = (P_jm y_l + y_j P_lm) /
+//      phi(z_m): for each margin m the vectors y_l / phi(z_lm) are added into
+//      bins indexed by the doubled rank (FP64 atomics; only tied rows share a
+//      bin) and suffix-summed over the bins, so a tie group takes the whole
+//      group. J = (1/n) sum s s' and Omega = cov(psi) are p x p contractions
+//      over the rows, again on the FP64 MFMA (p padded to 16 or 32: one or
+//      three 16 x 16 tiles); V = J^-1 Omega J^-1 / n, each parameter's
+//      variance V_qq.
+// The results are parameter-major (entry q K + m) so that the combination of
+// eq. (15) runs per parameter over each group (k_combine).
+#include <hip/hip_runtime.h>
+
+#include "family_math.h"
+#include "kernels.h"
+
+namespace cpc {
+
+namespace {
+
+constexpr int GT = 256;  // threads per workgroup
+constexpr int GW = GT / WAVE;
+constexpr int KMAX = 8;
+constexpr int PMAX = KMAX * (KMAX - 1) / 2;  // 28
+constexpr int PPAD = 32;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct GkParams {
+  const uint32_t* R;   // k columns of n_total doubled ranks
+  int64_t n_total;
+  int k, p, ldx, pad;
+  const SubDesc* subs;
+  int64_t n_min;
+  double* Z;           // rows x k (row-major), a subset's rows at its begin
+  double* X;           // rows x ldx: scores, then psi
+  double* B;           // bins: subset m owns (2 n + 2) k doubles from 2 (begin + m) k
+  ResultOut* out;      // parameter-major: q K + m
+  int64_t K;
+};
+
+// sum over rows r of A[r][i0 + i] A[r][j0 + j] (i, j < 16), A row-major with
+// leading dimension lda and ncol valid columns (the rest read as 0); rows
+// r0 = 4 (first + t step) .. of [0, n). Operands: lane l gives A[l % 16][l / 16]
+// and B[l / 16][l % 16]; the lane's 4 results are D[l / 16 + 4 e][l % 16]
+// (e = 0..3; the rows interleave across the four 16-lane groups, as measured
+// on gfx950).
+__device__ __forceinline__ d4 tile_gram(const double* A, int lda, int n, int i0, int j0, int ncol, int first,
+                                         int step) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int c = lane & 15, rr = lane >> 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 4 * first; r0 < n; r0 += 4 * step) {
+    const int r = r0 + rr;
+    double a = 0.0, b = 0.0;
+    if (r < n) {
+      if (i0 + c < ncol) a = A[(int64_t)r * lda + i0 + c];
+      if (j0 + c < ncol) b = A[(int64_t)r * lda + j0 + c];
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// The small dense linear algebra below runs on thread 0 with its matrices in
+// LDS; kept out of line so that it does not claim the kernel's registers.
+
+// Cholesky factor (lower, in place) of the n x n matrix A (leading dimension
+// ld); false if a pivot is not positive.
+__device__ __noinline__ bool chol(double* A, int n, int ld) {
+  for (int j = 0; j < n; ++j) {
+    double d = A[j * ld + j];
+    for (int s = 0; s < j; ++s) d -= A[j * ld + s] * A[j * ld + s];
+    if (!(d > 0.0)) return false;
+    d = sqrt(d);
+    A[j * ld + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * ld + j];
+      for (int s = 0; s < j; ++s) v -= A[i * ld + s] * A[j * ld + s];
+      A[i * ld + j] = v / d;
+    }
+  }
+  return true;
+}
+
+// Solve L L' x = b in place (b overwritten by x).
+__device__ __noinline__ void chol_solve(const double* L, int n, int ld, double* b) {
+  for (int i = 0; i < n; ++i) {
+    double v = b[i];
+    for (int s = 0; s < i; ++s) v -= L[i * ld + s] * b[s];
+    b[i] = v / L[i * ld + i];
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double v = b[i];
+    for (int s = i + 1; s < n; ++s) v -= L[s * ld + i] * b[s];
+    b[i] = v / L[i * ld + i];
+  }
+}
+
+struct GkShared {
+  double tiles[GW][16][16];  // per-wave MFMA tiles, reduced into G / J / Omega
+  double G[KMAX][KMAX];
+  double P[KMAX][KMAX];
+  double M[KMAX][KMAX];
+  double Rm[KMAX][KMAX];
+  double J[PPAD][PPAD];
+  double Om[PPAD][PPAD];
+  double Hm[PMAX][PMAX];
+  double th[PMAX], g[PMAX], st[PMAX], mu[PPAD], cand[PMAX], e[PMAX];
+  double L[KMAX][KMAX], PG[KMAX][KMAX];
+  double scal[4];  // loglik, status, iterations
+  double tot[GT][KMAX];
+  int pj[PMAX], pl[PMAX];
+  unsigned int mm[2 * KMAX];
+};
+
+// R from theta (thread 0)
+__device__ __noinline__ void corr_from(GkShared& S, const double* th, int k) {
+  int q = 0;
+  for (int j = 0; j < k; ++j) {
+    S.Rm[j][j] = 1.0;
+    for (int l = j + 1; l < k; ++l, ++q) S.Rm[j][l] = S.Rm[l][j] = th[q];
+  }
+}
+
+// Is the correlation matrix of th positive definite? (thread 0; uses M as scratch)
+__device__ __noinline__ bool corr_pd(GkShared& S, const double* th, int k) {
+  corr_from(S, th, k);
+  for (int j = 0; j < k; ++j)
+    for (int l = 0; l < k; ++l) S.M[j][l] = S.Rm[j][l];
+  return chol(&S.M[0][0], k, KMAX);
+}
+
+// P = R^-1, M = P G P and log det R (thread 0; R in S.Rm, positive definite)
+__device__ __noinline__ double inverse_and_m(GkShared& S, int k) {
+  for (int j = 0; j < k; ++j)
+    for (int l = 0; l < k; ++l) S.L[j][l] = S.Rm[j][l];
+  chol(&S.L[0][0], k, KMAX);
+  double logdet = 0.0;
+  for (int j = 0; j < k; ++j) logdet += 2.0 * log(S.L[j][j]);
+  for (int c = 0; c < k; ++c) {
+    for (int j = 0; j < k; ++j) S.e[j] = (j == c) ? 1.0 : 0.0;
+    chol_solve(&S.L[0][0], k, KMAX, S.e);
+    for (int j = 0; j < k; ++j) S.P[j][c] = S.e[j];
+  }
+  for (int j = 0; j < k; ++j)
+    for (int l = 0; l < k; ++l) {
+      double v = 0.0;
+      for (int s = 0; s < k; ++s) v += S.P[j][s] * S.G[s][l];
+      S.PG[j][l] = v;
+    }
+  for (int j = 0; j < k; ++j)
+    for (int l = 0; l < k; ++l) {
+      double v = 0.0;
+      for (int s = 0; s < k; ++s) v += S.PG[j][s] * S.P[s][l];
+      S.M[j][l] = v;
+    }
+  return logdet;
+}
+
+// gradient and Hessian of l at R (thread 0; after inverse_and_m)
+__device__ __noinline__ void grad_hess(GkShared& S, int p, double dn) {
+  for (int a = 0; a < p; ++a) {
+    const int j = S.pj[a], l = S.pl[a];
+    S.g[a] = -dn * S.P[j][l] + S.M[j][l];
+    for (int b = 0; b < p; ++b) {
+      const int s = S.pj[b], t = S.pl[b];
+      S.Hm[a][b] = dn * (S.P[j][s] * S.P[t][l] + S.P[j][t] * S.P[s][l]) -
+                   (S.P[j][s] * S.M[t][l] + S.P[j][t] * S.M[s][l] + S.M[j][s] * S.P[t][l] + S.M[j][t] * S.P[s][l]);
+    }
+  }
+}
+
+// the workgroup's four wave tiles summed into dst[i0 + i][j0 + j] (i, j < 16)
+// and, off the diagonal, its transpose
+__device__ __forceinline__ void store_tile(GkShared& S, d4 acc, double (*dst)[PPAD], int i0, int j0, bool sum_waves) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int c = lane & 15, r0 = lane >> 4;  // result e is row r0 + 4 e, column c
+  if (sum_waves) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S.tiles[w][r0 + 4 * e][c] = acc[e];
+    __syncthreads();
+    const int t = threadIdx.x;  // 256 threads, 256 entries
+    const int i = t >> 4, j = t & 15;
+    double v = 0.0;
+    for (int u = 0; u < GW; ++u) v += S.tiles[u][i][j];
+    dst[i0 + i][j0 + j] = v;
+    if (i0 != j0) dst[j0 + j][i0 + i] = v;
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      dst[i0 + r0 + 4 * e][j0 + c] = acc[e];
+      if (i0 != j0) dst[j0 + c][i0 + r0 + 4 * e] = acc[e];
+    }
+  }
+}
+
+// p x p contraction X' X / n over the subset's rows into dst: waves 0..2 take
+// the tiles (0,0), (0,1), (1,1) (only (0,0) when p <= 16)
+__device__ void contract(GkShared& S, const double* X, int ldx, int n, int p, double (*dst)[PPAD]) {
+  const int w = threadIdx.x / WAVE;
+  const int ntiles = p <= 16 ? 1 : 3;
+  if (w < ntiles) {
+    const int i0 = (w == 2) ? 16 : 0, j0 = (w == 0) ? 0 : 16;
+    const d4 acc = tile_gram(X, ldx, n, i0, j0, p, 0, 1);
+    store_tile(S, acc, dst, i0, j0, false);
+  }
+  __syncthreads();
+}
+
+template <int KD>
+__global__ void __launch_bounds__(GT) k_gaussk(GkParams P) {
+  constexpr int k = KD, p = KD * (KD - 1) / 2, ldx = p <= 16 ? 16 : 32;
+  __shared__ GkShared S;
+  const int sid = blockIdx.x, t = threadIdx.x;
+  const SubDesc sd = P.subs[sid];
+  const int n = sd.n;
+  const int64_t o = sd.begin;
+  const double dn = (double)n;
+  if (t < PMAX) {
+    int q = 0, jj = 0, ll = 1;
+    for (int j = 0; j < k; ++j)
+      for (int l = j + 1; l < k; ++l, ++q)
+        if (q == t) { jj = j; ll = l; }
+    S.pj[t] = jj;
+    S.pl[t] = ll;
+  }
+  if (t < 2 * KMAX) S.mm[t] = (t & 1) ? 0u : ~0u;
+  __syncthreads();
+
+  // 1. normal scores and each margin's range
+  const int64_t twon1 = 2 * (int64_t)n + 2;
+  double* Z = P.Z + o * k;
+  for (int64_t e = t; e < (int64_t)n * k; e += GT) {
+    const int i = (int)(e / k), j = (int)(e - (int64_t)i * k);
+    const uint32_t r = P.R[(int64_t)j * P.n_total + o + i];
+    Z[e] = qnorm_ppnd16((int64_t)r, twon1);
+    atomicMin(&S.mm[2 * j], r);
+    atomicMax(&S.mm[2 * j + 1], r);
+  }
+  __syncthreads();
+  bool degenerate = n < P.n_min || n < 2 || n <= k;
+  for (int j = 0; j < k; ++j) degenerate = degenerate || S.mm[2 * j] == S.mm[2 * j + 1];
+  if (degenerate) {  // workgroup-uniform
+    if (t < p) {
+      ResultOut r;
+      r.theta = NAN; r.var = NAN; r.loglik = NAN; r.score = NAN;
+      r.n = n; r.iters = 0; r.status = ST_DEGENERATE;
+      P.out[(int64_t)t * P.K + sid] = r;
+    }
+    return;
+  }
+
+  // 2. G on the matrix cores
+  {
+    const int w = t / WAVE;
+    const d4 acc = tile_gram(Z, k, n, 0, 0, k, w, GW);
+    store_tile(S, acc, S.Om, 0, 0, true);  // (Om as scratch)
+    if (t < KMAX * KMAX) {
+      const int j = t / KMAX, l = t % KMAX;
+      if (j < k && l < k) S.G[j][l] = S.Om[j][l];
+    }
+    __syncthreads();
+  }
+
+  // 3. Newton (thread 0)
+  if (t == 0) {
+    int status = ST_OK, it = 0;
+    {
+      double d[KMAX];
+      for (int j = 0; j < k; ++j) d[j] = sqrt(S.G[j][j]);
+      for (int q = 0; q < p; ++q) S.th[q] = S.G[S.pj[q]][S.pl[q]] / (d[S.pj[q]] * d[S.pl[q]]);
+    }
+    if (!corr_pd(S, S.th, k)) {
+      status = ST_BOUNDARY_BOX;
+    } else {
+      status = ST_NOCONV;
+      for (it = 1; it <= 100; ++it) {
+        corr_from(S, S.th, k);
+        inverse_and_m(S, k);
+        grad_hess(S, p, dn);
+        for (int a = 0; a < p; ++a)
+          for (int b = 0; b < p; ++b) S.Hm[a][b] = -S.Hm[a][b];
+        if (!chol(&S.Hm[0][0], p, PMAX)) break;  // NOCONV
+        for (int a = 0; a < p; ++a) S.st[a] = S.g[a];
+        chol_solve(&S.Hm[0][0], p, PMAX, S.st);
+        double lam = 1.0;
+        for (int h = 0; h < 30; ++h) {
+          for (int a = 0; a < p; ++a) S.cand[a] = S.th[a] + lam * S.st[a];
+          if (corr_pd(S, S.cand, k)) break;
+          lam *= 0.5;
+        }
+        double mstep = 0.0, mth = 0.0;
+        for (int a = 0; a < p; ++a) {
+          mstep = fmax(mstep, fabs(lam * S.st[a]));
+          mth = fmax(mth, fabs(S.th[a]));
+          S.cand[a] = S.th[a] + lam * S.st[a];
+        }
+        for (int a = 0; a < p; ++a) S.th[a] = S.cand[a];
+        if (mstep <= 1e-12 * (1.0 + mth)) {
+          status = ST_OK;
+          break;
+        }
+      }
+      if (it > 100) it = 100;
+    }
+    double ll = NAN;
+    if (status == ST_OK) {
+      corr_from(S, S.th, k);
+      const double logdet = inverse_and_m(S, k);
+      grad_hess(S, p, dn);
+      double tr = 0.0;
+      for (int j = 0; j < k; ++j)
+        for (int l = 0; l < k; ++l) tr += (S.P[j][l] - (j == l ? 1.0 : 0.0)) * S.G[l][j];
+      ll = -0.5 * dn * logdet - 0.5 * tr;
+    }
+    S.scal[0] = ll;
+    S.scal[1] = (double)status;
+    S.scal[2] = (double)it;
+  }
+  __syncthreads();
+  const int status = (int)S.scal[1];
+  if (status != ST_OK) {
+    if (t < p) {
+      ResultOut r;
+      r.theta = S.th[t]; r.var = NAN; r.loglik = NAN; r.score = NAN;
+      r.n = n; r.iters = (int)S.scal[2]; r.status = status;
+      P.out[(int64_t)t * P.K + sid] = r;
+    }
+    return;
+  }
+
+  // 4. scores into X, then J = X'X / n
+  double* X = P.X + o * ldx;
+  for (int i = t; i < n; i += GT) {
+    double z[KMAX], y[KMAX];
+    for (int j = 0; j < k; ++j) z[j] = Z[(int64_t)i * k + j];
+    for (int j = 0; j < k; ++j) {
+      double v = 0.0;
+      for (int l = 0; l < k; ++l) v += S.P[j][l] * z[l];
+      y[j] = v;
+    }
+    double* xi = X + (int64_t)i * ldx;
+    int q = 0;
+#pragma unroll
+    for (int j = 0; j < k; ++j)
+#pragma unroll
+      for (int l = j + 1; l < k; ++l, ++q) xi[q] = -S.P[j][l] + y[j] * y[l];
+#pragma unroll
+    for (int c = p; c < ldx; ++c) xi[c] = 0.0;
+  }
+  __syncthreads();
+  contract(S, X, ldx, n, p, S.J);
+
+  // 5. psi = s + sum_m W_m: per margin, bins by doubled rank, suffix sums
+  double* Bn = P.B + (2 * o + 2 * (int64_t)sid) * k;
+  const int64_t NB = twon1;  // bins 0 .. 2n + 1
+  const double inv_n = 1.0 / dn, inv_s2pi = 0.39894228040143267794;
+  for (int m = 0; m < k; ++m) {
+    for (int64_t e = t; e < NB * k; e += GT) Bn[e] = 0.0;
+    __syncthreads();
+    for (int i = t; i < n; i += GT) {
+      double z[KMAX];
+      for (int j = 0; j < k; ++j) z[j] = Z[(int64_t)i * k + j];
+      const double zm = z[m];
+      const double iphi = 1.0 / (inv_s2pi * exp(-0.5 * zm * zm));
+      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i];
+      for (int j = 0; j < k; ++j) {
+        double v = 0.0;
+        for (int l = 0; l < k; ++l) v += S.P[j][l] * z[l];
+        atomicAdd(&Bn[(int64_t)r * k + j], v * iphi);
+      }
+    }
+    __syncthreads();
+    // suffix sums over the bins: thread t takes bins [t C, (t + 1) C)
+    const int64_t C = (NB + GT - 1) / GT;
+    const int64_t b0 = t * C, b1 = min(b0 + C, NB);
+    double run[KMAX];
+    for (int j = 0; j < k; ++j) run[j] = 0.0;
+    for (int64_t b = b1 - 1; b >= b0; --b)
+      for (int j = 0; j < k; ++j) {
+        run[j] += Bn[b * k + j];
+        Bn[b * k + j] = run[j];
+      }
+    for (int j = 0; j < k; ++j) S.tot[t][j] = run[j];
+    __syncthreads();
+    double carry[KMAX];
+    for (int j = 0; j < k; ++j) carry[j] = 0.0;
+    for (int u = t + 1; u < GT; ++u)
+      for (int j = 0; j < k; ++j) carry[j] += S.tot[u][j];
+    for (int64_t b = b0; b < b1; ++b)
+      for (int j = 0; j < k; ++j) Bn[b * k + j] += carry[j];
+    __syncthreads();
+    for (int i = t; i < n; i += GT) {
+      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i];
+      double A[KMAX];
+      for (int j = 0; j < k; ++j) A[j] = Bn[(int64_t)r * k + j] * inv_n;
+      double* xi = X + (int64_t)i * ldx;
+      int q = 0;
+#pragma unroll
+      for (int j = 0; j < k; ++j)
+#pragma unroll
+        for (int l = j + 1; l < k; ++l, ++q) xi[q] += S.P[j][m] * A[l] + A[j] * S.P[l][m];
+    }
+    __syncthreads();
+  }
+
+  // 6. Omega = X'X / n - mean mean'
+  contract(S, X, ldx, n, p, S.Om);
+  {
+    // column sums of psi: per thread, per wave (shuffles), across waves (LDS)
+    for (int q = 0; q < p; ++q) {
+      double s = 0.0;
+      for (int i = t; i < n; i += GT) s += X[(int64_t)i * ldx + q];
+      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, WAVE);
+      if ((t & (WAVE - 1)) == 0) S.tiles[t / WAVE][q >> 4][q & 15] = s;
+    }
+    __syncthreads();
+    if (t < p) {
+      double s = 0.0;
+      for (int u = 0; u < GW; ++u) s += S.tiles[u][t >> 4][t & 15];
+      S.mu[t] = s * inv_n;
+    }
+    __syncthreads();
+  }
+
+  // 7. V = J^-1 Omega J^-1 / n (thread 0 inverts J; thread q forms V_qq)
+  if (t == 0) {
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) {
+        S.J[a][b] *= inv_n;
+        S.Om[a][b] = S.Om[a][b] * inv_n - S.mu[a] * S.mu[b];
+      }
+    // J^-1 into Hm (Cholesky of J in tiles-free scratch: reuse Hm rows)
+    for (int a = 0; a < p; ++a)
+      for (int b = 0; b < p; ++b) S.Hm[a][b] = S.J[a][b];
+    const bool ok = chol(&S.Hm[0][0], p, PMAX);
+    for (int c = 0; c < p; ++c) {
+      for (int a = 0; a < p; ++a) S.e[a] = (a == c) ? 1.0 : 0.0;
+      if (ok) chol_solve(&S.Hm[0][0], p, PMAX, S.e);
+      for (int a = 0; a < p; ++a) S.J[a][c] = ok ? S.e[a] : NAN;
+    }
+  }
+  __syncthreads();
+  if (t < p) {
+    const int q = t;
+    double v = 0.0;
+    for (int a = 0; a < p; ++a) {
+      double w = 0.0;
+      for (int b = 0; b < p; ++b) w += S.Om[a][b] * S.J[b][q];
+      v += S.J[a][q] * w;
+    }
+    v *= inv_n;
+    ResultOut r;
+    r.theta = S.th[q];
+    r.var = v;
+    r.loglik = S.scal[0];
+    r.score = S.g[q];
+    r.n = n;
+    r.iters = (int)S.scal[2];
+    r.status = (v > 0.0 && isfinite(v)) ? ST_OK : ST_BADVAR;
+    P.out[(int64_t)q * P.K + sid] = r;
+  }
+}
+
+}  // namespace
+
+int gaussk_ldx(int k) { return k * (k - 1) / 2 <= 16 ? 16 : 32; }
+
+hipError_t launch_gaussk(const uint32_t* R, int64_t n_total, int k, const SubDesc* subs, int64_t K, int64_t n_min,
+                         double* Z, double* X, double* B, ResultOut* out, hipStream_t s) {
+  GkParams p = {};
+  p.R = R; p.n_total = n_total; p.k = k; p.p = k * (k - 1) / 2; p.ldx = gaussk_ldx(k);
+  p.subs = subs; p.n_min = n_min; p.Z = Z; p.X = X; p.B = B; p.out = out; p.K = K;
+  if (K <= 0) return hipSuccess;
+  const dim3 grid((unsigned)K), block(GT);
+  switch (k) {
+    case 2: hipLaunchKernelGGL(k_gaussk<2>, grid, block, 0, s, p); break;
+    case 3: hipLaunchKernelGGL(k_gaussk<3>, grid, block, 0, s, p); break;
+    case 4: hipLaunchKernelGGL(k_gaussk<4>, grid, block, 0, s, p); break;
+    case 5: hipLaunchKernelGGL(k_gaussk<5>, grid, block, 0, s, p); break;
+    case 6: hipLaunchKernelGGL(k_gaussk<6>, grid, block, 0, s, p); break;
+    case 7: hipLaunchKernelGGL(k_gaussk<7>, grid, block, 0, s, p); break;
+    case 8: hipLaunchKernelGGL(k_gaussk<8>, grid, block, 0, s, p); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cpc

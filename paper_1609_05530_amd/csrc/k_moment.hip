@@ -20,6 +20,21 @@
 //     sigma^2 = var(psi) / (n rho_S'(theta)^2). dJ/du = 12 (v - 1/2) is a
 //     multiple of the integer r2 - (n+1)/2, so the suffix sums are exact
 //     64-bit integer sums over a histogram indexed by the doubled rank.
+//
+// The inversion of Kendall's tau, one workgroup per subset of up to 2^20
+// rows: tau hat = sum_i S_i / (n (n - 1)) with
+// S_i = sum_l sign(a_i - a_l) sign(b_i - b_l) (a, b the doubled ranks), and
+// var(tau hat) = 4 var(S_i / (n - 1)) / n (a U-statistic of degree two).
+// The S_i come from two merge sorts through the workspace: the rows sorted by
+// (a, b) give the sequence B_p of b values; a second merge sort of B counts,
+// for every position p, sum_{q<p} sign(B_p - B_q) (at each level a right-run
+// element adds (#left < B_p) - (#left > B_p), two binary searches in the left
+// run). Then with the runs of equal a and of equal (a, b) around p (binary
+// searches in the first sorted order), S = 2 (count - #{same a, b < b_p}) +
+// (#{same a, b < b_p} - #{same a, b > b_p}) - (R2 - n - 1), where
+// R2 - n - 1 = #{b_l < b_i} - #{b_l > b_i}. All counts are exact integers.
+// theta: Gaussian sin(pi tau / 2), Gumbel 1 / (1 - tau) in closed form;
+// Frank tau = 1 - 4 (1 - D1(theta)) / theta by the workgroup Newton.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -85,7 +100,107 @@ struct MomParams {
   long long* H2;
   int64_t base;   // index of the launch's first subset
   ResultOut* out;
+  // Kendall: per row of the subset (at its begin), two 64-bit sort buffers
+  // and the 32-bit sign counts
+  unsigned long long* W0;
+  unsigned long long* W1;
+  int* C;
 };
+
+enum { KIND_SPEARMAN = 0, KIND_KENDALL = 1 };
+
+// rho_S (KIND_SPEARMAN) or tau (KIND_KENDALL) at th and its theta-derivative
+// from the workgroup sums v of rho_terms (valid in thread 0).
+template <int FAM, int KIND>
+__device__ __forceinline__ void moment_value(double th, const double (&v)[4], double& val, double& der) {
+  if constexpr (FAM == FAM_GUMBEL) {  // (Spearman only: Kendall's Gumbel is closed form)
+    val = v[0] - 3.0;
+    der = v[1];
+  } else {
+    const double A = fabs(th);
+    if (A < 1e-2) {
+      const double t2 = th * th;
+      if constexpr (KIND == KIND_SPEARMAN) {
+        val = th * (1.0 / 6.0 - t2 / 450.0 + t2 * t2 / 23520.0);
+        der = 1.0 / 6.0 - t2 / 150.0 + t2 * t2 / 4704.0;
+      } else {
+        val = th * (1.0 / 9.0 - t2 / 900.0 + t2 * t2 / 52920.0);
+        der = 1.0 / 9.0 - t2 / 300.0 + t2 * t2 / 10584.0;
+      }
+    } else {
+      const double D1 = v[2] / A, e = 1.0 / expm1(A);
+      const double dD1 = -D1 / A + e;
+      double ra;
+      if constexpr (KIND == KIND_SPEARMAN) {
+        const double D2 = 2.0 * v[3] / (A * A), dD2 = -2.0 * D2 / A + 2.0 * e;
+        ra = 1.0 - 12.0 * (D1 - D2) / A;
+        der = 12.0 * (D1 - D2) / (A * A) - 12.0 * (dD1 - dD2) / A;  // even in theta
+      } else {
+        ra = 1.0 - 4.0 * (1.0 - D1) / A;
+        der = 4.0 * (1.0 - D1) / (A * A) + 4.0 * dD1 / A;  // even in theta
+      }
+      val = th < 0.0 ? -ra : ra;  // odd in theta
+    }
+  }
+}
+
+// theta in [BLO, BHI] with m(theta) = target (m = rho_S or tau, increasing)
+// by safeguarded Newton from th: the workgroup evaluates m and its slope at
+// each iterate, thread 0 takes the step and broadcasts it with the stopping
+// decision through bc[0..3] (so every thread leaves the loop together). On
+// return (every thread): th, slope at the last evaluated iterate, status
+// (OK or BOUNDARY_*), it (passes; > 100 means no convergence); fit = m at the
+// last iterate (thread 0).
+template <int FAM, int KIND, int W>
+__device__ void newton_invert(double target, double& th, double& slope, double& fit, int& it, int& status,
+                              double* red, double* bc) {
+  constexpr double BLO = FAM == FAM_FRANK ? -200.0 : 1.0, BHI = FAM == FAM_FRANK ? 200.0 : 100.0;
+  const int t = threadIdx.x;
+  double lo = BLO, hi = BHI;  // the bracket (thread 0's copy is the one used)
+  if (!(th > BLO && th < BHI)) th = 0.5 * (BLO + BHI);
+  for (it = 1; it <= 100; ++it) {
+    double f0, f1, f2, f3;
+    rho_terms<FAM>(th, f0, f1, f2, f3);
+    double v[4] = {f0, f1, f2, f3};
+    block_sum<W, 4>(v, red);
+    if (t == 0) {
+      double val, der;
+      moment_value<FAM, KIND>(th, v, val, der);
+      const double g = val - target;  // increasing in theta
+      int st = ST_OK;
+      double done = 0.0, tn = th;
+      if (g != 0.0) {  // (an exact root stops at th itself)
+        if (g < 0.0) lo = th; else hi = th;
+        tn = (der > 0.0) ? th - g / der : NAN;
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+      }
+      if (g == 0.0 || fabs(tn - th) <= 1e-12 * (1.0 + fabs(th))) {
+        done = 1.0;
+      } else if (tn - BLO <= 1e-9 * (1.0 + fabs(BLO))) {
+        done = 1.0;
+        tn = BLO;
+        st = FAM == FAM_GUMBEL ? ST_BOUNDARY_NATURAL : ST_BOUNDARY_BOX;
+      } else if (BHI - tn <= 1e-9 * (1.0 + fabs(BHI))) {
+        done = 1.0;
+        tn = BHI;
+        st = ST_BOUNDARY_BOX;
+      }
+      bc[1] = tn;
+      bc[2] = done;
+      bc[3] = der;
+      bc[0] = (double)st;
+      fit = val;
+    }
+    __syncthreads();
+    th = bc[1];
+    const bool done = bc[2] != 0.0;
+    slope = bc[3];
+    status = (int)bc[0];
+    __syncthreads();  // bc is written again in the next iteration
+    if (done) break;
+  }
+  if (it > 100) status = ST_NOCONV;
+}
 
 template <int FAM>
 __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
@@ -143,12 +258,6 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
     slope = 3.0 / (3.14159265358979323846 * sqrt(1.0 - 0.25 * th * th));
     fit = 6.0 / 3.14159265358979323846 * asin(0.5 * th);
   } else {
-    // safeguarded Newton inside the family's box; the workgroup evaluates
-    // rho_S and its slope at each iterate, thread 0 takes the step and
-    // broadcasts it with the stopping decision (so every thread leaves the
-    // loop together)
-    constexpr double BLO = FAM == FAM_FRANK ? -200.0 : 1.0, BHI = FAM == FAM_FRANK ? 200.0 : 100.0;
-    double lo = BLO, hi = BHI;  // the bracket (thread 0's copy is the one used)
     if (FAM == FAM_GUMBEL && rho <= 0.0) {
       status = ST_BOUNDARY_NATURAL;
       th = 1.0;
@@ -157,66 +266,7 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
                             : fmin(1.0 / (1.0 - 2.0 / 3.14159265358979323846 *
                                                    asin(fmin(2.0 * sin(3.14159265358979323846 * rho / 6.0), 1.0))),
                                    80.0);
-      if (!(th > BLO && th < BHI)) th = 0.5 * (BLO + BHI);
-      for (it = 1; it <= 100; ++it) {
-        double f0, f1, f2, f3;
-        rho_terms<FAM>(th, f0, f1, f2, f3);
-        double v[4] = {f0, f1, f2, f3};
-        block_sum<W, 4>(v, red);
-        if (t == 0) {
-          double val, der;
-          if constexpr (FAM == FAM_GUMBEL) {
-            val = v[0] - 3.0;
-            der = v[1];
-          } else {
-            const double A = fabs(th);
-            if (A < 1e-2) {
-              const double t2 = th * th;
-              val = th * (1.0 / 6.0 - t2 / 450.0 + t2 * t2 / 23520.0);
-              der = 1.0 / 6.0 - t2 / 150.0 + t2 * t2 / 4704.0;
-            } else {
-              const double D1 = v[2] / A, D2 = 2.0 * v[3] / (A * A);
-              const double e = 1.0 / expm1(A);
-              const double dD1 = -D1 / A + e, dD2 = -2.0 * D2 / A + 2.0 * e;
-              const double ra = 1.0 - 12.0 * (D1 - D2) / A;
-              val = th < 0.0 ? -ra : ra;
-              der = 12.0 * (D1 - D2) / (A * A) - 12.0 * (dD1 - dD2) / A;  // even in theta
-            }
-          }
-          const double g = val - rho;  // increasing in theta
-          int st = ST_OK;
-          double done = 0.0, tn = th;
-          if (g != 0.0) {  // (an exact root stops at th itself)
-            if (g < 0.0) lo = th; else hi = th;
-            tn = (der > 0.0) ? th - g / der : NAN;
-            if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-          }
-          if (g == 0.0 || fabs(tn - th) <= 1e-12 * (1.0 + fabs(th))) {
-            done = 1.0;
-          } else if (tn - BLO <= 1e-9 * (1.0 + fabs(BLO))) {
-            done = 1.0;
-            tn = BLO;
-            st = FAM == FAM_GUMBEL ? ST_BOUNDARY_NATURAL : ST_BOUNDARY_BOX;
-          } else if (BHI - tn <= 1e-9 * (1.0 + fabs(BHI))) {
-            done = 1.0;
-            tn = BHI;
-            st = ST_BOUNDARY_BOX;
-          }
-          bc[1] = tn;
-          bc[2] = done;
-          bc[3] = der;
-          bc[0] = (double)st;
-          fit = val;
-        }
-        __syncthreads();
-        th = bc[1];
-        const bool done = bc[2] != 0.0;
-        slope = bc[3];
-        status = (int)bc[0];
-        __syncthreads();  // bc is written again in the next iteration
-        if (done) break;
-      }
-      if (it > 100) status = ST_NOCONV;
+      newton_invert<FAM, KIND_SPEARMAN, W>(rho, th, slope, fit, it, status, red, bc);
     }
     if (status == ST_BOUNDARY_NATURAL) {  // the variance needs the slope at theta = 1
       double f0, f1, f2, f3;
@@ -294,11 +344,201 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
   }
 }
 
+// Number of entries of a[0 .. len) below x (a sorted ascending).
+__device__ __forceinline__ int lower_count(const unsigned long long* a, int len, unsigned long long x) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One bottom-up merge level (runs of L entries, L a power of two) of distinct
+// 64-bit words from src into dst. COUNT: the words are (value << 32 |
+// position) and every right-run word adds 2 ((#left < value) - (#left >
+// value)) to C[position] (the left run holds exactly the positions before the
+// right run's).
+template <bool COUNT>
+__device__ __forceinline__ void merge_level(const unsigned long long* src, unsigned long long* dst, int n, int L,
+                                            int lg, int* C) {
+  for (int p = threadIdx.x; p < n; p += MT) {
+    const int r = p >> lg, start = r << lg;
+    const unsigned long long w = src[p];
+    if (r & 1) {
+      const int ls = start - L;
+      const int le = lower_count(src + ls, L, w);  // left words below w: values <= this one's
+      dst[ls + (p - start) + le] = w;
+      if constexpr (COUNT) {
+        const int lt = lower_count(src + ls, le, (w >> 32) << 32);  // values below this one's
+        C[(uint32_t)w] += 2 * (lt - (L - le));
+      }
+    } else {
+      const int rs = start + L;
+      const int len = rs < n ? min(L, n - rs) : 0;
+      dst[p + lower_count(src + rs, len, w)] = w;
+    }
+  }
+}
+
+template <int FAM>
+__global__ void __launch_bounds__(MT) k_kendall(MomParams P) {
+  constexpr int W = MT / WAVE;
+  __shared__ double red[W * 4];
+  __shared__ long long redl[W];
+  __shared__ unsigned int mm[4];
+  __shared__ double bc[4];
+  const int sid = blockIdx.x, t = threadIdx.x;
+  const SubDesc sd = P.subs[sid];
+  const int n = sd.n;
+  const int64_t o = sd.begin;
+  ResultOut r;
+  r.theta = NAN; r.var = NAN; r.loglik = NAN; r.score = NAN;
+  r.n = n; r.iters = 0; r.status = ST_OK;
+  if (n < P.n_min || n < 2) {
+    if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; }
+    return;
+  }
+  const uint32_t* R1 = P.R1 + o;
+  const uint32_t* R2 = P.R2 + o;
+  unsigned long long* w0 = P.W0 + o;
+  unsigned long long* w1 = P.W1 + o;
+  int* C = P.C + o;
+  // index bits, and the multiplier of a in the (a, b) key (b <= 2n < M)
+  const int IB = 32 - __clz(n - 1);
+  const unsigned long long M = 2ull * (unsigned long long)n + 2ull;
+
+  // words (a M + b) << IB | row, and whether a margin has a single value
+  if (t == 0) { mm[0] = ~0u; mm[1] = 0u; mm[2] = ~0u; mm[3] = 0u; }
+  __syncthreads();
+  uint32_t a0 = ~0u, a1 = 0u, b0 = ~0u, b1 = 0u;
+  for (int i = t; i < n; i += MT) {
+    const uint32_t a = R1[i], b = R2[i];
+    w0[i] = (((unsigned long long)a * M + b) << IB) | (unsigned long long)i;
+    a0 = min(a0, a); a1 = max(a1, a); b0 = min(b0, b); b1 = max(b1, b);
+  }
+  atomicMin(&mm[0], a0); atomicMax(&mm[1], a1); atomicMin(&mm[2], b0); atomicMax(&mm[3], b1);
+  __syncthreads();
+  if (mm[0] == mm[1] || mm[2] == mm[3]) {  // workgroup-uniform
+    if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; }
+    return;
+  }
+
+  // 1. the rows in (a, b, row) order
+  unsigned long long* src = w0;
+  unsigned long long* dst = w1;
+  int lg = 0;
+  for (int L = 1; L < n; L <<= 1, ++lg) {
+    merge_level<false>(src, dst, n, L, lg, nullptr);
+    __syncthreads();
+    unsigned long long* x = src; src = dst; dst = x;
+  }
+  // 2. per position p: the runs of equal a and of equal (a, b) around it give
+  //    #{same a, b < b_p} and #{same a, b > b_p}; C[p] starts at the terms of
+  //    S that do not need the second sort; dst gets (b << 32 | p)
+  const unsigned long long imask = (1ull << IB) - 1ull;
+  for (int p = t; p < n; p += MT) {
+    const unsigned long long w = src[p];
+    const int i = (int)(w & imask);
+    const unsigned long long a = R1[i], b = R2[i], key = w >> IB;
+    const int A0 = lower_count(src, n, (a * M) << IB), A1 = lower_count(src, n, ((a + 1ull) * M) << IB);
+    const int J0 = lower_count(src, n, key << IB), J1 = lower_count(src, n, (key + 1ull) << IB);
+    C[p] = (n + 1) - (int)b - (J0 - A0) - (A1 - J1);
+    dst[p] = (b << 32) | (unsigned long long)p;
+  }
+  __syncthreads();
+  // 3. the sign counts: merge sort of (b << 32 | p)
+  src = dst;
+  dst = (src == w0) ? w1 : w0;
+  lg = 0;
+  for (int L = 1; L < n; L <<= 1, ++lg) {
+    merge_level<true>(src, dst, n, L, lg, C);
+    __syncthreads();
+    unsigned long long* x = src; src = dst; dst = x;
+  }
+  // 4. sum S and S^2 (exact)
+  long long s1 = 0, s2 = 0;
+  for (int p = t; p < n; p += MT) {
+    const long long v = C[p];
+    s1 += v;
+    s2 += v * v;
+  }
+  const long long S1 = block_sum_ll<W>(s1, redl);
+  const long long S2 = block_sum_ll<W>(s2, redl);
+  const double dn = (double)n, dn1 = (double)(n - 1);
+  double tau = 0.0, zeta = 0.0;
+  if (t == 0) {
+    tau = (double)S1 / (dn * dn1);
+    zeta = (double)S2 / (dn * dn1 * dn1) - tau * tau;
+    bc[0] = tau;
+  }
+  __syncthreads();
+  tau = bc[0];
+  __syncthreads();
+
+  // theta with tau(theta) = tau
+  double th = 0.0, slope = 0.0, fit = 0.0;
+  int it = 0, status = ST_OK;
+  constexpr double PI = 3.14159265358979323846;
+  if constexpr (FAM == FAM_GAUSSIAN) {
+    th = sin(0.5 * PI * tau);
+    const double edge = 1.0 - 1e-9;
+    if (th <= -edge) { status = ST_BOUNDARY_BOX; th = -edge; }
+    if (th >= edge) { status = ST_BOUNDARY_BOX; th = edge; }
+    slope = 2.0 / (PI * sqrt(1.0 - th * th));
+    fit = 2.0 / PI * asin(th);
+  } else if constexpr (FAM == FAM_GUMBEL) {
+    if (tau <= 0.0) {
+      status = ST_BOUNDARY_NATURAL;
+      th = 1.0;
+    } else if (tau >= 1.0 - 1.0 / 100.0) {
+      status = ST_BOUNDARY_BOX;
+      th = 100.0;
+    } else {
+      th = 1.0 / (1.0 - tau);
+    }
+    slope = 1.0 / (th * th);
+    fit = 1.0 - 1.0 / th;
+  } else {
+    th = fmin(fmax(4.0 * tau / (1.0 - fabs(tau)) + 5.0 * tau, -150.0), 150.0);
+    newton_invert<FAM, KIND_KENDALL, W>(tau, th, slope, fit, it, status, red, bc);
+  }
+  if (t == 0) {
+    r.theta = th;
+    r.loglik = tau;
+    r.score = fit - tau;
+    r.iters = it;
+    r.status = status;
+    if (status == ST_OK || status == ST_BOUNDARY_NATURAL) {
+      const double var = 4.0 * zeta / (dn * slope * slope);
+      r.var = var;
+      if (!(var > 0.0 && isfinite(var))) r.status = ST_BADVAR;
+    }
+    P.out[sid] = r;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_kendall(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
+                          int64_t K, int64_t n_min, unsigned long long* W0, unsigned long long* W1, int* C,
+                          ResultOut* out, hipStream_t s) {
+  MomParams p = {};
+  p.R1 = R1; p.R2 = R2; p.subs = subs + base; p.n_min = n_min; p.base = base;
+  p.out = out + base;
+  p.W0 = W0; p.W1 = W1; p.C = C;
+  if (K <= 0) return hipSuccess;
+  switch (fam) {
+    case FAM_GAUSSIAN: hipLaunchKernelGGL(k_kendall<FAM_GAUSSIAN>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+    case FAM_FRANK: hipLaunchKernelGGL(k_kendall<FAM_FRANK>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+    default: hipLaunchKernelGGL(k_kendall<FAM_GUMBEL>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
                            int64_t K, int64_t n_min, long long* H1, long long* H2, ResultOut* out, hipStream_t s) {
-  MomParams p;
+  MomParams p = {};
   p.R1 = R1; p.R2 = R2; p.subs = subs + base; p.n_min = n_min; p.H1 = H1; p.H2 = H2; p.base = base;
   p.out = out + base;
   if (K <= 0) return hipSuccess;

@@ -168,5 +168,17 @@ hipError_t launch_replicate_summary(int64_t S, const CombinedOut* comb, const Co
 // subsets base .. base + K - 1 of `subs`, results to out[base ..].
 hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
                            int64_t K, int64_t n_min, long long* H1, long long* H2, ResultOut* out, hipStream_t s);
+// The k-dimensional Gaussian copula of eq. (7) per subset (k_gaussk.hip),
+// 2 <= k <= 8: R holds k columns of n_total doubled ranks; Z (8 k B per
+// row), X (8 gaussk_ldx(k) B per row) and B ((2 n + 2) k doubles per subset
+// from 2 (begin + m) k) are scratch; out is parameter-major (q K + m).
+int gaussk_ldx(int k);
+hipError_t launch_gaussk(const uint32_t* R, int64_t n_total, int k, const SubDesc* subs, int64_t K, int64_t n_min,
+                         double* Z, double* X, double* B, ResultOut* out, hipStream_t s);
+// The inversion of Kendall's tau per subset (k_moment.hip): subsets of at
+// most 2^20 rows, whose rows own W0, W1 (8 B) and C (4 B) at their begin.
+hipError_t launch_kendall(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
+                          int64_t K, int64_t n_min, unsigned long long* W0, unsigned long long* W1, int* C,
+                          ResultOut* out, hipStream_t s);
 
 }  // namespace cpc

@@ -1,0 +1,113 @@
+"""GPU parity of the Kendall-inversion estimator (cpc_kendall_fit) against
+the FP64 oracle on the same data: the GPU ranks each subset (cpc_rank), the
+oracle ranks it itself (the two rankings are bit-identical, tested
+elsewhere). Tolerances: tau hat 1e-15 (both divide the same exact integer
+sum once), theta 1e-9 relative to max(|theta|, 0.1) (Gaussian and Gumbel
+are closed forms; Frank is solved by Newton on the GPU and by regula falsi
+in the oracle, both to ~1e-12), variance 1e-8 relative (the GPU forms
+var(S_i / (n - 1)) from exact sums of S_i and S_i^2, the oracle from the
+deviations; Frank's slope by quadrature against the oracle's Debye
+function), combined 1e-8."""
+import numpy as np
+import pytest
+import torch
+
+import oracle.oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# sizes: tiny, odd, powers of two and their neighbours, and larger than the
+# rank kernel's workgroup path (16384)
+SIZES = [3000, 20000, 700, 4096, 40, 2, 4097, 2100, 1, 16385]
+CASES = [("gaussian", 0.5), ("gaussian", -0.8), ("frank", 5.0), ("frank", -8.0), ("frank", 0.3),
+         ("gumbel", 2.0), ("gumbel", 1.02), ("gumbel", 8.0)]
+
+
+def compare(g, sub, comb, label):
+    st = sub["status"]
+    assert np.array_equal(g["status"], st), (label, g["status"], st)
+    fitted = (st == 0) | (st == 1) | (st == 2)
+    dth = np.abs(g["theta"][fitted] - sub["theta"][fitted]) / np.maximum(np.abs(sub["theta"][fitted]), 0.1)
+    dtau = np.abs(g["loglik"][fitted] - sub["loglik"][fitted])
+    use = (st == 0) | (st == 1)
+    dvar = np.abs(g["var"][use] / sub["var"][use] - 1.0)
+    dc = np.abs(g["combined_theta"] - comb["theta"]) / np.maximum(np.abs(comb["theta"]), 0.1)
+    print(f"[kendall] {label}: max dtheta {dth.max(initial=0):.2e} dtau {dtau.max(initial=0):.2e} "
+          f"dvar {dvar.max(initial=0):.2e} dcomb {np.nanmax(dc, initial=0):.2e}", flush=True)
+    assert dtau.max(initial=0) <= 1e-15, label
+    assert dth.max(initial=0) <= 1e-9, label
+    assert dvar.max(initial=0) <= 1e-8, label
+    assert np.array_equal(g["n_used"], comb["n_used"]), label
+    good = comb["status"] == 0
+    assert np.all(dc[good] <= 1e-8), label
+
+
+def gpu_fit(x, y, off, fams, gofs=None):
+    import paper_1609_05530_amd as m
+    dt = torch.float64
+    R1, R2 = m.rank(torch.as_tensor(x, dtype=dt).cuda(), torch.as_tensor(y, dtype=dt).cuda(), off)
+    res = m.kendall_fit(R1, R2, off, fams, gofs)
+    torch.cuda.synchronize()
+    return {k: getattr(res, k).cpu().numpy() for k in
+            ("theta", "var", "loglik", "status", "combined_theta", "n_used", "combined_status")}
+
+
+def oracle_fit(x, y, off, fams, gofs=None):
+    R1 = np.concatenate([O.ranks(x[off[m]:off[m + 1]]) for m in range(len(off) - 1)])
+    R2 = np.concatenate([O.ranks(y[off[m]:off[m + 1]]) for m in range(len(off) - 1)])
+    return O.kendall_fit_ranks(R1, R2, off, fams, gofs)
+
+
+@pytest.mark.parametrize("fam,th", CASES)
+def test_kendall_fit_parity(fam, th):
+    n = int(sum(SIZES))
+    x, y = synth.copula_pairs(fam, th, n, 1800 + int(abs(th) * 10))
+    off = synth.offsets_from_sizes(np.array(SIZES))
+    print(f"[kendall] {fam} {th}: n={n} K={len(SIZES)}", flush=True)
+    sub, comb = oracle_fit(x, y, off, fam)
+    compare(gpu_fit(x, y, off, fam), sub, comb, f"{fam} {th}")
+
+
+def test_kendall_groups_ties_and_statuses():
+    """Several groups of different families in one call, tied margins (the
+    FP32 rounding of one margin and a heavily tied one), a constant margin
+    (DEGENERATE), negative dependence under Gumbel (theta = 1,
+    BOUNDARY_NATURAL) and a concordant subset (the box edge). (A subset with
+    y = -x exactly has tau hat = -1, every S_i equal and a zero variance:
+    BADVAR on both sides.)"""
+    parts = [("frank", 4.0), ("gumbel", 2.5), ("gaussian", 0.6), ("gumbel", 3.0)]
+    xs, ys, offs, gofs = [], [], [0], [0]
+    rng = np.random.default_rng(6)
+    base = 0
+    for k, (fam, th) in enumerate(parts):
+        sizes = rng.integers(500, 6000, 5)
+        x, y = synth.copula_pairs(fam, th, int(sizes.sum()), 1900 + k)
+        o = synth.offsets_from_sizes(sizes)
+        if k == 0:
+            x[o[1]:o[3]] = np.round(x[o[1]:o[3]] * 4) / 4  # heavy ties
+            y[o[2]:o[4]] = y[o[2]:o[4]].astype(np.float32)
+        if k == 1:
+            x[o[2]:o[3]] = 1.5                             # a constant margin
+        if k == 3:
+            y[o[0]:o[1]] = -x[o[0]:o[1]] + rng.standard_normal(o[1] - o[0])  # negative dependence
+            y[o[1]:o[2]] = x[o[1]:o[2]]                     # all pairs concordant
+        xs.append(x); ys.append(y)
+        offs.extend((o[1:] + base).tolist()); base += int(o[-1])
+        gofs.append(gofs[-1] + len(sizes))
+    x = np.concatenate(xs); y = np.concatenate(ys)
+    offs = np.array(offs); gofs = np.array(gofs)
+    fams = [p[0] for p in parts]
+    print(f"[kendall] groups: n={len(x)} K={len(offs) - 1}", flush=True)
+    sub, comb = oracle_fit(x, y, offs, fams, gofs)
+    assert 3 in sub["status"] and 1 in sub["status"] and 2 in sub["status"]
+    compare(gpu_fit(x, y, offs, fams, gofs), sub, comb, "groups, ties, statuses")
+
+
+def test_kendall_rejects_subsets_beyond_its_limit():
+    import paper_1609_05530_amd as m
+    n = (1 << 20) + 1
+    R = torch.arange(2, 2 * n + 2, 2, dtype=torch.int32, device="cuda")
+    with pytest.raises(m.CpcError) as e:
+        m.kendall_fit(R, R, np.array([0, n]), "frank")
+    assert e.value.code == -9  # CPC_E_UNSUPPORTED
