@@ -337,8 +337,9 @@ size_t cpc_gaussk_workspace_bytes(int64_t n, int32_t k, int64_t K, int64_t G);
  * margin of one value; BOUNDARY_BOX when the normalised Gram matrix is not
  * positive definite; NOCONV; BADVAR). comb (device, p G entries, entry
  * q G + g): eq. (15) per parameter over the OK subsets of group g. Of opt
- * only n_min is used. workspace: device, at least
- * cpc_gaussk_workspace_bytes(n, k, K, G). */
+ * only n_min is used. workspace: ordinary (coarse-grained) device memory as
+ * hipMalloc returns it (its rank bins take hardware FP64 atomic adds), at
+ * least cpc_gaussk_workspace_bytes(n, k, K, G). */
 int cpc_gaussk_fit(cpc_handle_t h, const uint32_t* R, int64_t n, int32_t k, const int64_t* offsets, int64_t K,
                    const int64_t* group_offsets, int64_t G, const cpc_options_t* opt, void* workspace,
                    size_t ws_bytes, cpc_subset_result_t* out, cpc_combined_t* comb, void* stream);

@@ -1189,7 +1189,12 @@ int moment_fit(bool kendall, cpc_handle_t h, const uint32_t* R1, const uint32_t*
         HIP_OK(launch_kendall(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, W0, W1, C,
                               (ResultOut*)out, s));
       else
-        HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, H1, H2, (ResultOut*)out, s));
+      {
+        int64_t n_max = 0;
+        for (int64_t m = m0; m < m1; ++m) n_max = std::max<int64_t>(n_max, offsets[m + 1] - offsets[m]);
+        HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, n_max, H1, H2,
+                               (ResultOut*)out, s));
+      }
     }
     g = h2;
   }

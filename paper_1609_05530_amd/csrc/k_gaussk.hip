@@ -66,17 +66,21 @@ struct GkParams {
 // on gfx950).
 __device__ __forceinline__ d4 tile_gram(const double* A, int lda, int n, int i0, int j0, int ncol, int first,
                                          int step) {
+  constexpr int U = 8;  // row blocks whose loads are in flight together
   const int lane = threadIdx.x & (WAVE - 1);
   const int c = lane & 15, rr = lane >> 4;
+  const bool ci = i0 + c < ncol, cj = j0 + c < ncol;
   d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int r0 = 4 * first; r0 < n; r0 += 4 * step) {
-    const int r = r0 + rr;
-    double a = 0.0, b = 0.0;
-    if (r < n) {
-      if (i0 + c < ncol) a = A[(int64_t)r * lda + i0 + c];
-      if (j0 + c < ncol) b = A[(int64_t)r * lda + j0 + c];
+  for (int r0 = 4 * first; r0 < n; r0 += 4 * step * U) {
+    double a[U], b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + 4 * step * u + rr;
+      a[u] = (r < n && ci) ? A[(int64_t)r * lda + i0 + c] : 0.0;
+      b[u] = (r < n && cj) ? A[(int64_t)r * lda + j0 + c] : 0.0;
     }
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
   }
   return acc;
 }
@@ -215,21 +219,21 @@ __device__ __forceinline__ void store_tile(GkShared& S, d4 acc, double (*dst)[PP
   }
 }
 
-// p x p contraction X' X / n over the subset's rows into dst: waves 0..2 take
-// the tiles (0,0), (0,1), (1,1) (only (0,0) when p <= 16)
+// p x p contraction X' X over the subset's rows into dst: each 16 x 16 tile
+// ((0,0); with p > 16 also (0,1) and (1,1)) by all four waves, each taking
+// every fourth block of rows, summed through LDS
 __device__ void contract(GkShared& S, const double* X, int ldx, int n, int p, double (*dst)[PPAD]) {
   const int w = threadIdx.x / WAVE;
   const int ntiles = p <= 16 ? 1 : 3;
-  if (w < ntiles) {
-    const int i0 = (w == 2) ? 16 : 0, j0 = (w == 0) ? 0 : 16;
-    const d4 acc = tile_gram(X, ldx, n, i0, j0, p, 0, 1);
-    store_tile(S, acc, dst, i0, j0, false);
+  for (int tile = 0; tile < ntiles; ++tile) {
+    const int i0 = (tile == 2) ? 16 : 0, j0 = (tile == 0) ? 0 : 16;
+    const d4 acc = tile_gram(X, ldx, n, i0, j0, p, w, GW);
+    store_tile(S, acc, dst, i0, j0, true);
   }
-  __syncthreads();
 }
 
 template <int KD>
-__global__ void __launch_bounds__(GT) k_gaussk(GkParams P) {
+__global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
   constexpr int k = KD, p = KD * (KD - 1) / 2, ldx = p <= 16 ? 16 : 32;
   __shared__ GkShared S;
   const int sid = blockIdx.x, t = threadIdx.x;
@@ -374,7 +378,9 @@ __global__ void __launch_bounds__(GT) k_gaussk(GkParams P) {
 
   // 5. psi = s + sum_m W_m: per margin, bins by doubled rank, suffix sums
   double* Bn = P.B + (2 * o + 2 * (int64_t)sid) * k;
-  const int64_t NB = twon1;  // bins 0 .. 2n + 1
+  // bins floor(R / 2), 0 .. n: distinct tie groups differ by at least 2 in
+  // doubled rank, so no bin holds two groups
+  const int64_t NB = (int64_t)n + 1;
   const double inv_n = 1.0 / dn, inv_s2pi = 0.39894228040143267794;
   for (int m = 0; m < k; ++m) {
     for (int64_t e = t; e < NB * k; e += GT) Bn[e] = 0.0;
@@ -384,35 +390,39 @@ __global__ void __launch_bounds__(GT) k_gaussk(GkParams P) {
       for (int j = 0; j < k; ++j) z[j] = Z[(int64_t)i * k + j];
       const double zm = z[m];
       const double iphi = 1.0 / (inv_s2pi * exp(-0.5 * zm * zm));
-      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i];
+      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i] >> 1;
       for (int j = 0; j < k; ++j) {
         double v = 0.0;
         for (int l = 0; l < k; ++l) v += S.P[j][l] * z[l];
-        atomicAdd(&Bn[(int64_t)r * k + j], v * iphi);
+        unsafeAtomicAdd(&Bn[(int64_t)r * k + j], v * iphi);  // the hardware FP64 add (device memory)
       }
     }
     __syncthreads();
     // suffix sums over the bins: thread t takes bins [t C, (t + 1) C)
     const int64_t C = (NB + GT - 1) / GT;
     const int64_t b0 = t * C, b1 = min(b0 + C, NB);
+    // (the chunk total first, from independent loads; then the carries; then
+    // one walk down the chunk writing the suffix sums)
     double run[KMAX];
     for (int j = 0; j < k; ++j) run[j] = 0.0;
-    for (int64_t b = b1 - 1; b >= b0; --b)
-      for (int j = 0; j < k; ++j) {
-        run[j] += Bn[b * k + j];
-        Bn[b * k + j] = run[j];
-      }
+#pragma unroll 4
+    for (int64_t b = b0; b < b1; ++b)
+      for (int j = 0; j < k; ++j) run[j] += Bn[b * k + j];
     for (int j = 0; j < k; ++j) S.tot[t][j] = run[j];
     __syncthreads();
-    double carry[KMAX];
-    for (int j = 0; j < k; ++j) carry[j] = 0.0;
+    double acc[KMAX];
+    for (int j = 0; j < k; ++j) acc[j] = 0.0;
     for (int u = t + 1; u < GT; ++u)
-      for (int j = 0; j < k; ++j) carry[j] += S.tot[u][j];
-    for (int64_t b = b0; b < b1; ++b)
-      for (int j = 0; j < k; ++j) Bn[b * k + j] += carry[j];
+      for (int j = 0; j < k; ++j) acc[j] += S.tot[u][j];
+#pragma unroll 4
+    for (int64_t b = b1 - 1; b >= b0; --b)
+      for (int j = 0; j < k; ++j) {
+        acc[j] += Bn[b * k + j];
+        Bn[b * k + j] = acc[j];
+      }
     __syncthreads();
     for (int i = t; i < n; i += GT) {
-      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i];
+      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i] >> 1;
       double A[KMAX];
       for (int j = 0; j < k; ++j) A[j] = Bn[(int64_t)r * k + j] * inv_n;
       double* xi = X + (int64_t)i * ldx;

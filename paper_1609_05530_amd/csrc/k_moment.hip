@@ -44,6 +44,7 @@ namespace cpc {
 namespace {
 
 constexpr int MT = 256;  // threads per workgroup = quadrature nodes per evaluation
+constexpr int64_t kSpearmanLdsRows = 16384;  // rank bins in LDS up to this subset size
 
 // 8-point Gauss-Legendre rule on [-1, 1]
 __constant__ double kMx[4] = {0.1834346424956498049, 0.5255324099163289858, 0.7966664774136267396,
@@ -202,7 +203,10 @@ __device__ void newton_invert(double target, double& th, double& slope, double& 
   if (it > 100) status = ST_NOCONV;
 }
 
-template <int FAM>
+// LDSB: the rank bins in LDS (every subset of the launch has at most
+// kSpearmanLdsRows rows; dynamic LDS of 8 (n_max + 1) bytes), else in the
+// workspace.
+template <int FAM, bool LDSB>
 __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
   constexpr int W = MT / WAVE;
   __shared__ double red[W * 4];
@@ -285,42 +289,78 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
   // variance (OK and at the natural boundary)
   double var = NAN;
   if (status == ST_OK || status == ST_BOUNDARY_NATURAL) {
-    long long* H1 = P.H1 + 2 * (o + P.base + sid);
-    long long* H2 = P.H2 + 2 * (o + P.base + sid);
-    const int64_t NH = 2 * n + 2;  // doubled ranks 1 .. 2n+1
-    for (int64_t k = t; k < NH; k += MT) { H1[k] = 0; H2[k] = 0; }
-    __syncthreads();
-    for (int64_t i = t; i < n; i += MT) {
-      const uint32_t x = R1[i], y = R2[i];
-      atomicAdd((unsigned long long*)&H1[x], (unsigned long long)((long long)y - n1));
-      atomicAdd((unsigned long long*)&H2[y], (unsigned long long)((long long)x - n1));
-    }
-    __syncthreads();
-    // suffix sums over the doubled rank: thread t takes the block of
-    // consecutive entries [t*C, (t+1)*C), then adds the totals of the blocks
-    // above it
+    // the suffix sums as bins indexed by the doubled rank; distinct tie
+    // groups differ by at least 2 in doubled rank, so the bins floor(R / 2)
+    // (n + 1 of them) never merge two groups
+    const int64_t NH = n + 1;
     const int64_t C = (NH + MT - 1) / MT;
     const int64_t k0 = t * C, k1 = min(k0 + C, NH);
-    long long t1 = 0, t2 = 0;
-    for (int64_t k = k1 - 1; k >= k0; --k) {
-      t1 += H1[k]; H1[k] = t1;
-      t2 += H2[k]; H2[k] = t2;
-    }
     __shared__ long long tot[2][MT];
-    tot[0][t] = t1;
-    tot[1][t] = t2;
-    __syncthreads();
-    long long c1 = 0, c2 = 0;
-    for (int u = t + 1; u < MT; ++u) { c1 += tot[0][u]; c2 += tot[1][u]; }
-    for (int64_t k = k0; k < k1; ++k) { H1[k] += c1; H2[k] += c2; }
-    __syncthreads();
+    if constexpr (LDSB) {
+      // exact int32 sums in LDS (|sum| <= n^2 < 2^31 for n <= 16384)
+      extern __shared__ int hb[];
+      int* B1 = hb;
+      int* B2 = hb + NH;
+      for (int64_t k = t; k < NH; k += MT) { B1[k] = 0; B2[k] = 0; }
+      __syncthreads();
+      for (int64_t i = t; i < n; i += MT) {
+        const uint32_t x = R1[i], y = R2[i];
+        atomicAdd(&B1[x >> 1], (int)((long long)y - n1));
+        atomicAdd(&B2[y >> 1], (int)((long long)x - n1));
+      }
+      __syncthreads();
+      int t1 = 0, t2 = 0;
+      for (int64_t k = k1 - 1; k >= k0; --k) {
+        t1 += B1[k]; B1[k] = t1;
+        t2 += B2[k]; B2[k] = t2;
+      }
+      tot[0][t] = t1;
+      tot[1][t] = t2;
+      __syncthreads();
+      int c1 = 0, c2 = 0;
+      for (int u = t + 1; u < MT; ++u) { c1 += (int)tot[0][u]; c2 += (int)tot[1][u]; }
+      for (int64_t k = k0; k < k1; ++k) { B1[k] += c1; B2[k] += c2; }
+      __syncthreads();
+    } else {
+      long long* H1 = P.H1 + 2 * (o + P.base + sid);
+      long long* H2 = P.H2 + 2 * (o + P.base + sid);
+      for (int64_t k = t; k < NH; k += MT) { H1[k] = 0; H2[k] = 0; }
+      __syncthreads();
+      for (int64_t i = t; i < n; i += MT) {
+        const uint32_t x = R1[i], y = R2[i];
+        atomicAdd((unsigned long long*)&H1[x >> 1], (unsigned long long)((long long)y - n1));
+        atomicAdd((unsigned long long*)&H2[y >> 1], (unsigned long long)((long long)x - n1));
+      }
+      __syncthreads();
+      // thread t takes the block of consecutive bins [t*C, (t+1)*C), then
+      // adds the totals of the blocks above it
+      long long t1 = 0, t2 = 0;
+      for (int64_t k = k1 - 1; k >= k0; --k) {
+        t1 += H1[k]; H1[k] = t1;
+        t2 += H2[k]; H2[k] = t2;
+      }
+      tot[0][t] = t1;
+      tot[1][t] = t2;
+      __syncthreads();
+      long long c1 = 0, c2 = 0;
+      for (int u = t + 1; u < MT; ++u) { c1 += tot[0][u]; c2 += tot[1][u]; }
+      for (int64_t k = k0; k < k1; ++k) { H1[k] += c1; H2[k] += c2; }
+      __syncthreads();
+    }
     const double inv1 = 1.0 / (double)n1;
     const double wsc = 6.0 / (dn * (double)n1);
     KSum<double> sp, sq;
     for (int64_t i = t; i < n; i += MT) {
       const uint32_t x = R1[i], y = R2[i];
       const double J = 3.0 * (double)((long long)x - n1) * (double)((long long)y - n1) * inv1 * inv1;
-      const double psi = J + wsc * ((double)H1[x] + (double)H2[y]);
+      double w;
+      if constexpr (LDSB) {
+        extern __shared__ int hb[];
+        w = (double)hb[x >> 1] + (double)hb[NH + (y >> 1)];
+      } else {
+        w = (double)P.H1[2 * (o + P.base + sid) + (x >> 1)] + (double)P.H2[2 * (o + P.base + sid) + (y >> 1)];
+      }
+      const double psi = J + wsc * w;
       sp.add(psi);
       sq.add(psi * psi);
     }
@@ -537,15 +577,40 @@ hipError_t launch_kendall(int fam, const uint32_t* R1, const uint32_t* R2, const
 }
 
 hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
-                           int64_t K, int64_t n_min, long long* H1, long long* H2, ResultOut* out, hipStream_t s) {
+                           int64_t K, int64_t n_min, int64_t n_max, long long* H1, long long* H2, ResultOut* out,
+                           hipStream_t s) {
   MomParams p = {};
   p.R1 = R1; p.R2 = R2; p.subs = subs + base; p.n_min = n_min; p.H1 = H1; p.H2 = H2; p.base = base;
   p.out = out + base;
   if (K <= 0) return hipSuccess;
-  switch (fam) {
-    case FAM_GAUSSIAN: hipLaunchKernelGGL(k_spearman<FAM_GAUSSIAN>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
-    case FAM_FRANK: hipLaunchKernelGGL(k_spearman<FAM_FRANK>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
-    default: hipLaunchKernelGGL(k_spearman<FAM_GUMBEL>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
+  const dim3 grid((unsigned)K), block(MT);
+  if (n_max <= kSpearmanLdsRows) {
+    const size_t lds = 2 * sizeof(int) * (size_t)(n_max + 1);
+    static bool attr = false;  // allow the largest dynamic LDS once per process
+    if (!attr) {
+      const int most = (int)(2 * sizeof(int) * (kSpearmanLdsRows + 1));
+      hipError_t e = hipFuncSetAttribute((const void*)k_spearman<FAM_GAUSSIAN, true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, most);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_spearman<FAM_FRANK, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                most);
+      if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_spearman<FAM_GUMBEL, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                most);
+      if (e != hipSuccess) return e;
+      attr = true;
+    }
+    switch (fam) {
+      case FAM_GAUSSIAN: hipLaunchKernelGGL((k_spearman<FAM_GAUSSIAN, true>), grid, block, lds, s, p); break;
+      case FAM_FRANK: hipLaunchKernelGGL((k_spearman<FAM_FRANK, true>), grid, block, lds, s, p); break;
+      default: hipLaunchKernelGGL((k_spearman<FAM_GUMBEL, true>), grid, block, lds, s, p); break;
+    }
+  } else {
+    switch (fam) {
+      case FAM_GAUSSIAN: hipLaunchKernelGGL((k_spearman<FAM_GAUSSIAN, false>), grid, block, 0, s, p); break;
+      case FAM_FRANK: hipLaunchKernelGGL((k_spearman<FAM_FRANK, false>), grid, block, 0, s, p); break;
+      default: hipLaunchKernelGGL((k_spearman<FAM_GUMBEL, false>), grid, block, 0, s, p); break;
+    }
   }
   return hipGetLastError();
 }

@@ -167,7 +167,8 @@ hipError_t launch_replicate_summary(int64_t S, const CombinedOut* comb, const Co
 // H1, H2: 2 (n + K) int64 each.
 // subsets base .. base + K - 1 of `subs`, results to out[base ..].
 hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
-                           int64_t K, int64_t n_min, long long* H1, long long* H2, ResultOut* out, hipStream_t s);
+                           int64_t K, int64_t n_min, int64_t n_max, long long* H1, long long* H2, ResultOut* out,
+                           hipStream_t s);
 // The k-dimensional Gaussian copula of eq. (7) per subset (k_gaussk.hip),
 // 2 <= k <= 8: R holds k columns of n_total doubled ranks; Z (8 k B per
 // row), X (8 gaussk_ldx(k) B per row) and B ((2 n + 2) k doubles per subset
