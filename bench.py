@@ -327,6 +327,100 @@ def leg_replicate_batch(cpc, synth, O, dev, torch):
             "status_counts": {str(int(s)): int(np.sum(st == s)) for s in np.unique(st)}, "err_vs_oracle": err}
 
 
+def leg_moment_estimators(cpc, synth, O, dev, torch, w, x, y):
+    """The Spearman- and Kendall-inversion estimators on the headline
+    workload's ranks (9000 subsets, 9e7 rows): median of 5 timed calls each,
+    and the sampled error against the oracle (host ranks of the same rows)."""
+    R1, R2 = cpc.rank(x, y, w.offsets)
+    out = {}
+    for name, fn in (("spearman", cpc.spearman_fit), ("kendall", cpc.kendall_fit)):
+        ws = torch.empty(int(getattr(cpc._lib.lib(), f"cpc_{name}_workspace_bytes")(w.n, w.K, w.G)),
+                         dtype=torch.uint8, device=dev)
+        res = fn(R1, R2, w.offsets, w.families, w.group_offsets, workspace=ws)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            res = fn(R1, R2, w.offsets, w.families, w.group_offsets, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        med = float(np.median(ms))
+        # oracle on 2 subsets per setting
+        rng = np.random.default_rng(11)
+        picks = np.concatenate([rng.choice(np.arange(w.group_offsets[g], w.group_offsets[g + 1]), 2, replace=False)
+                                for g in range(w.G)])
+        xs = [w.x[w.offsets[m]:w.offsets[m + 1]].astype(np.float64) for m in picks]
+        ys = [w.y[w.offsets[m]:w.offsets[m + 1]].astype(np.float64) for m in picks]
+        r1 = np.concatenate([O.ranks(v) for v in xs]); r2 = np.concatenate([O.ranks(v) for v in ys])
+        off = synth.offsets_from_sizes(np.array([len(v) for v in xs]))
+        fam_of = [w.families[int(np.searchsorted(w.group_offsets, m, side="right") - 1)] for m in picks]
+        ofit = O.spearman_fit_ranks if name == "spearman" else O.kendall_fit_ranks
+        sub, _ = ofit(r1, r2, off, fam_of, np.arange(len(picks) + 1))
+        th = res.theta.cpu().numpy()[picks]
+        st = res.status.cpu().numpy()[picks]
+        ok = (sub["status"] == 0) & (st == 0)
+        rel = np.abs(th[ok] - sub["theta"][ok]) / np.maximum(np.abs(sub["theta"][ok]), 0.1)
+        out[name] = {"ms": med, "subset_fits_per_s": w.K / (med / 1e3), "rows_per_s": w.n / (med / 1e3),
+                     "err_vs_oracle": {"subsets_checked": int(ok.sum()), "theta_max_rel": float(rel.max(initial=0)),
+                                       "status_match": bool(np.array_equal(st, sub["status"]))}}
+    out["workload"] = "ranks of the 9 x 1e7-row headline workload (K = 9000), FP64 estimator arithmetic"
+    return out
+
+
+def leg_gaussk(cpc, synth, O, dev, torch, k=8, K=500, m=10_000):
+    """The k-dimensional Gaussian copula (eq. 7): K subsets of m rows of k
+    margins (host-drawn N(0, R) rows, R a fixed correlation matrix), ranks of
+    every margin and the fit timed separately (median of 5), and the sampled
+    error against the numpy oracle."""
+    from oracle import gaussk as GK
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((k, 2 * k))
+    Sg = A @ A.T + 0.5 * np.eye(k)
+    d = np.sqrt(np.diag(Sg))
+    Rm = Sg / np.outer(d, d)
+    n = K * m
+    t0 = time.perf_counter()
+    X = (rng.standard_normal((n, k)) @ np.linalg.cholesky(Rm).T).T.copy()
+    gen = time.perf_counter() - t0
+    off = np.arange(0, n + 1, m, dtype=np.int64)
+    Xd = torch.from_numpy(X).to(dev)
+    ws = torch.empty(int(cpc._lib.lib().cpc_gaussk_workspace_bytes(n, k, K, 1)), dtype=torch.uint8, device=dev)
+
+    def med(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    holder = {}
+    ms_rank = med(lambda: holder.__setitem__("R", cpc.rank_margins(Xd, off)))
+    ms_fit = med(lambda: holder.__setitem__("res", cpc.gaussk_fit(holder["R"], off, workspace=ws)))
+    res = holder["res"]
+    p = k * (k - 1) // 2
+    th = res.theta.cpu().numpy().reshape(p, K)
+    st = res.status.cpu().numpy().reshape(p, K)
+    errs = []
+    for mm in (0, K - 1):
+        Rs = np.stack([O.ranks(X[j, off[mm]:off[mm + 1]]) for j in range(k)], axis=1)
+        tho, _, _, _, _, sto = GK.fit_subset(Rs)
+        errs.append(float(np.max(np.abs(th[:, mm] - tho) / np.maximum(np.abs(tho), 0.1))) if sto == 0 else np.nan)
+    comb = res.combined_theta.cpu().numpy()
+    truth = np.array([Rm[j, l] for j, l in GK.pairs(k)])
+    return {"workload": f"k={k} margins, K={K} subsets x {m} rows (host-drawn N(0, R)), FP64",
+            "rank_ms": ms_rank, "fit_ms": ms_fit, "subset_fits_per_s": K / (ms_fit / 1e3),
+            "rows_per_s_fit": n / (ms_fit / 1e3), "gen_s": gen, "status_ok": bool(np.all(st == 0)),
+            "err_vs_oracle": {"subsets_checked": 2, "theta_max_rel": float(np.nanmax(errs))},
+            "combined_max_abs_dev_from_R": float(np.max(np.abs(comb - truth)))}
+
+
 def leg_hundred_million_rows(cpc, synth, O, dev, torch):
     """n = 1e8 FP32 pairs per family (Gumbel theta = 3, Frank theta = -8) drawn
     on the GPU, K = 1000 equal subsets: FP32c and FP64 times and errors."""
@@ -590,8 +684,12 @@ def main():
         }
     if not a.profile and not a.no_legs:
         import oracle.oracle as O
-        for name, fn in (("gumbel_theta2_1e7_k1000", leg_gumbel_headline_shape), ("replicate_batch_1000x1e5", leg_replicate_batch),
-                         ("rows_1e8", leg_hundred_million_rows)):
+        legs = (("gumbel_theta2_1e7_k1000", leg_gumbel_headline_shape),
+                ("replicate_batch_1000x1e5", leg_replicate_batch),
+                ("rows_1e8", leg_hundred_million_rows),
+                ("moment_estimators_9x1e7", lambda *args: leg_moment_estimators(*args, w, x, y)),
+                ("gaussk_k8_500x1e4", leg_gaussk))
+        for name, fn in legs:
             t0 = time.perf_counter()
             line[name] = fn(cpc, synth, O, dev, torch)
             print(f"[leg] {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
