@@ -384,39 +384,100 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
   }
 }
 
-// Number of entries of a[0 .. len) below x (a sorted ascending).
-__device__ __forceinline__ int lower_count(const unsigned long long* a, int len, unsigned long long x) {
-  int lo = 0, hi = len;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] < x) lo = mid + 1; else hi = mid;
+// V binary searches stepped together (so that their loads overlap):
+// cnt[v] = number of entries of a[v][0 .. len[v]) below x[v] (each sorted
+// ascending).
+template <int V>
+__device__ __forceinline__ void lower_counts(const unsigned long long* const (&a)[V], const int (&len)[V],
+                                             const unsigned long long (&x)[V], int (&cnt)[V]) {
+  int lo[V], hi[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) { lo[v] = 0; hi[v] = len[v]; }
+  while (true) {
+    bool more = false;
+    int mid[V];
+    unsigned long long val[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      mid[v] = (lo[v] + hi[v]) >> 1;
+      val[v] = lo[v] < hi[v] ? a[v][mid[v]] : 0ull;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (lo[v] < hi[v]) {
+        if (val[v] < x[v]) lo[v] = mid[v] + 1; else hi[v] = mid[v];
+        more = true;
+      }
+    }
+    if (!more) break;
   }
-  return lo;
+#pragma unroll
+  for (int v = 0; v < V; ++v) cnt[v] = lo[v];
 }
 
 // One bottom-up merge level (runs of L entries, L a power of two) of distinct
-// 64-bit words from src into dst. COUNT: the words are (value << 32 |
-// position) and every right-run word adds 2 ((#left < value) - (#left >
-// value)) to C[position] (the left run holds exactly the positions before the
-// right run's).
+// 64-bit words from src into dst, KV words per thread at a time. COUNT: the
+// words are (value << 32 | position) and every right-run word adds
+// 2 ((#left < value) - (#left > value)) to C[position] (the left run holds
+// exactly the positions before the right run's).
+constexpr int KV = 4;
 template <bool COUNT>
 __device__ __forceinline__ void merge_level(const unsigned long long* src, unsigned long long* dst, int n, int L,
                                             int lg, int* C) {
-  for (int p = threadIdx.x; p < n; p += MT) {
-    const int r = p >> lg, start = r << lg;
-    const unsigned long long w = src[p];
-    if (r & 1) {
-      const int ls = start - L;
-      const int le = lower_count(src + ls, L, w);  // left words below w: values <= this one's
-      dst[ls + (p - start) + le] = w;
-      if constexpr (COUNT) {
-        const int lt = lower_count(src + ls, le, (w >> 32) << 32);  // values below this one's
-        C[(uint32_t)w] += 2 * (lt - (L - le));
+  for (int base = threadIdx.x; base < n; base += MT * KV) {
+    const unsigned long long* arr[KV];
+    int len[KV], cnt[KV], pos[KV];
+    unsigned long long w[KV];
+    bool right[KV];
+#pragma unroll
+    for (int v = 0; v < KV; ++v) {
+      const int p = base + v * MT;
+      pos[v] = p;
+      right[v] = false;
+      arr[v] = src;
+      len[v] = 0;
+      w[v] = 0ull;
+      if (p < n) {
+        const int r = p >> lg, start = r << lg;
+        w[v] = src[p];
+        if (r & 1) {
+          right[v] = true;
+          arr[v] = src + (start - L);
+          len[v] = L;
+        } else {
+          const int rs = start + L;
+          if (rs < n) {
+            arr[v] = src + rs;
+            len[v] = min(L, n - rs);
+          }
+        }
       }
-    } else {
-      const int rs = start + L;
-      const int len = rs < n ? min(L, n - rs) : 0;
-      dst[p + lower_count(src + rs, len, w)] = w;
+    }
+    lower_counts<KV>(arr, len, w, cnt);
+#pragma unroll
+    for (int v = 0; v < KV; ++v) {
+      const int p = pos[v];
+      if (p < n) {
+        if (right[v]) {
+          const int start = (p >> lg) << lg;
+          dst[start - L + (p - start) + cnt[v]] = w[v];  // cnt: left words below w, values <= this one's
+        } else {
+          dst[p + cnt[v]] = w[v];
+        }
+      }
+    }
+    if constexpr (COUNT) {
+      unsigned long long x[KV];
+      int len2[KV], lt[KV];
+#pragma unroll
+      for (int v = 0; v < KV; ++v) {
+        x[v] = (w[v] >> 32) << 32;
+        len2[v] = (pos[v] < n && right[v]) ? cnt[v] : 0;
+      }
+      lower_counts<KV>(arr, len2, x, lt);  // values below this one's
+#pragma unroll
+      for (int v = 0; v < KV; ++v)
+        if (pos[v] < n && right[v]) C[(uint32_t)w[v]] += 2 * (lt[v] - (L - cnt[v]));
     }
   }
 }
@@ -477,14 +538,43 @@ __global__ void __launch_bounds__(MT) k_kendall(MomParams P) {
   //    #{same a, b < b_p} and #{same a, b > b_p}; C[p] starts at the terms of
   //    S that do not need the second sort; dst gets (b << 32 | p)
   const unsigned long long imask = (1ull << IB) - 1ull;
-  for (int p = t; p < n; p += MT) {
-    const unsigned long long w = src[p];
-    const int i = (int)(w & imask);
-    const unsigned long long a = R1[i], b = R2[i], key = w >> IB;
-    const int A0 = lower_count(src, n, (a * M) << IB), A1 = lower_count(src, n, ((a + 1ull) * M) << IB);
-    const int J0 = lower_count(src, n, key << IB), J1 = lower_count(src, n, (key + 1ull) << IB);
-    C[p] = (n + 1) - (int)b - (J0 - A0) - (A1 - J1);
-    dst[p] = (b << 32) | (unsigned long long)p;
+  constexpr int PV = 2;  // positions per thread at a time (4 searches each)
+  for (int base = t; base < n; base += MT * PV) {
+    const unsigned long long* arr[4 * PV];
+    int len[4 * PV], cnt[4 * PV];
+    unsigned long long x[4 * PV], bv[PV];
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+      const int p = base + v * MT;
+      unsigned long long a = 0, b = 0, key = 0;
+      if (p < n) {
+        const unsigned long long w = src[p];
+        const int i = (int)(w & imask);
+        a = R1[i];
+        b = R2[i];
+        key = w >> IB;
+      }
+      bv[v] = b;
+      x[4 * v] = (a * M) << IB;             // first of the run of equal a
+      x[4 * v + 1] = ((a + 1ull) * M) << IB;  // past it
+      x[4 * v + 2] = key << IB;             // first of the run of equal (a, b)
+      x[4 * v + 3] = (key + 1ull) << IB;    // past it
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        arr[4 * v + e] = src;
+        len[4 * v + e] = p < n ? n : 0;
+      }
+    }
+    lower_counts<4 * PV>(arr, len, x, cnt);
+#pragma unroll
+    for (int v = 0; v < PV; ++v) {
+      const int p = base + v * MT;
+      if (p < n) {
+        const int A0 = cnt[4 * v], A1 = cnt[4 * v + 1], J0 = cnt[4 * v + 2], J1 = cnt[4 * v + 3];
+        C[p] = (n + 1) - (int)bv[v] - (J0 - A0) - (A1 - J1);
+        dst[p] = (bv[v] << 32) | (unsigned long long)p;
+      }
+    }
   }
   __syncthreads();
   // 3. the sign counts: merge sort of (b << 32 | p)
