@@ -369,6 +369,43 @@ def leg_moment_estimators(cpc, synth, O, dev, torch, w, x, y):
     return out
 
 
+def leg_adjoint(cpc, synth, O, dev, torch, w, x, y, theta):
+    """The adjoint kernel (cpc_eval: per-subset sums of l, dl/dtheta and
+    d2l/dtheta2 of eq. (13)) on the headline workload's ranks at the fitted
+    theta, FP32c and FP64: one call per family's run of settings, median of
+    5; rows evaluated per second (each row gives l, s and h once)."""
+    R1, R2 = cpc.rank(x, y, w.offsets)
+    th = torch.as_tensor(theta, dtype=torch.float64, device=dev)
+    runs, g = [], 0
+    while g < w.G:
+        h = g
+        while h < w.G and w.families[h] == w.families[g]:
+            h += 1
+        m0, m1 = int(w.group_offsets[g]), int(w.group_offsets[h])
+        a, b = int(w.offsets[m0]), int(w.offsets[m1])
+        runs.append((w.families[g], R1[a:b], R2[a:b], w.offsets[m0:m1 + 1] - a, th[m0:m1].contiguous()))
+        g = h
+    out = {}
+    for prec in ("fp32c", "fp64"):
+        def call():
+            for fam, r1, r2, off, t in runs:
+                cpc.eval_subsets(r1, r2, off, fam, t, prec=prec)
+        call()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            call()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        out[prec] = {"ms": ms, "row_evals_per_s": w.n / (ms / 1e3), "subsets_per_s": w.K / (ms / 1e3)}
+    out["workload"] = "9 x 1e7-row headline ranks (K = 9000) at the fitted theta; l, s, h per row"
+    return out
+
+
 def leg_gaussk(cpc, synth, O, dev, torch, k=8, K=500, m=10_000):
     """The k-dimensional Gaussian copula (eq. 7): K subsets of m rows of k
     margins (host-drawn N(0, R) rows, R a fixed correlation matrix), ranks of
@@ -688,7 +725,8 @@ def main():
                 ("replicate_batch_1000x1e5", leg_replicate_batch),
                 ("rows_1e8", leg_hundred_million_rows),
                 ("moment_estimators_9x1e7", lambda *args: leg_moment_estimators(*args, w, x, y)),
-                ("gaussk_k8_500x1e4", leg_gaussk))
+                ("gaussk_k8_500x1e4", leg_gaussk),
+                ("adjoint_9x1e7", lambda *args: leg_adjoint(*args, w, x, y, theta)))
         for name, fn in legs:
             t0 = time.perf_counter()
             line[name] = fn(cpc, synth, O, dev, torch)

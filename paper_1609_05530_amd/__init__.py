@@ -248,21 +248,34 @@ def variance(R1: torch.Tensor, R2: torch.Tensor, offsets, family, theta: torch.T
 
 class LogLik(torch.autograd.Function):
     """theta (K,) -> per-subset pseudo log-likelihood eq. (13); its gradient is
-    the score from the hand-written adjoint kernel (twice differentiable:
-    the score's own gradient is the Hessian from the same kernel)."""
+    the score and the score's gradient the Hessian, all three from one launch
+    of the hand-written adjoint kernel (kept for the backward passes)."""
 
     @staticmethod
     def forward(ctx, theta, R1, R2, offsets, family, prec="fp32c"):
         out = eval_subsets(R1, R2, offsets, family, theta.detach(), prec=prec)
-        ctx.save_for_backward(theta)
-        ctx.meta = (R1, R2, offsets, family, prec)
+        ctx.save_for_backward(theta, out[:, 1].clone(), out[:, 2].clone())
         return out[:, 0].clone()
 
     @staticmethod
     def backward(ctx, g):
-        (theta,) = ctx.saved_tensors
-        R1, R2, offsets, family, prec = ctx.meta
-        return g * Score.apply(theta, R1, R2, offsets, family, prec), None, None, None, None, None
+        theta, score, hess = ctx.saved_tensors
+        return g * _Known.apply(theta, score, hess), None, None, None, None, None
+
+
+class _Known(torch.autograd.Function):
+    """theta -> a value already computed at theta, whose derivative with
+    respect to theta is also known (the score and its Hessian)."""
+
+    @staticmethod
+    def forward(ctx, theta, value, derivative):
+        ctx.save_for_backward(derivative)
+        return value.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (derivative,) = ctx.saved_tensors
+        return g * derivative, None, None
 
 
 class Score(torch.autograd.Function):

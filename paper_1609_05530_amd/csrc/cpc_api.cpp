@@ -1053,7 +1053,9 @@ int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, 
   touch_workspace(h, workspace);
   Carved c = carve(workspace, L);
   HIP_OK(hipMemcpyAsync(c.subs, subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
-  HIP_OK(launch_eval_wg(R1, R2, c.subs, K, family, o.prec == CPC_PREC_FP64 ? 1 : 0, theta, out, s));
+  int64_t n_max = 0;
+  for (int64_t m = 0; m < K; ++m) n_max = std::max<int64_t>(n_max, offsets[m + 1] - offsets[m]);
+  HIP_OK(launch_eval_wg(R1, R2, c.subs, K, family, o.prec == CPC_PREC_FP64 ? 1 : 0, n_max, theta, out, s));
   return CPC_SUCCESS;
 }
 

@@ -327,6 +327,31 @@ CPC_HD void frank_sh(const FrankConst<T>& k, T u, T v, T omv, T& s, T& h) {
   s = k.C1 - (u + v) - (T)2 * t.r1;
   h = k.C2 - (T)2 * r2 + (T)2 * t.r1 * t.r1;
 }
+// Adjoint pass: l (without log(theta E)), score and Hessian from one D.
+template <typename T, int FORM = -1>
+CPC_HD void frank_lsh(const FrankConst<T>& k, T u, T v, T omv, T& l, T& s, T& h) {
+  const bool scaled = FORM == 1 || (FORM == -1 && sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW);
+  const T th = k.th;
+  if (scaled) {
+    const T Ah = -m_expm1(-th * u) * k.ith, Bh = -m_expm1(-th * v) * k.ith;
+    const T a = (T)1 - th * Ah, b = (T)1 - th * Bh;
+    const T Dh = k.Eh - th * Ah * Bh;
+    const T iDh = m_rcp(Dh);
+    const T P = u * a * Bh + v * b * Ah;
+    l = -th * (u + v) - (T)2 * ((T)k.logth + m_log(Dh));
+    s = (k.Eh * k.psi - Ah * Bh * (k.Eh + k.e)) * k.iEh * iDh - (u + v) + (T)2 * P * iDh;
+    const T ith = k.ith;
+    const T r1 = (k.e - th * P) * iDh * ith;
+    const T r2 = (-k.e + th * (u * u * a * Bh + v * v * b * Ah) - (T)2 * u * v * a * b) * iDh * ith;
+    h = k.C2 - (T)2 * r2 + (T)2 * r1 * r1;
+    return;
+  }
+  const FrankTerms<T> t = frank_terms(k, u, v, omv);
+  const T Dpp = -k.e + u * u * t.a * t.Bm - (T)2 * u * v * t.a * t.b + v * v * t.b * t.Am;
+  l = -th * (u + v) - (T)2 * m_log(t.D);
+  s = k.C1 - (u + v) - (T)2 * t.r1;
+  h = k.C2 - (T)2 * Dpp * t.iD + (T)2 * t.r1 * t.r1;
+}
 // Variance pass: l (without log(theta E)), score, d2l/dtheta du, d2l/dtheta dv.
 template <typename T, int FORM = -1>
 CPC_HD void frank_full(const FrankConst<T>& k, T u, T v, T omv, T& l, T& s, T& g1, T& g2) {
@@ -485,6 +510,15 @@ CPC_HD void gumbel_sh(const GumbelConst<T>& k, T lx, T ly, T& s, T& h) {
   const T a = (t.wt + (T)1) * t.iden;
   s = -t.wt - t.dl * ((T)1 - t.q) * t.ip - t.H * k.ith2 + a;
   h = -t.wtt + t.wtt * t.iden - a * a + (T)2 * t.H * k.ith3 + (k.ith - (T)2) * t.V;
+}
+// Adjoint pass: l, score and Hessian from one set of terms.
+template <typename T>
+CPC_HD void gumbel_lsh(const GumbelConst<T>& k, T lx, T ly, T& l, T& s, T& h) {
+  const GumbelTerms<T> t = gumbel_terms(k, lx, ly);
+  const T a = (t.wt + (T)1) * t.iden;
+  s = -t.wt - t.dl * ((T)1 - t.q) * t.ip - t.H * k.ith2 + a;
+  h = -t.wtt + t.wtt * t.iden - a * a + (T)2 * t.H * k.ith3 + (k.ith - (T)2) * t.V;
+  l = -t.w + k.thm1 * (lx + ly) + m_exp(lx) + m_exp(ly) + (k.ith - (T)2) * t.LA + m_log(t.w + k.thm1);
 }
 // Variance pass: l, s, g1 = d2l/dtheta du, g2 = d2l/dtheta dv.
 template <typename T>

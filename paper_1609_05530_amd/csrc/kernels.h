@@ -139,7 +139,7 @@ constexpr int64_t kBigChunkMaxRows = 1 << 17;
 
 // Adjoint of eq. (13): per-subset sums of l, dl/dtheta, d2l/dtheta2.
 hipError_t launch_eval_wg(const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t K, int fam,
-                          int fp64, const double* theta, double* out, hipStream_t s);
+                          int fp64, int64_t n_max, const double* theta, double* out, hipStream_t s);
 
 // eq. (15) / (16) per group.
 struct CombinedOut {  // identical layout to cpc_combined_t

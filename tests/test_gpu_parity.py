@@ -341,6 +341,29 @@ def test_autograd_loglik_and_score():
         assert abs(h[k].item() - (sp - sm) / (2 * hfd)) <= 1e-5 * (1 + abs(h[k].item()))
 
 
+def test_loglik_backward_reuses_the_forward_launch(monkeypatch):
+    """LogLik keeps the score and Hessian of its one adjoint launch: the
+    gradient and the gradient of the gradient launch nothing more."""
+    import paper_1609_05530_amd as m
+    sizes = np.array([1500, 2500])
+    x, y = synth.copula_pairs("gumbel", 2.0, int(sizes.sum()), 32)
+    off = synth.offsets_from_sizes(sizes)
+    R1, R2 = m.rank(dev(x, torch.float64), dev(y, torch.float64), off)
+    ref = m.eval_subsets(R1, R2, off, "gumbel", torch.tensor([1.8, 2.3], dtype=torch.float64, device="cuda"),
+                         prec="fp64").cpu().numpy()
+    calls = []
+    real = m.eval_subsets
+    monkeypatch.setattr(m, "eval_subsets", lambda *a, **k: calls.append(1) or real(*a, **k))
+    theta = torch.tensor([1.8, 2.3], dtype=torch.float64, device="cuda", requires_grad=True)
+    ll = m.LogLik.apply(theta, R1, R2, off, "gumbel", "fp64")
+    (g,) = torch.autograd.grad(ll.sum(), theta, create_graph=True)
+    (h,) = torch.autograd.grad(g.sum(), theta)
+    assert len(calls) == 1
+    assert np.array_equal(ll.detach().cpu().numpy(), ref[:, 0])
+    assert np.array_equal(g.detach().cpu().numpy(), ref[:, 1])
+    assert np.array_equal(h.cpu().numpy(), ref[:, 2])
+
+
 def test_bitwise_deterministic():
     w = synth.nine_settings(settings=[("frank", 10.0), ("gaussian", 0.5)], n=200_000, K=20, lo=5000, hi=15000)
     fams = w.families
