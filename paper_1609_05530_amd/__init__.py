@@ -36,9 +36,13 @@ def _code(table, v):
 
 
 def _options(prec="fp64", ties="average", var="ggr", max_iter=60, tol=0.0, n_min=2, graph=False,
-             phase_times=False) -> Options:
+             phase_times=False, schedule=None) -> Options:
+    """schedule: None (the library's default, autotuned rank shapes), 0 (built-in
+    shapes) or 1 + a rank shape index (that shape for its size class)."""
     o = Options()
     lib().cpc_default_options(ctypes.byref(o))
+    if schedule is not None:
+        o.schedule = int(schedule)
     o.prec = _code(PRECISIONS, prec)
     o.ties = _code(TIES, ties)
     o.var = _code(VARIANCES, var)

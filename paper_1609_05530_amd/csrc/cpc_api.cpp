@@ -109,7 +109,9 @@ int read_options(const cpc_options_t* o, Options& r) {
   if (o->max_iter < 1) return fail(CPC_E_OPTIONS, "max_iter must be >= 1 (got %d)", o->max_iter);
   if (!(o->tol >= 0.0) || !std::isfinite(o->tol)) return fail(CPC_E_OPTIONS, "tol must be finite and >= 0");
   if (o->n_min < 0) return fail(CPC_E_OPTIONS, "n_min must be >= 0");
-  if (o->schedule != -1 && o->schedule != 0) return fail(CPC_E_OPTIONS, "schedule must be -1 or 0 (got %d)", o->schedule);
+  if (o->schedule < -1 || o->schedule > kNumRankShapes)
+    return fail(CPC_E_OPTIONS, "schedule must be -1, 0 or 1 + a rank shape index below %d (got %d)", kNumRankShapes,
+                o->schedule);
   r.prec = o->prec;
   r.ties = o->ties;
   r.var = o->var;
@@ -472,7 +474,7 @@ struct GraphCache {
             size_t ws_bytes_, void* out_, void* comb_) const {
     return valid && x == x_ && y == y_ && dtype == dtype_ && n == n_ && K == K_ && G == G_ && ws == ws_ &&
            ws_bytes == ws_bytes_ && out == out_ && comb == comb_ && o.prec == o_.prec && o.ties == o_.ties &&
-           o.var == o_.var && o.max_iter == o_.max_iter && o.tol == o_.tol && o.n_min == o_.n_min &&
+           o.var == o_.var && o.max_iter == o_.max_iter && o.tol == o_.tol && o.n_min == o_.n_min && o.schedule == o_.schedule &&
            o.flags == o_.flags && std::equal(offsets.begin(), offsets.end(), off_) &&
            std::equal(gofs.begin(), gofs.end(), gofs_) && fam == fam_;
   }
@@ -549,6 +551,11 @@ int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, 
   Tuner& t = tuner_of(h);
   for (Bucket& b : P.rank_buckets) {
     b.shape = kRankDefaultShape[b.cls];
+    if (o.schedule > 0) {  // a forced shape, for the classes whose capacity it has
+      if (kw == 1 && kRankShapes[o.schedule - 1].cap == kClassThreads[b.cls] * kClassItems[b.cls])
+        b.shape = o.schedule - 1;
+      continue;
+    }
     if (o.schedule == 0 || kw != 1 || b.count <= 0) continue;
     double mean = 0.0;
     for (int32_t i = 0; i < b.count; ++i) mean += P.subs[P.order_rank[b.first + i]].n;
@@ -566,7 +573,7 @@ int choose_rank_shapes(cpc_handle_t h, Plan& P, const Carved& c, const void* x, 
     RankParams rp = rank_params(c, x, y, o);
     rp.order = c.order_rank + b.first;
     float best = 0.0f;
-    for (int k = 0; k < 5 && kRankCandidates[b.cls][k] >= 0; ++k) {
+    for (int k = 0; k < 6 && kRankCandidates[b.cls][k] >= 0; ++k) {
       const int shape = kRankCandidates[b.cls][k];
       HIP_OK(launch_rank_shape(shape, kw, rp, b.count, s));  // warm-up
       HIP_OK(hipEventRecord(h->ev[0], s));
@@ -962,7 +969,11 @@ int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_
   const int kw = (dtype == CPC_F64) ? 2 : 1;
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
-    HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
+    // a shape forced through opt->schedule for the classes it serves; else the class default
+    if (o.schedule > 0 && kw == 1 && kRankShapes[o.schedule - 1].cap == kClassThreads[b.cls] * kClassItems[b.cls])
+      HIP_OK(launch_rank_shape(o.schedule - 1, kw, rp, b.count, s));
+    else
+      HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
   }
   set_big(c, P, o.n_min);
   HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s));

@@ -32,6 +32,13 @@ static hipError_t launch_shape1(const RankParams& p, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int T, int E>
+static hipError_t launch_shape_merge(const RankParams& p, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_rank_wg<T, E, 4, 1, false, false, false, true, true>), dim3(grid), dim3(T), 0, s, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, hipStream_t s) {
   if (shape < 0 || shape >= kNumRankShapes) return hipErrorInvalidValue;
   if (kw == 2) {  // 64-bit keys: the unpacked default of the class the shape serves
@@ -54,6 +61,7 @@ hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, h
     case 11: return launch_shape1<256, 32, true>(p, grid, s);
     case 12: return launch_shape1<1024, 16, true>(p, grid, s);
     case 13: return launch_shape1<512, 32, true>(p, grid, s);
+    case 14: return launch_shape_merge<64, 8>(p, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -2,7 +2,8 @@
 // arXiv:1609.05530 within each subset of the partition (eq. 14), for subsets
 // of up to T*E rows. Each margin is read once from HBM into registers
 // (blocked arrangement), stably radix-sorted by its order-preserving key
-// with the row index as payload (block_rank.h), and tie groups are found in
+// with the row index as payload (block_rank.h) or, in the one-wave merge
+// shape, merge-sorted as (key, row) words, and tie groups are found in
 // sorted order by two workgroup scans. Outputs per row: the doubled rank
 // R = 2 r (average ranks for ties: R = 2 #{less} + #{equal} + 1, or ties
 // broken by row order), the sorted position and the start of the row's tie
@@ -72,13 +73,76 @@ struct RankLds {
 static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
 
 
+// Merge-sort alternative to the radix passes (32-bit keys): each element is
+// the 64-bit word (key << 32 | row), so that the sorted order of the words
+// is the stable order of the keys. Each thread sorts its E words in
+// registers (bitonic network), then runs of E, 2E, ... are merged by merge
+// path in LDS: a thread's E outputs start where the diagonal through its
+// first output crosses the two runs (one binary search), and the words are
+// merged with two pointers into registers; after a barrier they are written
+// back in place. Levels stop once one run holds every valid element (the
+// words past n are the largest and already in order).
+template <int E>
+__device__ __forceinline__ void sort_regs_u64(uint64_t (&w)[E]) {
+#pragma unroll
+  for (int k = 2; k <= E; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool up = (i & k) == 0;
+          const uint64_t a = w[i], b = w[l];
+          const bool swap = up ? (a > b) : (a < b);
+          w[i] = swap ? b : a;
+          w[l] = swap ? a : b;
+        }
+      }
+}
+
+template <int T, int E>
+__device__ __forceinline__ void merge_sort_words(uint64_t (&w)[E], uint64_t* buf, int n) {
+  const int p0 = threadIdx.x * E;
+  sort_regs_u64<E>(w);
+#pragma unroll 1
+  for (int L = E; L < n; L <<= 1) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) buf[p0 + j] = w[j];
+    __syncthreads();
+    const int base = p0 & ~(2 * L - 1);
+    const uint64_t* A = buf + base;
+    const uint64_t* Bv = buf + base + L;
+    const int d0 = p0 - base;
+    int lo = max(0, d0 - L), hi = min(d0, L);
+    while (lo < hi) {
+      const int i = (lo + hi) >> 1;
+      if (A[i] < Bv[d0 - i - 1]) lo = i + 1; else hi = i;
+    }
+    int ia = lo, ib = d0 - lo;
+    uint64_t a = ia < L ? A[ia] : ~0ull, b = ib < L ? Bv[ib] : ~0ull;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const bool ta = a < b;  // (an exhausted run reads as ~0, above every word)
+      w[j] = ta ? a : b;
+      ia += ta ? 1 : 0;
+      ib += ta ? 0 : 1;
+      const int idx = ta ? ia : ib;
+      const uint64_t v = idx < L ? (ta ? A : Bv)[idx] : ~0ull;
+      a = ta ? v : a;
+      b = ta ? b : v;
+    }
+    __syncthreads();
+  }
+}
+
 // Ranks one margin and writes, per row of the subset, the sorted position e
 // and, if the margin has ties, the doubled rank R and the tie-group start lb
 // (without ties R = 2e + 2 and lb = e, and e_is_l is set in every thread;
 // MODE_RANK writes R alone, as 32-bit values). Returns true (in every thread)
 // if the margin holds a non-finite value; sets all_tied (in thread 0) if
 // every value is equal.
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, typename DT>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, bool MERGE, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
                                                 RankLds<T, E, B, KW, ALIAS, P32, PAD>& sm, uint16_t* Rg, uint16_t* Eg,
                                                 uint16_t* Lg, uint32_t* R32, bool& all_tied, bool& e_is_l) {
@@ -190,7 +254,22 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   bool packed = false;
   int kbase = 0;
   const bool active = w * WAVE * E < n;
-  if (var != 0ull && n > 1) {
+  if constexpr (MERGE) {
+    static_assert(KW == 1 && !ALIAS && !PACK, "merge sort: 32-bit keys, own buffer");
+    static_assert(Lds::MAIN >= 2 * CAP, "the 64-bit merge buffer fits the LDS layout");
+    if (var != 0ull && n > 1) {
+      uint64_t wd[E];
+#pragma unroll
+      for (int j = 0; j < E; ++j) wd[j] = ((uint64_t)klo[j] << 32) | pay[j];
+      __syncthreads();  // the keys' transposition buffer is read
+      merge_sort_words<T, E>(wd, reinterpret_cast<uint64_t*>(sm.main), n);
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        klo[j] = (uint32_t)(wd[j] >> 32);
+        pay[j] = (uint32_t)wd[j];
+      }
+    }
+  } else if (var != 0ull && n > 1) {
     const int lo = __builtin_ctzll(var);
     const int hi = 63 - __builtin_clzll(var);
     const int npass = (hi - lo) / B + 1;
@@ -441,7 +520,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   return bad;
 }
 
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false, bool PAD = false>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false, bool PAD = false, bool MERGE = false>
 __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   __shared__ RankLds<T, E, B, KW, ALIAS, P32, PAD> sm;
   const int sid = P.order[blockIdx.x];
@@ -460,17 +539,17 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   bool t1, t2, b1, b2, q1, q2;
   const int64_t o = sd.begin;
   if constexpr (KW == 2) {
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
                                                      P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
                                                      P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2);
   } else {
     const bool ik = P.int_keys != 0;
     const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
     const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
                                                     P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
                                                     P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2);
   }
   if (rk) return;
