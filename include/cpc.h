@@ -101,9 +101,10 @@ typedef struct {
   double tol;        /* stop when |dtheta| <= tol (1 + |theta|); 0 = default (1e-12 FP64, 1e-9 FP32C) */
   int64_t n_min;     /* subsets with fewer rows are DEGENERATE; default (and minimum) 2 */
   int32_t schedule;  /* -1 = rank-kernel launch shapes chosen by the autotuner (default); 0 = built-in shapes;
-                        1 + s (0 <= s < 15) forces rank-kernel shape s on FP32 data for the size class of its
-                        capacity (0..13: radix-sort variants; 14: the one-wave merge sort for up to 512
-                        rows), the built-in shapes elsewhere */
+                        1 + s (0 <= s < 16) forces rank-kernel shape s on FP32 data for the size class of its
+                        capacity (0..13: radix-sort variants; 14: the one-wave merge sort and 15 the
+                        one-wave sort truncated to 24 leading key bits, for up to 512 rows), the built-in
+                        shapes elsewhere */
   int32_t flags;     /* bit 0: capture/replay the launch sequence as a hipGraph */
 } cpc_options_t;
 

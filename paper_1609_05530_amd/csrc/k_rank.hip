@@ -39,6 +39,13 @@ static hipError_t launch_shape_merge(const RankParams& p, int grid, hipStream_t 
   return hipGetLastError();
 }
 
+template <int T, int E>
+static hipError_t launch_shape_trunc(const RankParams& p, int grid, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_rank_wg<T, E, 4, 1, false, false, false, true, false, 24>), dim3(grid), dim3(T), 0, s, p);
+  return hipGetLastError();
+}
+
 hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, hipStream_t s) {
   if (shape < 0 || shape >= kNumRankShapes) return hipErrorInvalidValue;
   if (kw == 2) {  // 64-bit keys: the unpacked default of the class the shape serves
@@ -62,6 +69,7 @@ hipError_t launch_rank_shape(int shape, int kw, const RankParams& p, int grid, h
     case 12: return launch_shape1<1024, 16, true>(p, grid, s);
     case 13: return launch_shape1<512, 32, true>(p, grid, s);
     case 14: return launch_shape_merge<64, 8>(p, grid, s);
+    case 15: return launch_shape_trunc<64, 8>(p, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

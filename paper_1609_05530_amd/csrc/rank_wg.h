@@ -54,7 +54,7 @@ struct RankLds {
   static constexpr int SMALL = 3 * W + W * KW + 8;  // red, wmax, wmin, wl, andor (+ non-finite flag)
   static constexpr int MAIN = ALIAS ? (CNT > XW ? CNT : XW) + SMALL : CNT + XW;
   // tie phase (not aliased): wmax, wmin, wl and the per-wave tie flags in the counters
-  static_assert(ALIAS || CNT >= 3 * W + W * KW, "tie-phase arrays fit in the counters");
+  static_assert(ALIAS || CNT >= 4 * W + W * KW, "tie-phase arrays fit in the counters");
   alignas(16) uint32_t main[MAIN];  // 16-byte vector reads of keys, payloads, counters
   __device__ __forceinline__ uint32_t* cnt() { return main; }
   __device__ __forceinline__ uint32_t* xk() { return ALIAS ? main : main + CNT; }
@@ -68,6 +68,8 @@ struct RankLds {
   // per-wave "has a tie" votes (counter region, free after the passes;
   // unaliased layout only)
   __device__ __forceinline__ int32_t* wflag() { return wmax() + 2 * W + W * KW; }
+  // per-wave longest run of equal leading key bits (truncated sorts)
+  __device__ __forceinline__ int32_t* wrun() { return wflag() + W; }
   __device__ __forceinline__ uint32_t* andor() { return ALIAS ? small() + 3 * W + W * KW : xv32(); }
 };
 static_assert(sizeof(RankLds<1024, 16, 4, 2, false, false, true>) <= 160 * 1024, "largest rank LDS layout fits");
@@ -142,10 +144,11 @@ __device__ __forceinline__ void merge_sort_words(uint64_t (&w)[E], uint64_t* buf
 // MODE_RANK writes R alone, as 32-bit values). Returns true (in every thread)
 // if the margin holds a non-finite value; sets all_tied (in thread 0) if
 // every value is equal.
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, bool MERGE, typename DT>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK, bool PAD, bool MERGE, int TRUNC, typename DT>
 __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties, bool int_keys,
                                                 RankLds<T, E, B, KW, ALIAS, P32, PAD>& sm, uint16_t* Rg, uint16_t* Eg,
-                                                uint16_t* Lg, uint32_t* R32, bool& all_tied, bool& e_is_l) {
+                                                uint16_t* Lg, uint32_t* R32, bool& all_tied, bool& e_is_l,
+                                                bool& redo) {
   using Rank = BlockDigitRank<T, E, B>;
   using Lds = RankLds<T, E, B, KW, ALIAS, P32, PAD>;
   constexpr int W = T / WAVE;
@@ -158,8 +161,16 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   uint32_t* andor = sm.andor();
   all_tied = false;
   e_is_l = false;
+  redo = false;
   if (n <= 0) return false;
 
+  // Truncated sorts (TRUNC > 0, 32-bit keys) first sort on the TRUNC leading
+  // varying key bits only and put the elements of each run of equal leading
+  // bits in order by counting, in the run, the keys below theirs; a run
+  // longer than RUN_MAX returns with `redo` set, nothing written: the caller
+  // then sorts the margin again over every varying bit.
+  static_assert(TRUNC == 0 || (KW == 1 && !ALIAS && !PACK && !MERGE), "truncated sorts: 32-bit keys, unpacked");
+  constexpr int RUN_MAX = 32;
   // load, keys, non-finite flag, AND / OR of the keys. 32-bit keys are read
   // coalesced and transposed to the blocked arrangement through LDS; 64-bit
   // keys are read blocked. An item past the end takes the largest key: the
@@ -253,6 +264,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   constexpr uint32_t PMASK = (1u << PB) - 1u;
   bool packed = false;
   int kbase = 0;
+  int tsh = 0;  // truncated sort: the lowest key bit sorted on (0: every varying bit)
   const bool active = w * WAVE * E < n;
   if constexpr (MERGE) {
     static_assert(KW == 1 && !ALIAS && !PACK, "merge sort: 32-bit keys, own buffer");
@@ -270,8 +282,12 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
       }
     }
   } else if (var != 0ull && n > 1) {
-    const int lo = __builtin_ctzll(var);
     const int hi = 63 - __builtin_clzll(var);
+    int lo = __builtin_ctzll(var);
+    if (TRUNC > 0 && hi + 1 - TRUNC > lo) {
+      lo = hi + 1 - TRUNC;
+      tsh = lo;
+    }
     const int npass = (hi - lo) / B + 1;
     int ps = 0;
     // passes with separate key and payload (the last of them may already
@@ -404,7 +420,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   }
 
   // tie groups: a sorted position starts a group unless its key equals its
-  // predecessor's
+  // predecessor's (truncated sorts: runs of equal leading bits, put in order
+  // and split into tie groups below)
   if (lane == WAVE - 1) {
     sm.wl()[w * KW] = klo[E - 1];
     if (KW == 2) sm.wl()[w * KW + KW - 1] = khi[E - 1];
@@ -423,7 +440,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   for (int j = 0; j < E; ++j) {
     const uint32_t ql = j ? klo[j - 1] : plo;
     const uint32_t qh = j ? khi[j - 1] : phi;
-    const bool head = (j < nv) && ((p0 + j == 0) || ql != klo[j] || (KW == 2 && qh != khi[j]));
+    const bool head = (j < nv) && ((p0 + j == 0) || (ql >> tsh) != (klo[j] >> tsh) || (KW == 2 && qh != khi[j]));
     headm |= head ? (1u << j) : 0u;
     hmax = head ? p0 + j : hmax;
     hmin = head ? min(hmin, p0 + j) : hmin;
@@ -437,7 +454,7 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   // group starts are stored beside the sorted positions)
   const uint32_t vmask = nv >= 32 ? 0xFFFFFFFFu : ((1u << nv) - 1u);
   const bool tied_here = (headm & vmask) != vmask;
-  if constexpr (!ALIAS) {
+  if (!ALIAS && tsh == 0) {
     const bool wtie = __ballot(tied_here) != 0ull;
     if (lane == 0) sm.wflag()[w] = wtie ? 1 : 0;
   }
@@ -445,7 +462,27 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   int cr = __shfl_down(imin, 1, WAVE);
   if (lane == 0) cl = -1;
   if (lane == WAVE - 1) cr = INT_MAX;
+  if (TRUNC > 0 && tsh > 0) {
+    // truncated sort: the longest stretch of one run inside this wave (a run
+    // over two waves is at most twice that; one over three fills a wave)
+    int cur = max(cl, w * WAVE * E), rl = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if ((headm >> j) & 1u) cur = p0 + j;
+      rl = (j < nv) ? max(rl, p0 + j - cur + 1) : rl;
+    }
+    rl = __builtin_amdgcn_readlane(wave_incl_max_i32(rl), WAVE - 1);
+    if (lane == 0) sm.wrun()[w] = rl;
+  }
   __syncthreads();
+  if (TRUNC > 0 && tsh > 0) {  // workgroup-uniform
+    const int mr = __builtin_amdgcn_readlane(row_incl_max_i32(lane < W ? sm.wrun()[lane] : 0), W - 1);
+    if (mr > RUN_MAX) {
+      __syncthreads();  // every thread has read the run lengths
+      redo = true;      // the caller sorts again over every varying bit
+      return bad;
+    }
+  }
   {
     // the waves before (max) and after (min) this one: every lane of row 0
     // reads one wave's value, scanned across the row
@@ -456,14 +493,6 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
     if (wu > 0) cl = max(cl, __builtin_amdgcn_readlane(a, wu - 1));
     if (wu + 1 < W) cr = min(cr, __builtin_amdgcn_readlane(b, wu + 1));
   }
-  // workgroup-uniform: every row's group start equals its sorted position
-  // (and its doubled rank is 2 x position + 2: neither is stored then)
-  bool eq = false;
-  if constexpr (!ALIAS) {
-    const int f = lane < W ? sm.wflag()[lane] : 0;
-    eq = (ties == 1) || (__ballot(f != 0) == 0ull);
-  }
-  e_is_l = eq;
   cr = min(cr, n);
   uint32_t lb[E], ub[E];
   {
@@ -480,19 +509,63 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
       if ((headm >> j) & 1u) cur = p0 + j;
     }
   }
+  // sorted positions; truncated sorts: the order inside each run of equal
+  // leading bits, from the full keys of the run (in sorted order in the
+  // exchange buffer since the last pass), and the exact tie groups
+  uint32_t epos[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) epos[j] = (uint32_t)(p0 + j);
+  const bool fixup = TRUNC > 0 && tsh > 0;  // workgroup-uniform
+  if (fixup) {
+    bool tie = false;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      if (j < nv && ub[j] - lb[j] > 1u) {
+        const uint32_t k = klo[j], p = (uint32_t)(p0 + j);
+        uint32_t less = 0u, eqc = 0u, eqb = 0u;
+#pragma unroll 1
+        for (uint32_t q = lb[j]; q < ub[j]; ++q) {
+          const uint32_t kq = xk[Lds::kx((int)q)];
+          less += kq < k ? 1u : 0u;
+          eqc += kq == k ? 1u : 0u;
+          eqb += (kq == k && q < p) ? 1u : 0u;
+        }
+        epos[j] = lb[j] + less + eqb;
+        lb[j] += less;
+        ub[j] = lb[j] + eqc;
+        tie |= eqc > 1u;
+      }
+    }
+    const bool wtie = __ballot(tie) != 0ull;
+    if (lane == 0) sm.wflag()[w] = wtie ? 1 : 0;  // read after the row-order scatter
+    __syncthreads();  // the runs' keys are read before the scatter overwrites them
+  }
+  // workgroup-uniform: every row's group start equals its sorted position
+  // (and its doubled rank is 2 x position + 2: neither is stored then); after
+  // a fix-up the tie flags are read after the row-order scatter
+  bool eq = false;
+  auto read_eq = [&]() {
+    if constexpr (!ALIAS) {
+      const int f = lane < W ? sm.wflag()[lane] : 0;
+      eq = (ties == 1) || (__ballot(f != 0) == 0ull);
+    }
+  };
+  if (!fixup) read_eq();
   all_tied = (n >= 1) && (t == 0) && (ub[0] >= (uint32_t)n);
   // R, sorted position and group start, scattered to row order in LDS
   uint16_t* xl = sm.xv16();
   // (an item past the end carries a payload >= n)
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const uint32_t e = (uint32_t)(p0 + j);
+    const uint32_t e = epos[j];
     const uint32_t R = (ties == 1) ? 2u * (e + 1u) : lb[j] + ub[j] + 1u;
     const uint32_t l = (ties == 1) ? e : lb[j];
     xk[pay[j]] = R | (e << 16);
     if (!eq) xl[pay[j]] = (uint16_t)l;
   }
   __syncthreads();
+  if (fixup) read_eq();
+  e_is_l = eq;
   if (R32) {
     for (int i = t; i < n; i += T) R32[i] = xk[i] & 0xFFFFu;
   } else {
@@ -520,7 +593,8 @@ __device__ __forceinline__ bool rank_one_margin(const DT* data, int n, int ties,
   return bad;
 }
 
-template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false, bool PAD = false, bool MERGE = false>
+template <int T, int E, int B, int KW, bool ALIAS, bool P32, bool PACK = false, bool PAD = false, bool MERGE = false,
+          int TRUNC = 0>
 __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
   __shared__ RankLds<T, E, B, KW, ALIAS, P32, PAD> sm;
   const int sid = P.order[blockIdx.x];
@@ -536,21 +610,31 @@ __global__ void __launch_bounds__(T) k_rank_wg(RankParams P) {
     return;
   }
   const bool rk = P.mode == MODE_RANK;
-  bool t1, t2, b1, b2, q1, q2;
+  bool t1, t2, b1, b2, q1, q2, redo;
   const int64_t o = sd.begin;
   if constexpr (KW == 2) {
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, double>((const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o,
-                                                     P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, double>((const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o,
-                                                     P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2);
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, TRUNC, double>(
+        (const double*)P.x + o, n, P.ties, false, sm, P.rows.R1 + o, P.rows.E1 + o, P.rows.L1 + o,
+        rk ? P.R1out + o : nullptr, t1, q1, redo);
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, TRUNC, double>(
+        (const double*)P.y + o, n, P.ties, false, sm, P.rows.R2 + o, P.rows.E2 + o, P.rows.L2 + o,
+        rk ? P.R2out + o : nullptr, t2, q2, redo);
   } else {
     const bool ik = P.int_keys != 0;
     const float* xp = ik ? (const float*)((const uint32_t*)P.x + o) : (const float*)P.x + o;
     const float* yp = ik ? (const float*)((const uint32_t*)P.y + o) : (const float*)P.y + o;
-    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, float>(xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o,
-                                                    P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1);
-    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, float>(yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o,
-                                                    P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2);
+    // a truncated sort that met a long run of equal leading bits leaves the
+    // margin to the full sort
+    b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, TRUNC, float>(
+        xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1, redo);
+    if (TRUNC > 0 && redo)
+      b1 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, 0, float>(
+          xp, n, P.ties, ik, sm, P.rows.R1 + o, P.rows.E1 + o, P.rows.L1 + o, rk ? P.R1out + o : nullptr, t1, q1, redo);
+    b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, TRUNC, float>(
+        yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2, redo);
+    if (TRUNC > 0 && redo)
+      b2 = rank_one_margin<T, E, B, KW, ALIAS, P32, PACK, PAD, MERGE, 0, float>(
+          yp, n, P.ties, ik, sm, P.rows.R2 + o, P.rows.E2 + o, P.rows.L2 + o, rk ? P.R2out + o : nullptr, t2, q2, redo);
   }
   if (rk) return;
   const bool bad = b1 || b2;

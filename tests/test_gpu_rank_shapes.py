@@ -1,8 +1,12 @@
-"""Every launch shape of the workgroup rank kernel (the radix variants and the
-one-wave merge sort the autotuner chooses among), forced for the size class
-of its capacity: ranks bit-exact against the oracle for sizes spanning the
-class (ragged, powers of two and one past them), FP32 margins with ties,
-+-0, values of one sign, two values, and both tie rules; and a whole batched
+"""Every launch shape of the workgroup rank kernel (the radix variants, the
+one-wave merge sort and the truncated sorts the autotuner chooses among),
+forced for the size class of its capacity: ranks bit-exact against the
+oracle for sizes spanning the class (ragged, powers of two and one past
+them), FP32 margins with ties, +-0, values of one sign, two values, uniform
+values, a narrow cluster and a cluster a few ulps wide beside an outlier
+(long runs of equal leading bits: a truncated sort falls back to the full
+sort), values rounded to 1e-5 (exact ties inside short runs), and both tie
+rules; and a whole batched
 fit under each forced shape is bitwise identical to the built-in shapes (the
 sorted positions and tie starts are those of the stable order whatever the
 sort)."""
@@ -15,10 +19,11 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-# (threads, items) of each shape, in the library's shape order; 14 is the merge sort
+# (threads, items) of each shape, in the library's shape order; 14 is the
+# merge sort, 15 the truncated sort
 SHAPES = [(64, 8), (256, 8), (128, 16), (512, 16), (256, 32), (1024, 16), (512, 32),
           (64, 8), (256, 8), (128, 16), (512, 16), (256, 32), (1024, 16), (512, 32),
-          (64, 8)]
+          (64, 8), (64, 8)]
 CLASS_OF_CAP = {512: (1, 512), 2048: (513, 2048), 8192: (2049, 8192), 16384: (8193, 16384)}
 
 
@@ -31,7 +36,7 @@ def margins(sizes, rng):
     xs, ys = [], []
     for i, m in enumerate(sizes):
         g = rng.standard_normal(m)
-        kind = i % 5
+        kind = i % 9
         if kind == 1:
             x = np.round(g * 4) / 4                     # heavy ties
         elif kind == 2:
@@ -40,10 +45,19 @@ def margins(sizes, rng):
             x = g.copy(); x[::7] = 0.0; x[1::7] = -0.0  # signed zeros
         elif kind == 4:
             x = np.where(g > 0.3, 1.0, 2.0)             # two values
+        elif kind == 5:
+            x = rng.random(m)                           # uniform on [0, 1)
+        elif kind == 6:
+            x = 1.0 + 1e-3 * g                          # a narrow cluster
+        elif kind == 7:
+            x = np.round(g, 5)                          # exact ties among nearby values
+        elif kind == 8:
+            x = 1.0 + rng.integers(0, 64, m) * 2.0 ** -23  # a cluster a few ulps wide ...
+            x[0] = -1e4                                 # ... beside an outlier
         else:
             x = g
         xs.append(x)
-        ys.append(rng.permutation(x) + (0.0 if kind == 4 else 0.5 * rng.standard_normal(m)))
+        ys.append(rng.permutation(x) + (0.0 if kind in (4, 8) else 0.5 * rng.standard_normal(m)))
     return np.concatenate(xs).astype(np.float32), np.concatenate(ys).astype(np.float32)
 
 
@@ -88,6 +102,6 @@ def test_fit_with_forced_shapes_equals_built_in_shapes():
         got = m.fit_batched(x, y, off, gofs, ["frank"], prec="fp32c", schedule=1 + shape)
         assert np.array_equal(got.raw.cpu().numpy(), ref_raw, equal_nan=True), shape
     # graph mode, the schedule changing between calls (each schedule captures its own launches)
-    for sched in (0, 15, 0):
+    for sched in (0, 15, 16, 0):
         got = m.fit_batched(x, y, off, gofs, ["frank"], prec="fp32c", graph=True, schedule=sched)
         assert np.array_equal(got.raw.cpu().numpy(), ref_raw, equal_nan=True), sched
