@@ -10,7 +10,7 @@
 //      (16 x 16 x 4 MFMA, four rows per instruction, the k margins padded to
 //      16; each wave takes every fourth block of rows);
 //   3. l(R) = -(n/2) log det R - (1/2) tr((R^-1 - I) G) is maximised by
-//      Newton on the p correlations (thread 0, everything in LDS): with
+//      Newton on the p correlations (one wave, everything in LDS): with
 //      P = R^-1, M = P G P, dl/dr_jl = -n P_jl + M_jl and
 //      d2l/dr_jl dr_st = n (P_js P_tl + P_jt P_sl)
 //                        - (P_js M_tl + P_jt M_sl + M_js P_tl + M_jt P_sl),
@@ -85,41 +85,6 @@ __device__ __forceinline__ d4 tile_gram(const double* A, int lda, int n, int i0,
   return acc;
 }
 
-// The small dense linear algebra below runs on thread 0 with its matrices in
-// LDS; kept out of line so that it does not claim the kernel's registers.
-
-// Cholesky factor (lower, in place) of the n x n matrix A (leading dimension
-// ld); false if a pivot is not positive.
-__device__ __noinline__ bool chol(double* A, int n, int ld) {
-  for (int j = 0; j < n; ++j) {
-    double d = A[j * ld + j];
-    for (int s = 0; s < j; ++s) d -= A[j * ld + s] * A[j * ld + s];
-    if (!(d > 0.0)) return false;
-    d = sqrt(d);
-    A[j * ld + j] = d;
-    for (int i = j + 1; i < n; ++i) {
-      double v = A[i * ld + j];
-      for (int s = 0; s < j; ++s) v -= A[i * ld + s] * A[j * ld + s];
-      A[i * ld + j] = v / d;
-    }
-  }
-  return true;
-}
-
-// Solve L L' x = b in place (b overwritten by x).
-__device__ __noinline__ void chol_solve(const double* L, int n, int ld, double* b) {
-  for (int i = 0; i < n; ++i) {
-    double v = b[i];
-    for (int s = 0; s < i; ++s) v -= L[i * ld + s] * b[s];
-    b[i] = v / L[i * ld + i];
-  }
-  for (int i = n - 1; i >= 0; --i) {
-    double v = b[i];
-    for (int s = i + 1; s < n; ++s) v -= L[s * ld + i] * b[s];
-    b[i] = v / L[i * ld + i];
-  }
-}
-
 struct GkShared {
   double tiles[GW][16][16];  // per-wave MFMA tiles, reduced into G / J / Omega
   double G[KMAX][KMAX];
@@ -129,7 +94,7 @@ struct GkShared {
   double J[PPAD][PPAD];
   double Om[PPAD][PPAD];
   double Hm[PMAX][PMAX];
-  double th[PMAX], g[PMAX], st[PMAX], mu[PPAD], cand[PMAX], e[PMAX];
+  double th[PMAX], g[PMAX], st[PMAX], mu[PPAD], cand[PMAX];
   double L[KMAX][KMAX], PG[KMAX][KMAX];
   double scal[4];  // loglik, status, iterations
   double tot[GT][KMAX];
@@ -137,61 +102,188 @@ struct GkShared {
   unsigned int mm[2 * KMAX];
 };
 
-// R from theta (thread 0)
-__device__ __noinline__ void corr_from(GkShared& S, const double* th, int k) {
-  int q = 0;
-  for (int j = 0; j < k; ++j) {
-    S.Rm[j][j] = 1.0;
-    for (int l = j + 1; l < k; ++l, ++q) S.Rm[j][l] = S.Rm[l][j] = th[q];
+// The small dense linear algebra below runs on wave 0 with its matrices in
+// LDS; its lanes take the rows, entries or right-hand sides of each step.
+
+// Orders one wave's LDS operations around a hand-off between its lanes (a
+// wave's LDS operations are performed in program order; the fences keep the
+// compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Cholesky factor (lower, in place) of the N x N matrix A (leading dimension
+// LD), right-looking: per column the pivot, the column divided by its square
+// root, then the lanes update the trailing lower triangle. Every entry sees
+// the subtractions of the column-by-column form, in the same order. False
+// (in every lane) if a pivot is not positive.
+template <int N, int LD>
+__device__ __noinline__ bool wave_chol(double* A) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll 1
+  for (int j = 0; j < N; ++j) {
+    const double d = A[j * LD + j];
+    if (!(d > 0.0)) return false;  // the same value in every lane
+    const double sd = sqrt(d);
+    for (int i = j + 1 + lane; i < N; i += WAVE) A[i * LD + j] /= sd;
+    if (lane == 0) A[j * LD + j] = sd;
+    wave_sync();
+    const int m = N - j - 1;
+    for (int idx = lane; idx < m * m; idx += WAVE) {
+      const int i = j + 1 + idx / m, c = j + 1 + idx % m;
+      if (c <= i) A[i * LD + c] -= A[i * LD + j] * A[c * LD + j];
+    }
+    wave_sync();
+  }
+  return true;
+}
+
+// Solve L L' x = b in place (b: N entries in LDS), by columns: each solved
+// entry is subtracted from the later (then the earlier) ones by the lanes.
+template <int N, int LD>
+__device__ __noinline__ void wave_chol_solve(const double* L, double* b) {
+  const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) {
+    const double xi = b[i] / L[i * LD + i];
+    for (int r = i + 1 + lane; r < N; r += WAVE) b[r] -= L[r * LD + i] * xi;
+    if (lane == 0) b[i] = xi;
+    wave_sync();
+  }
+#pragma unroll 1
+  for (int i = N - 1; i >= 0; --i) {
+    const double xi = b[i] / L[i * LD + i];
+    for (int r = lane; r < i; r += WAVE) b[r] -= L[i * LD + r] * xi;
+    if (lane == 0) b[i] = xi;
+    wave_sync();
   }
 }
 
-// Is the correlation matrix of th positive definite? (thread 0; uses M as scratch)
-__device__ __noinline__ bool corr_pd(GkShared& S, const double* th, int k) {
-  corr_from(S, th, k);
-  for (int j = 0; j < k; ++j)
-    for (int l = 0; l < k; ++l) S.M[j][l] = S.Rm[j][l];
-  return chol(&S.M[0][0], k, KMAX);
+// Solve L L' x = e_c for the lane's column c (x in registers; L in LDS,
+// read by every lane alike).
+template <int N, int LD>
+__device__ __forceinline__ void lane_chol_solve_unit(const double* L, int c, double (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double v = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int s = 0; s < i; ++s) v -= L[i * LD + s] * x[s];
+    x[i] = v / L[i * LD + i];
+  }
+#pragma unroll
+  for (int i = N - 1; i >= 0; --i) {
+    double v = x[i];
+#pragma unroll
+    for (int s = i + 1; s < N; ++s) v -= L[s * LD + i] * x[s];
+    x[i] = v / L[i * LD + i];
+  }
 }
 
-// P = R^-1, M = P G P and log det R (thread 0; R in S.Rm, positive definite)
-__device__ __noinline__ double inverse_and_m(GkShared& S, int k) {
-  for (int j = 0; j < k; ++j)
-    for (int l = 0; l < k; ++l) S.L[j][l] = S.Rm[j][l];
-  chol(&S.L[0][0], k, KMAX);
+// The same, in place in column c of X (leading dimension LDX, in LDS): for
+// right-hand sides too many for registers.
+template <int N, int LD, int LDX>
+__device__ __noinline__ void lane_chol_solve_unit_lds(const double* L, int c, double* X) {
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) {
+    double v = (i == c) ? 1.0 : 0.0;
+    for (int s = 0; s < i; ++s) v -= L[i * LD + s] * X[s * LDX + c];
+    X[i * LDX + c] = v / L[i * LD + i];
+  }
+#pragma unroll 1
+  for (int i = N - 1; i >= 0; --i) {
+    double v = X[i * LDX + c];
+    for (int s = i + 1; s < N; ++s) v -= L[s * LD + i] * X[s * LDX + c];
+    X[i * LDX + c] = v / L[i * LD + i];
+  }
+}
+
+// index of parameter (j, l), j < l, in the order (0,1), (0,2), ..., (k-2,k-1)
+template <int KD>
+__device__ __forceinline__ int pidx_of(int j, int l) {
+  return j * (2 * KD - j - 1) / 2 + (l - j - 1);
+}
+
+// R from theta into dst (k x k, leading dimension KMAX)
+template <int KD>
+__device__ void wave_corr_from(double (*dst)[KMAX], const double* th) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (lane < KD * KD) {
+    const int j = lane / KD, l = lane % KD;
+    dst[j][l] = (j == l) ? 1.0 : th[j < l ? pidx_of<KD>(j, l) : pidx_of<KD>(l, j)];
+  }
+  wave_sync();
+}
+
+// Is the correlation matrix of th positive definite? (M as scratch)
+template <int KD>
+__device__ __noinline__ bool wave_corr_pd(GkShared& S, const double* th) {
+  wave_corr_from<KD>(S.M, th);
+  return wave_chol<KD, KMAX>(&S.M[0][0]);
+}
+
+// From R in S.Rm (positive definite): P = R^-1, M = P G P; returns log det R
+// (in every lane)
+template <int KD>
+__device__ __noinline__ double wave_inverse_and_m(GkShared& S) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (lane < KD * KD) S.L[lane / KD][lane % KD] = S.Rm[lane / KD][lane % KD];
+  wave_sync();
+  wave_chol<KD, KMAX>(&S.L[0][0]);
   double logdet = 0.0;
-  for (int j = 0; j < k; ++j) logdet += 2.0 * log(S.L[j][j]);
-  for (int c = 0; c < k; ++c) {
-    for (int j = 0; j < k; ++j) S.e[j] = (j == c) ? 1.0 : 0.0;
-    chol_solve(&S.L[0][0], k, KMAX, S.e);
-    for (int j = 0; j < k; ++j) S.P[j][c] = S.e[j];
+#pragma unroll
+  for (int j = 0; j < KD; ++j) logdet += 2.0 * log(S.L[j][j]);
+  if (lane < KD) {
+    double x[KD];
+    lane_chol_solve_unit<KD, KMAX>(&S.L[0][0], lane, x);
+#pragma unroll
+    for (int j = 0; j < KD; ++j) S.P[j][lane] = x[j];
   }
-  for (int j = 0; j < k; ++j)
-    for (int l = 0; l < k; ++l) {
-      double v = 0.0;
-      for (int s = 0; s < k; ++s) v += S.P[j][s] * S.G[s][l];
-      S.PG[j][l] = v;
-    }
-  for (int j = 0; j < k; ++j)
-    for (int l = 0; l < k; ++l) {
-      double v = 0.0;
-      for (int s = 0; s < k; ++s) v += S.PG[j][s] * S.P[s][l];
-      S.M[j][l] = v;
-    }
+  wave_sync();
+  if (lane < KD * KD) {
+    const int j = lane / KD, l = lane % KD;
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < KD; ++s) v += S.P[j][s] * S.G[s][l];
+    S.PG[j][l] = v;
+  }
+  wave_sync();
+  if (lane < KD * KD) {
+    const int j = lane / KD, l = lane % KD;
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < KD; ++s) v += S.PG[j][s] * S.P[s][l];
+    S.M[j][l] = v;
+  }
+  wave_sync();
   return logdet;
 }
 
-// gradient and Hessian of l at R (thread 0; after inverse_and_m)
-__device__ __noinline__ void grad_hess(GkShared& S, int p, double dn) {
-  for (int a = 0; a < p; ++a) {
-    const int j = S.pj[a], l = S.pl[a];
-    S.g[a] = -dn * S.P[j][l] + S.M[j][l];
-    for (int b = 0; b < p; ++b) {
-      const int s = S.pj[b], t = S.pl[b];
-      S.Hm[a][b] = dn * (S.P[j][s] * S.P[t][l] + S.P[j][t] * S.P[s][l]) -
-                   (S.P[j][s] * S.M[t][l] + S.P[j][t] * S.M[s][l] + S.M[j][s] * S.P[t][l] + S.M[j][t] * S.P[s][l]);
-    }
+// gradient of l into S.g and the negated Hessian into S.Hm (after
+// wave_inverse_and_m)
+template <int KD>
+__device__ __noinline__ void wave_grad_neg_hess(GkShared& S, double dn) {
+  constexpr int p = KD * (KD - 1) / 2;
+  const int lane = threadIdx.x & (WAVE - 1);
+  for (int a = lane; a < p; a += WAVE) S.g[a] = -dn * S.P[S.pj[a]][S.pl[a]] + S.M[S.pj[a]][S.pl[a]];
+  for (int idx = lane; idx < p * p; idx += WAVE) {
+    const int a = idx / p, b = idx % p;
+    const int j = S.pj[a], l = S.pl[a], s = S.pj[b], t = S.pl[b];
+    const double h = dn * (S.P[j][s] * S.P[t][l] + S.P[j][t] * S.P[s][l]) -
+                     (S.P[j][s] * S.M[t][l] + S.P[j][t] * S.M[s][l] + S.M[j][s] * S.P[t][l] + S.M[j][t] * S.P[s][l]);
+    S.Hm[a][b] = -h;
   }
+  wave_sync();
 }
 
 // the workgroup's four wave tiles summed into dst[i0 + i][j0 + j] (i, j < 16)
@@ -287,40 +379,43 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
     __syncthreads();
   }
 
-  // 3. Newton (thread 0)
-  if (t == 0) {
+  // 3. Newton (wave 0; the other waves wait at the barrier after it)
+  if (t < WAVE) {
+    const int lane = t;
     int status = ST_OK, it = 0;
-    {
-      double d[KMAX];
-      for (int j = 0; j < k; ++j) d[j] = sqrt(S.G[j][j]);
-      for (int q = 0; q < p; ++q) S.th[q] = S.G[S.pj[q]][S.pl[q]] / (d[S.pj[q]] * d[S.pl[q]]);
+    for (int q = lane; q < p; q += WAVE) {
+      const int j = S.pj[q], l = S.pl[q];
+      S.th[q] = S.G[j][l] / (sqrt(S.G[j][j]) * sqrt(S.G[l][l]));
     }
-    if (!corr_pd(S, S.th, k)) {
+    wave_sync();
+    if (!wave_corr_pd<KD>(S, S.th)) {
       status = ST_BOUNDARY_BOX;
     } else {
       status = ST_NOCONV;
       for (it = 1; it <= 100; ++it) {
-        corr_from(S, S.th, k);
-        inverse_and_m(S, k);
-        grad_hess(S, p, dn);
-        for (int a = 0; a < p; ++a)
-          for (int b = 0; b < p; ++b) S.Hm[a][b] = -S.Hm[a][b];
-        if (!chol(&S.Hm[0][0], p, PMAX)) break;  // NOCONV
-        for (int a = 0; a < p; ++a) S.st[a] = S.g[a];
-        chol_solve(&S.Hm[0][0], p, PMAX, S.st);
+        wave_corr_from<KD>(S.Rm, S.th);
+        wave_inverse_and_m<KD>(S);
+        wave_grad_neg_hess<KD>(S, dn);
+        if (!wave_chol<p, PMAX>(&S.Hm[0][0])) break;  // NOCONV
+        for (int a = lane; a < p; a += WAVE) S.st[a] = S.g[a];
+        wave_sync();
+        wave_chol_solve<p, PMAX>(&S.Hm[0][0], S.st);
         double lam = 1.0;
         for (int h = 0; h < 30; ++h) {
-          for (int a = 0; a < p; ++a) S.cand[a] = S.th[a] + lam * S.st[a];
-          if (corr_pd(S, S.cand, k)) break;
+          for (int a = lane; a < p; a += WAVE) S.cand[a] = S.th[a] + lam * S.st[a];
+          wave_sync();
+          if (wave_corr_pd<KD>(S, S.cand)) break;
           lam *= 0.5;
         }
         double mstep = 0.0, mth = 0.0;
-        for (int a = 0; a < p; ++a) {
+        for (int a = lane; a < p; a += WAVE) {
           mstep = fmax(mstep, fabs(lam * S.st[a]));
           mth = fmax(mth, fabs(S.th[a]));
-          S.cand[a] = S.th[a] + lam * S.st[a];
+          S.th[a] += lam * S.st[a];
         }
-        for (int a = 0; a < p; ++a) S.th[a] = S.cand[a];
+        mstep = wave_max_d(mstep);
+        mth = wave_max_d(mth);
+        wave_sync();
         if (mstep <= 1e-12 * (1.0 + mth)) {
           status = ST_OK;
           break;
@@ -330,17 +425,22 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
     }
     double ll = NAN;
     if (status == ST_OK) {
-      corr_from(S, S.th, k);
-      const double logdet = inverse_and_m(S, k);
-      grad_hess(S, p, dn);
+      wave_corr_from<KD>(S.Rm, S.th);
+      const double logdet = wave_inverse_and_m<KD>(S);
+      wave_grad_neg_hess<KD>(S, dn);
       double tr = 0.0;
-      for (int j = 0; j < k; ++j)
-        for (int l = 0; l < k; ++l) tr += (S.P[j][l] - (j == l ? 1.0 : 0.0)) * S.G[l][j];
+      if (lane < KD * KD) {
+        const int j = lane / KD, l = lane % KD;
+        tr = (S.P[j][l] - (j == l ? 1.0 : 0.0)) * S.G[l][j];
+      }
+      tr = wave_sum_d(tr);
       ll = -0.5 * dn * logdet - 0.5 * tr;
     }
-    S.scal[0] = ll;
-    S.scal[1] = (double)status;
-    S.scal[2] = (double)it;
+    if (lane == 0) {
+      S.scal[0] = ll;
+      S.scal[1] = (double)status;
+      S.scal[2] = (double)it;
+    }
   }
   __syncthreads();
   const int status = (int)S.scal[1];
@@ -408,12 +508,25 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
 #pragma unroll 4
     for (int64_t b = b0; b < b1; ++b)
       for (int j = 0; j < k; ++j) run[j] += Bn[b * k + j];
-    for (int j = 0; j < k; ++j) S.tot[t][j] = run[j];
-    __syncthreads();
+    // the totals of the later threads: suffix sums within the wave
+    // (shuffles), then the later waves' totals through LDS
     double acc[KMAX];
-    for (int j = 0; j < k; ++j) acc[j] = 0.0;
-    for (int u = t + 1; u < GT; ++u)
-      for (int j = 0; j < k; ++j) acc[j] += S.tot[u][j];
+    {
+      const int lane = t & (WAVE - 1), w = t / WAVE;
+      for (int j = 0; j < k; ++j) {
+        double v = run[j];
+        for (int d = 1; d < WAVE; d <<= 1) {
+          const double o2 = __shfl_down(v, d, WAVE);
+          if (lane + d < WAVE) v += o2;
+        }
+        const double nxt = __shfl_down(v, 1, WAVE);
+        acc[j] = (lane + 1 < WAVE) ? nxt : 0.0;
+        if (lane == 0) S.tot[w][j] = v;
+      }
+      __syncthreads();
+      for (int j = 0; j < k; ++j)
+        for (int u = w + 1; u < GW; ++u) acc[j] += S.tot[u][j];
+    }
 #pragma unroll 4
     for (int64_t b = b1 - 1; b >= b0; --b)
       for (int j = 0; j < k; ++j) {
@@ -454,21 +567,23 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
     __syncthreads();
   }
 
-  // 7. V = J^-1 Omega J^-1 / n (thread 0 inverts J; thread q forms V_qq)
-  if (t == 0) {
-    for (int a = 0; a < p; ++a)
-      for (int b = 0; b < p; ++b) {
-        S.J[a][b] *= inv_n;
-        S.Om[a][b] = S.Om[a][b] * inv_n - S.mu[a] * S.mu[b];
+  // 7. V = J^-1 Omega J^-1 / n (wave 0 factors J, lane c solves column c of
+  //    its inverse; thread q forms V_qq)
+  for (int idx = t; idx < p * p; idx += GT) {
+    const int a = idx / p, b = idx % p;
+    S.J[a][b] *= inv_n;
+    S.Om[a][b] = S.Om[a][b] * inv_n - S.mu[a] * S.mu[b];
+    S.Hm[a][b] = S.J[a][b];
+  }
+  __syncthreads();
+  if (t < WAVE) {
+    const bool ok = wave_chol<p, PMAX>(&S.Hm[0][0]);
+    if (t < p) {
+      if (ok) {
+        lane_chol_solve_unit_lds<p, PMAX, PPAD>(&S.Hm[0][0], t, &S.J[0][0]);
+      } else {
+        for (int a = 0; a < p; ++a) S.J[a][t] = NAN;
       }
-    // J^-1 into Hm (Cholesky of J in tiles-free scratch: reuse Hm rows)
-    for (int a = 0; a < p; ++a)
-      for (int b = 0; b < p; ++b) S.Hm[a][b] = S.J[a][b];
-    const bool ok = chol(&S.Hm[0][0], p, PMAX);
-    for (int c = 0; c < p; ++c) {
-      for (int a = 0; a < p; ++a) S.e[a] = (a == c) ? 1.0 : 0.0;
-      if (ok) chol_solve(&S.Hm[0][0], p, PMAX, S.e);
-      for (int a = 0; a < p; ++a) S.J[a][c] = ok ? S.e[a] : NAN;
     }
   }
   __syncthreads();
