@@ -1238,7 +1238,7 @@ size_t cpc_gaussk_workspace_bytes(int64_t n, int32_t k, int64_t K, int64_t G) {
   const int64_t p = (int64_t)k * (k - 1) / 2;
   return align_up(sizeof(SubDesc) * (size_t)K) + align_up(sizeof(int64_t) * (size_t)(p * G + 1)) +
          align_up(sizeof(double) * (size_t)n * (size_t)k) + align_up(sizeof(double) * (size_t)n * (size_t)gaussk_ldx(k)) +
-         align_up(sizeof(double) * (size_t)(2 * n + 2 * K) * (size_t)k);
+         align_up(sizeof(double) * (size_t)(n + K) * (size_t)k * (size_t)k);
 }
 
 int cpc_gaussk_fit(cpc_handle_t h, const uint32_t* R, int64_t n, int32_t k, const int64_t* offsets, int64_t K,

@@ -19,10 +19,13 @@
 //   4. the sandwich variance: per row the scores s_i,jl = -P_jl + y_ij y_il
 //      (y_i = P z_i) and psi_i = s_i + sum_m W_m(u_im), W_m(u_im) the mean over
 //      the rows with u_lm >= u_im of ds_l/du_m = (P_jm y_l + y_j P_lm) /
-//      phi(z_m): for each margin m the vectors y_l / phi(z_lm) are added into
-//      bins indexed by the doubled rank (FP64 atomics; only tied rows share a
-//      bin) and suffix-summed over the bins, so a tie group takes the whole
-//      group. J = (1/n) sum s s' and Omega = cov(psi) are p x p contractions
+//      phi(z_m): in one pass over the rows the vectors y_l / phi(z_lm) are
+//      added into margin m's bins, indexed by the doubled rank, for every m
+//      (only tied rows share a bin: margins found tie-free through a bitmap
+//      of the bins in LDS take plain stores, the others FP64 atomics), the
+//      bins are suffix-summed
+//      (a tie group takes the whole group), and one more pass forms each
+//      row's psi from the bins at its ranks. J = (1/n) sum s s' and Omega = cov(psi) are p x p contractions
 //      over the rows, again on the FP64 MFMA (p padded to 16 or 32: one or
 //      three 16 x 16 tiles); V = J^-1 Omega J^-1 / n, each parameter's
 //      variance V_qq.
@@ -42,6 +45,12 @@ constexpr int GW = GT / WAVE;
 constexpr int KMAX = 8;
 constexpr int PMAX = KMAX * (KMAX - 1) / 2;  // 28
 constexpr int PPAD = 32;
+// Subsets of up to kSeenRows rows find out which margins have ties (rows
+// sharing a rank bin) from a bitmap in LDS; their tie-free margins fill the
+// bins with plain stores, every bin but bin 0 once. Larger subsets, and
+// margins with ties, add into the bins atomically.
+constexpr int kSeenWords = 6144;  // 24 KiB
+constexpr int kSeenRows = kSeenWords * 32 / KMAX - 1;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -53,7 +62,7 @@ struct GkParams {
   int64_t n_min;
   double* Z;           // rows x k (row-major), a subset's rows at its begin
   double* X;           // rows x ldx: scores, then psi
-  double* B;           // bins: subset m owns (2 n + 2) k doubles from 2 (begin + m) k
+  double* B;           // bins: subset m owns k (n + 1) k doubles from k k (begin + m) (k margins' bins)
   ResultOut* out;      // parameter-major: q K + m
   int64_t K;
 };
@@ -100,6 +109,8 @@ struct GkShared {
   double tot[GT][KMAX];
   int pj[PMAX], pl[PMAX];
   unsigned int mm[2 * KMAX];
+  unsigned int tied[KMAX];         // margin m has two rows in one rank bin
+  unsigned int seen[kSeenWords];   // per margin, one bit per rank bin (subsets of up to kSeenRows rows)
 };
 
 // The small dense linear algebra below runs on wave 0 with its matrices in
@@ -476,28 +487,68 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
   __syncthreads();
   contract(S, X, ldx, n, p, S.J);
 
-  // 5. psi = s + sum_m W_m: per margin, bins by doubled rank, suffix sums
-  double* Bn = P.B + (2 * o + 2 * (int64_t)sid) * k;
+  // 5. psi = s + sum_m W_m. One pass over the rows adds each row's
+  //    y / phi(z_m) into margin m's bins at its doubled rank, for every
+  //    margin; each margin's bins are then suffix-summed; a last pass forms
+  //    psi from s and the bins at the row's ranks, writing each row once.
   // bins floor(R / 2), 0 .. n: distinct tie groups differ by at least 2 in
   // doubled rank, so no bin holds two groups
   const int64_t NB = (int64_t)n + 1;
+  double* Bn = P.B + (o + (int64_t)sid) * k * k;  // margin m's bins at Bn + m NB k
   const double inv_n = 1.0 / dn, inv_s2pi = 0.39894228040143267794;
-  for (int m = 0; m < k; ++m) {
-    for (int64_t e = t; e < NB * k; e += GT) Bn[e] = 0.0;
+  const bool small = n <= kSeenRows;  // workgroup-uniform
+  const int wpm = (int)((NB + 31) / 32);  // bitmap words per margin
+  if (t < KMAX) S.tied[t] = small ? 0u : 1u;
+  if (small) {
+    for (int e = t; e < wpm * KD; e += GT) S.seen[e] = 0u;
     __syncthreads();
     for (int i = t; i < n; i += GT) {
-      double z[KMAX];
-      for (int j = 0; j < k; ++j) z[j] = Z[(int64_t)i * k + j];
-      const double zm = z[m];
-      const double iphi = 1.0 / (inv_s2pi * exp(-0.5 * zm * zm));
-      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i] >> 1;
-      for (int j = 0; j < k; ++j) {
-        double v = 0.0;
-        for (int l = 0; l < k; ++l) v += S.P[j][l] * z[l];
-        unsafeAtomicAdd(&Bn[(int64_t)r * k + j], v * iphi);  // the hardware FP64 add (device memory)
+#pragma unroll
+      for (int m = 0; m < KD; ++m) {
+        const uint32_t r = P.R[(int64_t)m * P.n_total + o + i] >> 1;
+        const uint32_t bit = 1u << (r & 31u);
+        const uint32_t old = atomicOr(&S.seen[m * wpm + (int)(r >> 5)], bit);
+        if (old & bit) S.tied[m] = 1u;
       }
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  // clear the bins that stores will not cover: all of a margin with ties (or
+  // of a large subset), bin 0 of the others
+  for (int m = 0; m < KD; ++m) {
+    double* Bm = Bn + (int64_t)m * NB * KD;
+    const int64_t len = S.tied[m] ? NB * KD : KD;
+    for (int64_t e = t; e < len; e += GT) Bm[e] = 0.0;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += GT) {
+    double z[KD], y[KD];
+#pragma unroll
+    for (int j = 0; j < KD; ++j) z[j] = Z[(int64_t)i * KD + j];
+#pragma unroll
+    for (int j = 0; j < KD; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int l = 0; l < KD; ++l) v += S.P[j][l] * z[l];
+      y[j] = v;
+    }
+#pragma unroll
+    for (int m = 0; m < KD; ++m) {
+      const double iphi = 1.0 / (inv_s2pi * exp(-0.5 * z[m] * z[m]));
+      const uint32_t r = P.R[(int64_t)m * P.n_total + o + i] >> 1;
+      double* bm = Bn + ((int64_t)m * NB + r) * KD;
+      if (S.tied[m]) {  // workgroup-uniform
+#pragma unroll
+        for (int j = 0; j < KD; ++j) unsafeAtomicAdd(&bm[j], y[j] * iphi);  // the hardware FP64 add (device memory)
+      } else {
+#pragma unroll
+        for (int j = 0; j < KD; ++j) bm[j] = y[j] * iphi;
+      }
+    }
+  }
+  __syncthreads();
+  for (int m = 0; m < KD; ++m) {
+    double* Bm = Bn + (int64_t)m * NB * KD;
     // suffix sums over the bins: thread t takes bins [t C, (t + 1) C)
     const int64_t C = (NB + GT - 1) / GT;
     const int64_t b0 = t * C, b1 = min(b0 + C, NB);
@@ -507,7 +558,7 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
     for (int j = 0; j < k; ++j) run[j] = 0.0;
 #pragma unroll 4
     for (int64_t b = b0; b < b1; ++b)
-      for (int j = 0; j < k; ++j) run[j] += Bn[b * k + j];
+      for (int j = 0; j < k; ++j) run[j] += Bm[b * k + j];
     // the totals of the later threads: suffix sums within the wave
     // (shuffles), then the later waves' totals through LDS
     double acc[KMAX];
@@ -530,23 +581,36 @@ __global__ void __launch_bounds__(GT, 2) k_gaussk(GkParams P) {
 #pragma unroll 4
     for (int64_t b = b1 - 1; b >= b0; --b)
       for (int j = 0; j < k; ++j) {
-        acc[j] += Bn[b * k + j];
-        Bn[b * k + j] = acc[j];
+        acc[j] += Bm[b * k + j];
+        Bm[b * k + j] = acc[j];
       }
     __syncthreads();
-    for (int i = t; i < n; i += GT) {
+  }
+  for (int i = t; i < n; i += GT) {
+    double* xi = X + (int64_t)i * ldx;
+    double psi[p];
+#pragma unroll
+    for (int q = 0; q < p; ++q) psi[q] = xi[q];
+#pragma unroll 1
+    for (int m = 0; m < KD; ++m) {
       const uint32_t r = P.R[(int64_t)m * P.n_total + o + i] >> 1;
-      double A[KMAX];
-      for (int j = 0; j < k; ++j) A[j] = Bn[(int64_t)r * k + j] * inv_n;
-      double* xi = X + (int64_t)i * ldx;
+      const double* bm = Bn + ((int64_t)m * NB + r) * KD;
+      double A[KD], Pm[KD];
+#pragma unroll
+      for (int j = 0; j < KD; ++j) {
+        A[j] = bm[j] * inv_n;
+        Pm[j] = S.P[j][m];
+      }
       int q = 0;
 #pragma unroll
-      for (int j = 0; j < k; ++j)
+      for (int j = 0; j < KD; ++j)
 #pragma unroll
-        for (int l = j + 1; l < k; ++l, ++q) xi[q] += S.P[j][m] * A[l] + A[j] * S.P[l][m];
+        for (int l = j + 1; l < KD; ++l, ++q) psi[q] += Pm[j] * A[l] + A[j] * Pm[l];
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < p; ++q) xi[q] = psi[q];
   }
+  __syncthreads();
 
   // 6. Omega = X'X / n - mean mean'
   contract(S, X, ldx, n, p, S.Om);
