@@ -1122,7 +1122,8 @@ size_t cpc_spearman_workspace_bytes(int64_t n, int64_t K, int64_t G) {
 size_t cpc_kendall_workspace_bytes(int64_t n, int64_t K, int64_t G) {
   if (n < 0 || K < 1 || G < 1) return 0;
   return align_up(sizeof(SubDesc) * (size_t)K) + align_up(sizeof(int64_t) * (size_t)(G + 1)) +
-         2 * align_up(sizeof(unsigned long long) * (size_t)n) + align_up(sizeof(int) * (size_t)n);
+         2 * align_up(sizeof(unsigned long long) * (size_t)n) + align_up(sizeof(int) * (size_t)n) +
+         align_up(sizeof(int) * (size_t)K);
 }
 
 namespace {
@@ -1172,12 +1173,15 @@ int moment_fit(bool kendall, cpc_handle_t h, const uint32_t* R1, const uint32_t*
   unsigned long long* W0 = nullptr;
   unsigned long long* W1 = nullptr;
   int* C = nullptr;
+  int* flag = nullptr;
   if (kendall) {
     W0 = (unsigned long long*)b;
     b += align_up(sizeof(unsigned long long) * (size_t)n);
     W1 = (unsigned long long*)b;
     b += align_up(sizeof(unsigned long long) * (size_t)n);
     C = (int*)b;
+    b += align_up(sizeof(int) * (size_t)n);
+    flag = (int*)b;
   } else {
     H1 = (long long*)b;
     b += align_up(sizeof(long long) * 2 * (size_t)(n + K));
@@ -1199,7 +1203,7 @@ int moment_fit(bool kendall, cpc_handle_t h, const uint32_t* R1, const uint32_t*
     const int64_t m0 = group_offsets[g], m1 = group_offsets[h2];
     if (m1 > m0) {
       if (kendall)
-        HIP_OK(launch_kendall(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, W0, W1, C,
+        HIP_OK(launch_kendall(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, W0, W1, C, flag,
                               (ResultOut*)out, s));
       else
       {

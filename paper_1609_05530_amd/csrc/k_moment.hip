@@ -37,6 +37,7 @@
 // Frank tau = 1 - 4 (1 - D1(theta)) / theta by the workgroup Newton.
 #include <hip/hip_runtime.h>
 
+#include "block_rank.h"
 #include "kernels.h"
 
 namespace cpc {
@@ -106,6 +107,7 @@ struct MomParams {
   unsigned long long* W0;
   unsigned long long* W1;
   int* C;
+  int* flag;  // per subset of the launch (Kendall): 0 done, 1 left to the workspace kernel, 2 sums in W0
 };
 
 enum { KIND_SPEARMAN = 0, KIND_KENDALL = 1 };
@@ -482,6 +484,65 @@ __device__ __forceinline__ void merge_level(const unsigned long long* src, unsig
   }
 }
 
+// tau and theta from the exact sums S1 = sum_i S_i and S2 = sum_i S_i^2, the
+// U-statistic variance, and the subset's result (thread 0 writes it)
+template <int FAM, int W>
+__device__ void kendall_finish(long long S1, long long S2, int n, double* red, double* bc, ResultOut r,
+                               ResultOut* out) {
+  const int t = threadIdx.x;
+  const double dn = (double)n, dn1 = (double)(n - 1);
+  double tau = 0.0, zeta = 0.0;
+  if (t == 0) {
+    tau = (double)S1 / (dn * dn1);
+    zeta = (double)S2 / (dn * dn1 * dn1) - tau * tau;
+    bc[0] = tau;
+  }
+  __syncthreads();
+  tau = bc[0];
+  __syncthreads();
+
+  // theta with tau(theta) = tau
+  double th = 0.0, slope = 0.0, fit = 0.0;
+  int it = 0, status = ST_OK;
+  constexpr double PI = 3.14159265358979323846;
+  if constexpr (FAM == FAM_GAUSSIAN) {
+    th = sin(0.5 * PI * tau);
+    const double edge = 1.0 - 1e-9;
+    if (th <= -edge) { status = ST_BOUNDARY_BOX; th = -edge; }
+    if (th >= edge) { status = ST_BOUNDARY_BOX; th = edge; }
+    slope = 2.0 / (PI * sqrt(1.0 - th * th));
+    fit = 2.0 / PI * asin(th);
+  } else if constexpr (FAM == FAM_GUMBEL) {
+    if (tau <= 0.0) {
+      status = ST_BOUNDARY_NATURAL;
+      th = 1.0;
+    } else if (tau >= 1.0 - 1.0 / 100.0) {
+      status = ST_BOUNDARY_BOX;
+      th = 100.0;
+    } else {
+      th = 1.0 / (1.0 - tau);
+    }
+    slope = 1.0 / (th * th);
+    fit = 1.0 - 1.0 / th;
+  } else {
+    th = fmin(fmax(4.0 * tau / (1.0 - fabs(tau)) + 5.0 * tau, -150.0), 150.0);
+    newton_invert<FAM, KIND_KENDALL, W>(tau, th, slope, fit, it, status, red, bc);
+  }
+  if (t == 0) {
+    r.theta = th;
+    r.loglik = tau;
+    r.score = fit - tau;
+    r.iters = it;
+    r.status = status;
+    if (status == ST_OK || status == ST_BOUNDARY_NATURAL) {
+      const double var = 4.0 * zeta / (dn * slope * slope);
+      r.var = var;
+      if (!(var > 0.0 && isfinite(var))) r.status = ST_BADVAR;
+    }
+    *out = r;
+  }
+}
+
 template <int FAM>
 __global__ void __launch_bounds__(MT) k_kendall(MomParams P) {
   constexpr int W = MT / WAVE;
@@ -490,12 +551,18 @@ __global__ void __launch_bounds__(MT) k_kendall(MomParams P) {
   __shared__ unsigned int mm[4];
   __shared__ double bc[4];
   const int sid = blockIdx.x, t = threadIdx.x;
+  const int flag = P.flag[sid];
+  if (flag == 0) return;  // done in LDS (a degenerate subset)
   const SubDesc sd = P.subs[sid];
   const int n = sd.n;
   const int64_t o = sd.begin;
   ResultOut r;
   r.theta = NAN; r.var = NAN; r.loglik = NAN; r.score = NAN;
   r.n = n; r.iters = 0; r.status = ST_OK;
+  if (flag == 2) {  // the sums from the LDS kernel
+    kendall_finish<FAM, W>((long long)P.W0[o], (long long)P.W0[o + 1], n, red, bc, r, P.out + sid);
+    return;
+  }
   if (n < P.n_min || n < 2) {
     if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; }
     return;
@@ -595,56 +662,244 @@ __global__ void __launch_bounds__(MT) k_kendall(MomParams P) {
   }
   const long long S1 = block_sum_ll<W>(s1, redl);
   const long long S2 = block_sum_ll<W>(s2, redl);
-  const double dn = (double)n, dn1 = (double)(n - 1);
-  double tau = 0.0, zeta = 0.0;
-  if (t == 0) {
-    tau = (double)S1 / (dn * dn1);
-    zeta = (double)S2 / (dn * dn1 * dn1) - tau * tau;
-    bc[0] = tau;
-  }
-  __syncthreads();
-  tau = bc[0];
-  __syncthreads();
+  kendall_finish<FAM, W>(S1, S2, n, red, bc, r, P.out + sid);
+}
 
-  // theta with tau(theta) = tau
-  double th = 0.0, slope = 0.0, fit = 0.0;
-  int it = 0, status = ST_OK;
-  constexpr double PI = 3.14159265358979323846;
-  if constexpr (FAM == FAM_GAUSSIAN) {
-    th = sin(0.5 * PI * tau);
-    const double edge = 1.0 - 1e-9;
-    if (th <= -edge) { status = ST_BOUNDARY_BOX; th = -edge; }
-    if (th >= edge) { status = ST_BOUNDARY_BOX; th = edge; }
-    slope = 2.0 / (PI * sqrt(1.0 - th * th));
-    fit = 2.0 / PI * asin(th);
-  } else if constexpr (FAM == FAM_GUMBEL) {
-    if (tau <= 0.0) {
-      status = ST_BOUNDARY_NATURAL;
-      th = 1.0;
-    } else if (tau >= 1.0 - 1.0 / 100.0) {
-      status = ST_BOUNDARY_BOX;
-      th = 100.0;
-    } else {
-      th = 1.0 / (1.0 - tau);
+// The Kendall estimator in LDS, for subsets of up to KL rows (1024 threads,
+// KE rows each); the others, and subsets with a tie group of more than
+// kKendallTieMax rows in the first margin, are flagged for the workspace
+// kernel above, which runs after it on the same subsets and takes the
+// inversion of the others from their sums S and S^2 (left in the subset's
+// first two words of the workspace). Same counts, in 32-bit words:
+//   1. the rows in (a, b, row) order without a sort: a histogram of a's bins
+//      floor(a / 2) (distinct tie groups never share one) gives each group
+//      its first position; the rows of a group (mostly one) are put in
+//      (b, row) order by counting, within the group, the (b, row) keys below
+//      theirs, which also gives the runs of equal a and of equal (a, b);
+//   2. the sign counts by a merge sort of (b << 14 | p) in place: at each
+//      level every thread reads its words, finds their destinations and,
+//      for right-run words, the left words of smaller value by binary
+//      searches stepped together, then after a barrier writes them back and
+//      adds 2 (#left < b - #left > b) to C[p].
+constexpr int KT = 1024;
+constexpr int KL = 16384;
+constexpr int KE = KL / KT;
+constexpr int kKendallTieMax = 32;
+
+// cnt[v] = number of entries of A[base[v] .. base[v] + len[v]) below x[v]
+// (sorted ascending), the V searches stepped together
+template <int V>
+__device__ __forceinline__ void lds_lower_counts(const uint32_t* A, const int (&base)[V], const int (&len)[V],
+                                                 const uint32_t (&x)[V], int (&cnt)[V]) {
+  int lo[V], hi[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) { lo[v] = base[v]; hi[v] = base[v] + len[v]; }
+  while (true) {
+    bool more = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (lo[v] < hi[v]) {
+        const int mid = (lo[v] + hi[v]) >> 1;
+        if (A[mid] < x[v]) lo[v] = mid + 1; else hi[v] = mid;
+        more = true;
+      }
     }
-    slope = 1.0 / (th * th);
-    fit = 1.0 - 1.0 / th;
-  } else {
-    th = fmin(fmax(4.0 * tau / (1.0 - fabs(tau)) + 5.0 * tau, -150.0), 150.0);
-    newton_invert<FAM, KIND_KENDALL, W>(tau, th, slope, fit, it, status, red, bc);
+    if (!more) break;
   }
-  if (t == 0) {
-    r.theta = th;
-    r.loglik = tau;
-    r.score = fit - tau;
-    r.iters = it;
-    r.status = status;
-    if (status == ST_OK || status == ST_BOUNDARY_NATURAL) {
-      const double var = 4.0 * zeta / (dn * slope * slope);
-      r.var = var;
-      if (!(var > 0.0 && isfinite(var))) r.status = ST_BADVAR;
+#pragma unroll
+  for (int v = 0; v < V; ++v) cnt[v] = lo[v] - base[v];
+}
+
+template <int FAM>
+__global__ void __launch_bounds__(KT) k_kendall_lds(MomParams P) {
+  constexpr int W = KT / WAVE;
+  static_assert(KL <= (1 << 14) && KE * KT == KL, "positions fit 14 bits");
+  __shared__ uint32_t buf[KL];   // group members, then the (b << 14 | p) words
+  __shared__ int cv[KL + 1];     // bins (first position << 16 | size), then C
+  __shared__ double red[W * 4];
+  __shared__ long long redl[W];
+  __shared__ unsigned int mm[5];
+  __shared__ double bc[4];
+  const int sid = blockIdx.x, t = threadIdx.x;
+  const SubDesc sd = P.subs[sid];
+  const int n = sd.n;
+  const int64_t o = sd.begin;
+  if (n > KL) {
+    if (t == 0) P.flag[sid] = 1;
+    return;
+  }
+  ResultOut r;
+  r.theta = NAN; r.var = NAN; r.loglik = NAN; r.score = NAN;
+  r.n = n; r.iters = 0; r.status = ST_OK;
+  if (n < P.n_min || n < 2) {
+    if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; P.flag[sid] = 0; }
+    return;
+  }
+  uint32_t a[KE], b[KE];
+  if (t == 0) { mm[0] = ~0u; mm[1] = 0u; mm[2] = ~0u; mm[3] = 0u; mm[4] = 0u; }
+  for (int e = t; e <= n; e += KT) cv[e] = 0;
+  __syncthreads();
+  uint32_t a0 = ~0u, a1 = 0u, b0 = ~0u, b1 = 0u;
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int i = t + k * KT;
+    a[k] = i < n ? P.R1[o + i] : 0u;
+    b[k] = i < n ? P.R2[o + i] : 0u;
+    if (i < n) {
+      a0 = min(a0, a[k]); a1 = max(a1, a[k]); b0 = min(b0, b[k]); b1 = max(b1, b[k]);
+      atomicAdd(&cv[a[k] >> 1], 1);
     }
-    P.out[sid] = r;
+  }
+  atomicMin(&mm[0], a0); atomicMax(&mm[1], a1); atomicMin(&mm[2], b0); atomicMax(&mm[3], b1);
+  __syncthreads();
+  if (mm[0] == mm[1] || mm[2] == mm[3]) {  // workgroup-uniform
+    if (t == 0) { r.status = ST_DEGENERATE; P.out[sid] = r; P.flag[sid] = 0; }
+    return;
+  }
+  // 1. first position of every bin (exclusive scan of the counts, thread t
+  //    taking bins [t CB, (t + 1) CB)), packed with the bin's size
+  {
+    constexpr int CB = (KL + 1 + KT - 1) / KT;
+    const int c0 = t * CB;
+    int cnt[CB], run = 0, big = 0;
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      cnt[j] = (c0 + j <= n) ? cv[c0 + j] : 0;
+      run += cnt[j];
+      big = max(big, cnt[j]);
+    }
+    const int lane = t & (WAVE - 1), w = t / WAVE;
+    const uint32_t incl = wave_incl_sum_u32((uint32_t)run);
+    if (lane == WAVE - 1) redl[w] = (long long)incl;
+    if (big > kKendallTieMax) mm[4] = 1u;
+    __syncthreads();
+    long long before = 0;
+    for (int u = 0; u < w; ++u) before += redl[u];
+    int pos = (int)before + (int)(incl - (uint32_t)run);
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      if (c0 + j <= n) cv[c0 + j] = (pos << 16) | cnt[j];
+      pos += cnt[j];
+    }
+  }
+  __syncthreads();
+  if (mm[4] != 0u) {  // a long tie group: the workspace kernel
+    if (t == 0) P.flag[sid] = 1;
+    return;
+  }
+  // the group members, (b << 14 | row), in arrival order
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int i = t + k * KT;
+    if (i < n) {
+      const int slot = atomicAdd(&cv[a[k] >> 1], 1 << 16) >> 16;
+      buf[slot] = (b[k] << 14) | (uint32_t)i;
+    }
+  }
+  __syncthreads();
+  // each row's position in (a, b, row) order and the first terms of C
+  int pos[KE], c[KE];
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int i = t + k * KT;
+    pos[k] = 0;
+    c[k] = 0;
+    if (i < n) {
+      const int v = cv[a[k] >> 1];
+      const int g = v & 0xFFFF, s0 = (v >> 16) - g;
+      int less = 0, blt = 0, ble = g;
+      if (g > 1) {
+        const uint32_t key = (b[k] << 14) | (uint32_t)i;
+        ble = 0;
+        for (int q = s0; q < s0 + g; ++q) {
+          const uint32_t kq = buf[q];
+          less += kq < key ? 1 : 0;
+          blt += (kq >> 14) < b[k] ? 1 : 0;
+          ble += (kq >> 14) <= b[k] ? 1 : 0;
+        }
+      }
+      pos[k] = s0 + less;
+      // (n + 1) - b - #{same a, b < b_p} - #{same a, b > b_p}
+      c[k] = (n + 1) - (int)b[k] - blt - (g - ble);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int i = t + k * KT;
+    if (i < n) {
+      buf[pos[k]] = (b[k] << 14) | (uint32_t)pos[k];
+      cv[pos[k]] = c[k];
+    }
+  }
+  __syncthreads();
+  // 2. the sign counts: merge sort of (b << 14 | p), in place
+  int lg = 0;
+  for (int L = 1; L < n; L <<= 1, ++lg) {
+    uint32_t wd[KE];
+    int base[KE], len[KE], cnt[KE], dst[KE];
+    bool right[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int p = t + k * KT;
+      wd[k] = 0u;
+      base[k] = 0;
+      len[k] = 0;
+      right[k] = false;
+      if (p < n) {
+        wd[k] = buf[p];
+        const int rr = p >> lg, start = rr << lg;
+        if (rr & 1) {
+          right[k] = true;
+          base[k] = start - L;
+          len[k] = L;
+        } else if (start + L < n) {
+          base[k] = start + L;
+          len[k] = min(L, n - start - L);
+        }
+      }
+    }
+    lds_lower_counts<KE>(buf, base, len, wd, cnt);
+    uint32_t xb[KE];
+    int len2[KE], lt[KE];
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int p = t + k * KT;
+      dst[k] = p + cnt[k];
+      if (right[k]) {
+        const int start = (p >> lg) << lg;
+        dst[k] = start - L + (p - start) + cnt[k];  // cnt: left words below, values <= this one's
+      }
+      xb[k] = (wd[k] >> 14) << 14;
+      len2[k] = (p < n && right[k]) ? cnt[k] : 0;
+    }
+    lds_lower_counts<KE>(buf, base, len2, xb, lt);  // left values below this one's
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KE; ++k) {
+      const int p = t + k * KT;
+      if (p < n) {
+        buf[dst[k]] = wd[k];
+        if (right[k]) cv[wd[k] & 0x3FFFu] += 2 * (lt[k] - (L - cnt[k]));
+      }
+    }
+    __syncthreads();
+  }
+  // 3. sum S and S^2 (exact)
+  long long s1 = 0, s2 = 0;
+  for (int p = t; p < n; p += KT) {
+    const long long v = cv[p];
+    s1 += v;
+    s2 += v * v;
+  }
+  const long long S1 = block_sum_ll<W>(s1, redl);
+  const long long S2 = block_sum_ll<W>(s2, redl);
+  // the inversion (a Newton iteration with workgroup quadrature for Frank)
+  // runs in the workspace kernel, whose small workgroups share a CU
+  if (t == 0) {
+    P.W0[o] = (unsigned long long)S1;
+    P.W0[o + 1] = (unsigned long long)S2;
+    P.flag[sid] = 2;
   }
 }
 
@@ -652,12 +907,19 @@ __global__ void __launch_bounds__(MT) k_kendall(MomParams P) {
 
 hipError_t launch_kendall(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
                           int64_t K, int64_t n_min, unsigned long long* W0, unsigned long long* W1, int* C,
-                          ResultOut* out, hipStream_t s) {
+                          int* flag, ResultOut* out, hipStream_t s) {
   MomParams p = {};
   p.R1 = R1; p.R2 = R2; p.subs = subs + base; p.n_min = n_min; p.base = base;
   p.out = out + base;
-  p.W0 = W0; p.W1 = W1; p.C = C;
+  p.W0 = W0; p.W1 = W1; p.C = C; p.flag = flag + base;
   if (K <= 0) return hipSuccess;
+  // subsets of up to KL rows in LDS; the rest (flagged) in the workspace
+  switch (fam) {
+    case FAM_GAUSSIAN: hipLaunchKernelGGL(k_kendall_lds<FAM_GAUSSIAN>, dim3((unsigned)K), dim3(KT), 0, s, p); break;
+    case FAM_FRANK: hipLaunchKernelGGL(k_kendall_lds<FAM_FRANK>, dim3((unsigned)K), dim3(KT), 0, s, p); break;
+    default: hipLaunchKernelGGL(k_kendall_lds<FAM_GUMBEL>, dim3((unsigned)K), dim3(KT), 0, s, p); break;
+  }
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   switch (fam) {
     case FAM_GAUSSIAN: hipLaunchKernelGGL(k_kendall<FAM_GAUSSIAN>, dim3((unsigned)K), dim3(MT), 0, s, p); break;
     case FAM_FRANK: hipLaunchKernelGGL(k_kendall<FAM_FRANK>, dim3((unsigned)K), dim3(MT), 0, s, p); break;

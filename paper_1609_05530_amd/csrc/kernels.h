@@ -180,6 +180,7 @@ hipError_t launch_gaussk(const uint32_t* R, int64_t n_total, int k, const SubDes
 // most 2^20 rows, whose rows own W0, W1 (8 B) and C (4 B) at their begin.
 hipError_t launch_kendall(int fam, const uint32_t* R1, const uint32_t* R2, const SubDesc* subs, int64_t base,
                           int64_t K, int64_t n_min, unsigned long long* W0, unsigned long long* W1, int* C,
+                          int* flag,
                           ResultOut* out, hipStream_t s);
 
 }  // namespace cpc

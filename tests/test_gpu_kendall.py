@@ -104,6 +104,22 @@ def test_kendall_groups_ties_and_statuses():
     compare(gpu_fit(x, y, offs, fams, gofs), sub, comb, "groups, ties, statuses")
 
 
+def test_kendall_tie_groups_in_lds_and_beyond():
+    """The first margin rounded so that its tie groups hold a few rows (the
+    LDS kernel orders them itself) or a few dozen (left to the workspace
+    kernel), beside untied subsets, at the headline subset sizes."""
+    rng = np.random.default_rng(8)
+    sizes = rng.integers(5000, 15001, 6)
+    x, y = synth.copula_pairs("frank", 3.0, int(sizes.sum()), 1950)
+    off = synth.offsets_from_sizes(sizes)
+    x[off[0]:off[2]] = np.round(x[off[0]:off[2]], 3)   # groups of a few rows
+    x[off[3]:off[4]] = np.round(x[off[3]:off[4]], 2)   # groups of dozens
+    y[off[4]:off[5]] = np.round(y[off[4]:off[5]], 3)   # ties in the second margin only
+    print(f"[kendall] tie groups: n={len(x)} K={len(sizes)}", flush=True)
+    sub, comb = oracle_fit(x, y, off, "frank")
+    compare(gpu_fit(x, y, off, "frank"), sub, comb, "tie groups")
+
+
 def test_kendall_rejects_subsets_beyond_its_limit():
     import paper_1609_05530_amd as m
     n = (1 << 20) + 1
