@@ -22,7 +22,8 @@
 //     64-bit integer sums over a histogram indexed by the doubled rank.
 //
 // The inversion of Kendall's tau, one workgroup per subset of up to 2^20
-// rows: tau hat = sum_i S_i / (n (n - 1)) with
+// rows (subsets of up to 16384 rows count in LDS: k_kendall_lds below):
+// tau hat = sum_i S_i / (n (n - 1)) with
 // S_i = sum_l sign(a_i - a_l) sign(b_i - b_l) (a, b the doubled ranks), and
 // var(tau hat) = 4 var(S_i / (n - 1)) / n (a U-statistic of degree two).
 // The S_i come from two merge sorts through the workspace: the rows sorted by
