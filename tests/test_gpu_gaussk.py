@@ -82,6 +82,21 @@ def test_gaussk_parity(k):
     compare(gpu_fit(X, off), sub, comb, f"k={k}")
 
 
+def test_gaussk_large_subsets_and_tied_margins():
+    """Subsets past the size up to which tie-free margins are found in LDS
+    (24575 rows: their bins are all added atomically) beside smaller ones, one
+    with a tied margin (its bins added atomically, the others stored)."""
+    k = 5
+    sizes = np.array([24575, 24576, 30000, 6000])
+    off = synth.offsets_from_sizes(sizes)
+    X = draw(corr(k, 41), int(sizes.sum()), 42)
+    X[off[3]:off[4], 1] = np.round(X[off[3]:off[4], 1] * 8) / 8  # ties in one margin
+    print(f"[gaussk] large subsets: n={len(X)} K={len(sizes)}", flush=True)
+    sub, comb = oracle_fit(X, off)
+    assert np.all(sub["status"] == 0)
+    compare(gpu_fit(X, off), sub, comb, "large subsets, tied margin")
+
+
 def test_gaussk_groups_ties_and_statuses():
     """Groups, tied margins, too few rows (n <= k), a constant margin and two
     nearly collinear margins. (A margin repeated exactly gives a normalised

@@ -120,6 +120,17 @@ def test_kendall_tie_groups_in_lds_and_beyond():
     compare(gpu_fit(x, y, off, "frank"), sub, comb, "tie groups")
 
 
+def test_kendall_lds_size_limit():
+    """Subsets at the LDS kernel's largest size (16384 rows) and one past it
+    (the workspace kernel), with powers of two and their neighbours below."""
+    sizes = np.array([16384, 16385, 8192, 8193, 16383])
+    x, y = synth.copula_pairs("gaussian", 0.4, int(sizes.sum()), 1960)
+    off = synth.offsets_from_sizes(sizes)
+    print(f"[kendall] size limit: n={len(x)} K={len(sizes)}", flush=True)
+    sub, comb = oracle_fit(x, y, off, "gaussian")
+    compare(gpu_fit(x, y, off, "gaussian"), sub, comb, "size limit")
+
+
 def test_kendall_rejects_subsets_beyond_its_limit():
     import paper_1609_05530_amd as m
     n = (1 << 20) + 1
