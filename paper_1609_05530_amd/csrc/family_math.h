@@ -353,17 +353,24 @@ CPC_HD void frank_lsh(const FrankConst<T>& k, T u, T v, T omv, T& l, T& s, T& h)
   h = k.C2 - (T)2 * Dpp * t.iD + (T)2 * t.r1 * t.r1;
 }
 // Variance pass: l (without log(theta E)), score, d2l/dtheta du, d2l/dtheta dv.
+// FORM 2 (FP32, theta near 0): the scaled form with l written as
+// -theta (u + v) - 2 log1p(-theta Ah Bh / Eh), which is O(theta) and keeps its
+// relative accuracy; the caller adds the per-subset constant log(theta / E)
+// (the rest of -2 log(theta Dh) + log(theta E)) in FP64.
 template <typename T, int FORM = -1>
 CPC_HD void frank_full(const FrankConst<T>& k, T u, T v, T omv, T& l, T& s, T& g1, T& g2) {
   const T th = k.th;
-  const bool scaled = FORM == 1 || (FORM == -1 && sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW);
+  const bool scaled = FORM >= 1 || (FORM == -1 && sizeof(T) == 4 && k.th < (T)FRANK_SCALED_BELOW);
   if (scaled) {
     const T Ah = -m_expm1(-th * u) * k.ith, Bh = -m_expm1(-th * v) * k.ith;
     const T a = (T)1 - th * Ah, b = (T)1 - th * Bh;
     const T Dh = k.Eh - th * Ah * Bh;
     const T iDh = m_rcp(Dh);
     const T P = u * a * Bh + v * b * Ah;
-    l = -th * (u + v) - (T)2 * ((T)k.logth + m_log(Dh));
+    if constexpr (FORM == 2)
+      l = -th * (u + v) - (T)2 * m_log1p(-th * Ah * Bh * k.iEh);
+    else
+      l = -th * (u + v) - (T)2 * ((T)k.logth + m_log(Dh));
     s = (k.Eh * k.psi - Ah * Bh * (k.Eh + k.e)) * k.iEh * iDh - (u + v) + (T)2 * P * iDh;
     const T r1t = (k.e - th * P) * iDh;  // theta D'/D
     const T ab = a * b;

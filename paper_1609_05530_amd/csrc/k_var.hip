@@ -125,7 +125,13 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   const double dn = (double)n;
   const double idn = 1.0 / dn;  // W1, W2 are means over the subset
   const Consts<CT> c = make_consts<CT>(FAM, theta);
-  const bool rd = sizeof(CT) == 4 && c.use_d;  // FP64 rows near the family boundaries
+  // Frank near independence (FRANK_SERIES_BELOW <= |theta| < FRANK_F32_MIN_ABS)
+  // takes FP32 rows here: the rank of the variance needs no more (the
+  // estimate itself came from FP64 rows), and l keeps its relative accuracy
+  // in the log1p form, its per-subset constant added in FP64 below
+  const bool fsmall = FAM == FAM_FRANK && sizeof(CT) == 4 && fabs(theta) >= FRANK_SERIES_BELOW &&
+                      fabs(theta) < FRANK_F32_MIN_ABS;
+  const bool rd = sizeof(CT) == 4 && c.use_d && !fsmall;  // FP64 rows near the family boundaries
 
   // Row arithmetic in RT (CT, or double near the family boundaries), results
   // in CT. The choice is uniform over the workgroup and made once, outside
@@ -376,6 +382,8 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
   using Auto = std::integral_constant<int, -1>;
   if (rd || sizeof(CT) == 8 || FAM != FAM_FRANK)
     rd ? rows(double{}, Auto{}) : rows(CT{}, Auto{});
+  else if (fsmall)
+    rows(CT{}, std::integral_constant<int, 2>{});
   else if (c.fk.th < (CT)FRANK_SCALED_BELOW)
     rows(CT{}, std::integral_constant<int, 1>{});
   else
@@ -394,6 +402,10 @@ __global__ void __launch_bounds__(T, MINW) k_var_wg(VarParams P) {
     } else {
       const SubState st = P.state[sid];
       double loglik = v[0], score = v[1];
+      if (fsmall) {  // n log(|theta| / E), E = 1 - e^{-|theta|}
+        const double a = fabs(st.theta);
+        loglik += dn * log(a / -expm1(-a));
+      }
       if (FAM == FAM_GAUSSIAN) {  // from the FP64 sufficient statistics
         double H;
         loglik = gauss_loglik(st.theta, dn, st.Sp, st.Sm);

@@ -77,7 +77,8 @@ CPC_HD Consts<CT> make_consts(int fam, double theta) {
 // Frank rows. In double: reflection and series inside frank_row_d. In float:
 // the FP32 forms of family_math.h (|theta| within [0.5, 50]).
 // FORM (FP32 only): 1 scaled form, 0 direct form, -1 chosen per call (the
-// kernels choose once per subset and pass it down).
+// kernels choose once per subset and pass it down); 2 (variance rows only)
+// the scaled form near theta = 0, l without its per-subset constant.
 template <typename CT, int FORM = -1>
 CPC_HD void frank_rsh(const Consts<CT>& c, uint32_t R1, uint32_t R2, uint32_t twon1, CT inv, CT& s,
                       CT& h) {
@@ -103,7 +104,7 @@ CPC_HD void frank_rfull(const Consts<CT>& c, uint32_t R1, uint32_t R2, uint32_t 
     const CT v = c.neg ? q.omu : q.u, omv = c.neg ? q.u : q.omu;
     CT ll, ss, gg1, gg2;
     frank_full<CT, FORM>(c.fk, p.u, v, omv, ll, ss, gg1, gg2);
-    l = ll + (CT)c.fk.logthE;
+    l = (FORM == 2) ? ll : ll + (CT)c.fk.logthE;  // (FORM 2: the constant is the caller's)
     s = c.neg ? -ss : ss;
     g1 = c.neg ? -gg1 : gg1;
     g2 = gg2;

@@ -722,6 +722,20 @@ def test_autotuned_shapes_give_identical_results(tmp_path, monkeypatch):
 # handful of sampled subsets can miss.
 
 
+@pytest.mark.parametrize("th", [0.1, -0.02, 0.4])
+def test_frank_near_independence_fp32c(th):
+    """FP32c on Frank subsets whose estimate lies in the FP64-row band near
+    independence: the estimate from FP64 rows, the variance and the
+    log-likelihood from FP32 rows (l in its log1p form plus the subset's
+    constant in FP64), all against the oracle at the FP32c tolerances."""
+    sizes = np.array([3000, 12000, 700, 9000])
+    x, y = synth.copula_pairs("frank", th, int(sizes.sum()), 31 + int(abs(th) * 100), dtype=np.float32)
+    off = synth.offsets_from_sizes(sizes)
+    sub, comb = O.fit(x.astype(np.float64), y.astype(np.float64), off, "frank", nthreads=0)
+    res = to_np(cpc().fit(dev(x, torch.float32), dev(y, torch.float32), off, "frank", prec="fp32c"))
+    compare(res, sub, comb, "fp32c", "frank", f"frank {th} fp32c near independence")
+
+
 def test_fp32c_matches_fp64_on_every_subset():
     m = cpc()
     w = synth.nine_settings(n=1_000_000, K=100)
