@@ -71,6 +71,8 @@ def parse():
                     help="skip the GPU times of the n=1e4 and n=1e6 FP64 workloads")
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the n=1e8, replicate-batch and Gumbel legs")
+    ap.add_argument("--legs", default="",
+                    help="comma-separated names of the legs to run (default: all of them)")
     ap.add_argument("--oracle-1thread", action="store_true",
                     help="also time the oracle on one thread on the n=1e4 and n=1e6 workloads (minutes)")
     return ap.parse_args()
@@ -325,6 +327,56 @@ def leg_replicate_batch(cpc, synth, O, dev, torch):
     return {"workload": "1000 replicates x n=1e5 FP32 (GPU sampler), K=50 Dirichlet(1), family r mod 3",
             "subsets": R * K, "ms_per_fit": ms, "subset_fits_per_s": R * K / (ms / 1e3), "gen_s": gen,
             "status_counts": {str(int(s)): int(np.sum(st == s)) for s in np.unique(st)}, "err_vs_oracle": err}
+
+
+def leg_partition(cpc, synth, O, dev, torch):
+    """Partitioning schemes on the paper's largest study cell: 50 replicates
+    of 2e5 FP64 pairs (Gaussian 0.3, GPU sampler) split into M = 100 subsets
+    by cpc_partition (x-order blocks and strided: ranks of both margins with
+    ties by row order, then the scatter kernel); two replicates checked bit
+    for bit against the partition oracle; and the partition study of that
+    cell (bias and MSE against the full-data estimates per scheme)."""
+    import oracle.partition as OP
+    from paper_1609_05530_amd import study
+    S, N, M = 50, 200_000, 100
+    x, y = cpc.sample("gaussian", 0.3, S * N, seed=4242, dtype=torch.float64, device=dev)
+    rep = np.arange(0, S * N + 1, N, dtype=np.int64)
+    out = {"workload": f"{S} replicates x {N} FP64 pairs, M = {M}"}
+    ws = torch.empty(int(cpc._lib.lib().cpc_partition_workspace_bytes(rep.ctypes.data, S, 0, 1)),
+                     dtype=torch.uint8, device=dev)
+    for scheme in ("blocks", "strided"):
+        for _ in range(2):
+            cpc.partition(x, y, rep, M, scheme, workspace=ws)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ms = []
+        for _ in range(10):
+            ev[0].record()
+            xo, yo, offs = cpc.partition(x, y, rep, M, scheme, workspace=ws)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        med = float(np.median(ms))
+        hx, hy = x[: 2 * N].cpu().numpy(), y[: 2 * N].cpu().numpy()
+        ex, ey, _ = OP.partition(hx, hy, rep[:3], M, scheme)
+        same = bool(np.array_equal(xo[: 2 * N].cpu().numpy().view(np.uint64), ex.view(np.uint64))
+                    and np.array_equal(yo[: 2 * N].cpu().numpy().view(np.uint64), ey.view(np.uint64)))
+        out[scheme] = {"ms": med, "rows_per_s": S * N / (med / 1e3), "bit_exact_2_replicates": same}
+        del xo, yo
+    for _ in range(2):
+        cpc.rank(x, y, rep, ties="first")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(10):
+        ev[0].record()
+        cpc.rank(x, y, rep, ties="first")
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    out["ranks_alone_ms"] = float(np.median(ms))
+    rows = study.partition_cell("gaussian", 0.3, N, M, S, x=x, y=y)
+    out["study"] = {r["scheme"]: {"bias": r["bias"], "mse": r["mse"], "bias_vs_theta": r["bias_vs_theta"],
+                                  "sd_combined": r["sd_combined"], "replicates": r["S"]} for r in rows}
+    return out
 
 
 def leg_moment_estimators(cpc, synth, O, dev, torch, w, x, y):
@@ -726,8 +778,15 @@ def main():
                 ("rows_1e8", leg_hundred_million_rows),
                 ("moment_estimators_9x1e7", lambda *args: leg_moment_estimators(*args, w, x, y)),
                 ("gaussk_k8_500x1e4", leg_gaussk),
+                ("partition_50x2e5_m100", leg_partition),
                 ("adjoint_9x1e7", lambda *args: leg_adjoint(*args, w, x, y, theta)))
+        pick = set(s for s in a.legs.split(",") if s)
+        unknown = pick - set(name for name, _ in legs)
+        if unknown:
+            raise SystemExit(f"unknown legs: {sorted(unknown)}")
         for name, fn in legs:
+            if pick and name not in pick:
+                continue
             t0 = time.perf_counter()
             line[name] = fn(cpc, synth, O, dev, torch)
             print(f"[leg] {name}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

@@ -271,6 +271,50 @@ int cpc_density_distance(cpc_handle_t h, int32_t family, int64_t P, const double
 int cpc_replicate_summary(cpc_handle_t h, int64_t S, const cpc_combined_t* combined,
                           const cpc_combined_t* full, double* out, void* stream);
 
+/* Partitioning schemes: how the rows of each replicate are split into its M
+ * subsets (the row partition of eq. 14). Sec. 4 leaves the effect of the
+ * partitioning method on the estimate to future work; these schemes are the
+ * inputs of that study. p(i) is row i's position, from 0, in its
+ * replicate's order of x with ties (-0 equal to +0) broken by row order. */
+typedef enum {
+  CPC_PART_CONTIGUOUS = 0, /* subset m = stored rows floor(m N/M) .. floor((m+1) N/M) - 1 (Sec. 2.5's split) */
+  CPC_PART_BLOCKS = 1,     /* subset m = positions floor(m N/M) .. floor((m+1) N/M) - 1 of the x-order */
+  CPC_PART_STRIDED = 2     /* subset m = positions p with p mod M = m (ceil((N - m) / M) rows) */
+} cpc_partition_t;
+
+/* Workspace bytes of cpc_partition for these replicates (rep_offsets: host,
+ * R+1 values); 0 if rep_offsets is not a partition of 0 .. rep_offsets[R] or
+ * an argument is out of range. About 36 bytes per row for the x-order
+ * schemes (doubled ranks of both margins and the rank kernels' own
+ * workspace, + 88 per row of replicates above 16384 rows), plus the
+ * replicate table of 8 (R + 1) bytes (all that CPC_PART_CONTIGUOUS needs). */
+size_t cpc_partition_workspace_bytes(const int64_t* rep_offsets, int64_t R, int32_t dtype, int32_t scheme);
+
+/* Splits every replicate r (rows rep_offsets[r] .. rep_offsets[r+1] - 1, N_r
+ * rows; host array of R+1 values) into M subsets by `scheme` and writes the
+ * rows, subset after subset, to x_out, y_out (device, n values each of type
+ * dtype; buffers of their own, not overlapping x or y): subset (r, m) is
+ * rows offsets_out[r M + m] .. offsets_out[r M + m + 1] - 1 (offsets_out:
+ * host, R M + 1 values, written before the call returns), inside the
+ * replicate's own row range. Inside a subset the rows keep their stored order
+ * (CPC_PART_CONTIGUOUS) or follow the x-order (the other schemes); more
+ * subsets than rows leave some empty. The x-order comes from the rank
+ * kernels of eq. (12) with ties by row order (on x alone for replicates of
+ * more than 16384 rows; smaller ones are ranked by the workgroup kernels,
+ * which take y along). x must be finite: with a NaN or an infinity in a
+ * replicate, its output is a permutation of its rows in an unspecified order.
+ * The result is ready when the stream has run the call's work; offsets_out
+ * and x_out / y_out can be passed to cpc_fit_batched (one group of M subsets
+ * per replicate). workspace: device, at least
+ * cpc_partition_workspace_bytes(rep_offsets, R, dtype, scheme).
+ * CPC_E_SIZE for M < 1, M >= 2^31, R M + 1 beyond int64, or x_out / y_out
+ * the same buffer as x, y or each other; CPC_E_ENUM for an
+ * unknown scheme or dtype; CPC_E_OFFSETS / CPC_E_UNSUPPORTED as for the
+ * offsets of cpc_fit. */
+int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n,
+                  const int64_t* rep_offsets, int64_t R, int64_t M, int32_t scheme, void* workspace,
+                  size_t ws_bytes, void* x_out, void* y_out, int64_t* offsets_out, void* stream);
+
 /* Workspace bytes of cpc_spearman_fit for n rows, K subsets and G groups. */
 size_t cpc_spearman_workspace_bytes(int64_t n, int64_t K, int64_t G);
 

@@ -369,6 +369,39 @@ def replicate_summary(combined: torch.Tensor, full: torch.Tensor) -> torch.Tenso
     return out
 
 
+PARTITION_SCHEMES = {"contiguous": 0, "blocks": 1, "strided": 2}
+
+
+def partition(x: torch.Tensor, y: torch.Tensor, rep_offsets, M: int, scheme: str = "contiguous", *,
+              workspace: Optional[torch.Tensor] = None):
+    """Each replicate (rows rep_offsets[r] .. rep_offsets[r+1] - 1) split into
+    M subsets by a partitioning scheme (cpc_partition): "contiguous" (equal
+    runs of stored rows), "blocks" (equal runs of the x-order) or "strided"
+    (every M-th row of the x-order). Returns (x_out, y_out, offsets) with
+    offsets a host int64 array of R M + 1 subset bounds, ready for
+    fit_batched with one group of M subsets per replicate."""
+    x = _dev(x, "x")
+    y = _dev(y, "y")
+    if x.shape != y.shape or x.dtype != y.dtype or x.dim() != 1:
+        raise ValueError("x and y must be 1-D tensors of one shape and dtype")
+    rep = _i64(rep_offsets)
+    R = rep.shape[0] - 1
+    code = _code(PARTITION_SCHEMES, scheme)
+    dt = _dtype_code(x)
+    # 0 for arguments the call itself rejects (with the reason)
+    need = max(int(lib().cpc_partition_workspace_bytes(rep.ctypes.data, R, dt, code)) if R >= 1 else 0, 1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    xo = torch.empty_like(x)
+    yo = torch.empty_like(y)
+    # (an M the library rejects gets a placeholder; nothing is written to it)
+    offs = np.empty(R * int(M) + 1 if R >= 1 and 1 <= int(M) < 2 ** 31 else 1, dtype=np.int64)
+    check(lib().cpc_partition(_handle(x.device), x.data_ptr(), y.data_ptr(), dt, x.shape[0], rep.ctypes.data, R,
+                              int(M), code, workspace.data_ptr(), workspace.numel(), xo.data_ptr(), yo.data_ptr(),
+                              offs.ctypes.data, _stream(x.device)))
+    return xo, yo, offs
+
+
 def spearman_fit(R1: torch.Tensor, R2: torch.Tensor, offsets, families, group_offsets=None, *, n_min: int = 2,
                  workspace: Optional[torch.Tensor] = None) -> FitResult:
     """The inversion of Spearman's rho per subset from doubled ranks (as made

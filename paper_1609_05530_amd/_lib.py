@@ -49,6 +49,8 @@ SIGNATURES = {
     "cpc_sample": (_I32, [_P, _I32, ctypes.c_double, ctypes.c_uint64, _I64, _I64, _I32, _P, _P, _P]),
     "cpc_density_distance": (_I32, [_P, _I32, _I64, _P, _P, ctypes.c_double, _I32, _P, _SZ, _P, _P]),
     "cpc_replicate_summary": (_I32, [_P, _I64, _P, _P, _P, _P]),
+    "cpc_partition_workspace_bytes": (_SZ, [_P, _I64, _I32, _I32]),
+    "cpc_partition": (_I32, [_P, _P, _P, _I32, _I64, _P, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P]),
     "cpc_spearman_workspace_bytes": (_SZ, [_I64, _I64, _I64]),
     "cpc_spearman_fit": (_I32, [_P, _P, _P, _I64, _P, _I64, _P, _I64, _P, ctypes.POINTER(Options), _P, _SZ, _P, _P,
                                 _P]),

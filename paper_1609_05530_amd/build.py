@@ -25,7 +25,7 @@ PROBE = os.path.join(HERE, "libcpc_probe.so")
 
 ARCH = "gfx950"
 SOURCES = ["cpc_api.cpp", "k_rank.hip", "k_fit.hip", "k_var.hip", "k_big.hip", "k_eval.hip", "k_combine.hip",
-           "k_sample.hip", "k_study.hip", "k_moment.hip", "k_gaussk.hip"]
+           "k_sample.hip", "k_study.hip", "k_moment.hip", "k_gaussk.hip", "k_partition.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

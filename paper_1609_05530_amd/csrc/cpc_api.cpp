@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -231,6 +232,7 @@ struct Plan {
   std::vector<BigSeg> bsegs;
   std::vector<BigTile> btiles;
   std::vector<int64_t> bxorder;
+  std::vector<int64_t> part_rep;  // replicate bounds of cpc_partition
 };
 
 // Deals per-subset work items to 8 queues (one per XCD: block b runs on XCD
@@ -932,9 +934,11 @@ int cpc_fit_batched_noalloc(cpc_handle_t h, const void* x, const void* y, int32_
                  (hipStream_t)stream, true);
 }
 
-int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
-             int64_t K, const cpc_options_t* opt, void* workspace, size_t ws_bytes, uint32_t* R1, uint32_t* R2,
-             void* stream) {
+// The body of cpc_rank; margins = 1 leaves the y ranks of subsets above
+// kResidentMaxRows unwritten (the workgroup kernels rank both margins).
+static int rank_impl(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
+                     int64_t K, const cpc_options_t* opt, void* workspace, size_t ws_bytes, uint32_t* R1,
+                     uint32_t* R2, void* stream, int margins) {
   if (int rc = check_handle(h)) return rc;
   if (!x || !y || !offsets || !R1 || !R2) return fail(CPC_E_NULL, "a required pointer is NULL");
   if (n < 0) return fail(CPC_E_SIZE, "n < 0");
@@ -976,8 +980,14 @@ int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_
       HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
   }
   set_big(c, P, o.n_min);
-  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s));
+  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s, margins));
   return CPC_SUCCESS;
+}
+
+int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
+             int64_t K, const cpc_options_t* opt, void* workspace, size_t ws_bytes, uint32_t* R1, uint32_t* R2,
+             void* stream) {
+  return rank_impl(h, x, y, dtype, n, offsets, K, opt, workspace, ws_bytes, R1, R2, stream, 2);
 }
 
 int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets,
@@ -1110,6 +1120,80 @@ int cpc_replicate_summary(cpc_handle_t h, int64_t S, const cpc_combined_t* combi
   HIP_OK(hipSetDevice(h->device));
   HIP_OK(launch_replicate_summary(S, (const CombinedOut*)combined, (const CombinedOut*)full, out,
                                   (hipStream_t)stream));
+  return CPC_SUCCESS;
+}
+
+// Rank options of cpc_partition: ties broken by row order, so that the
+// doubled ranks are 2 (position + 1) in the x-order.
+static cpc_options_t partition_rank_options() {
+  cpc_options_t o;
+  cpc_default_options(&o);
+  o.ties = CPC_TIES_FIRST;
+  return o;
+}
+
+size_t cpc_partition_workspace_bytes(const int64_t* rep_offsets, int64_t R, int32_t dtype, int32_t scheme) {
+  if (!rep_offsets || R < 1) return 0;
+  if (dtype != CPC_F64 && dtype != CPC_F32) return 0;
+  if (scheme < CPC_PART_CONTIGUOUS || scheme > CPC_PART_STRIDED) return 0;
+  if (check_offsets(rep_offsets, R, rep_offsets[R]) != CPC_SUCCESS) return 0;
+  size_t need = align_up(sizeof(int64_t) * (size_t)(R + 1));
+  if (scheme != CPC_PART_CONTIGUOUS) {
+    const cpc_options_t o = partition_rank_options();
+    need += 2 * align_up(sizeof(uint32_t) * (size_t)rep_offsets[R]) +
+            cpc_workspace_bytes_for(rep_offsets, R, 1, dtype, &o);
+  }
+  return need;
+}
+
+int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* rep_offsets,
+                  int64_t R, int64_t M, int32_t scheme, void* workspace, size_t ws_bytes, void* x_out, void* y_out,
+                  int64_t* offsets_out, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!x || !y || !rep_offsets || !x_out || !y_out || !offsets_out) return fail(CPC_E_NULL, "a required pointer is NULL");
+  if (n < 0) return fail(CPC_E_SIZE, "n < 0");
+  if (R < 1) return fail(CPC_E_SIZE, "R < 1");
+  if (M < 1 || M >= ((int64_t)1 << 31)) return fail(CPC_E_SIZE, "M = %lld: expected 1 <= M < 2^31", (long long)M);
+  if (M > (INT64_MAX - 1) / R) return fail(CPC_E_SIZE, "R M + 1 offsets do not fit in int64");
+  if (dtype != CPC_F64 && dtype != CPC_F32) return fail(CPC_E_ENUM, "unknown dtype %d", dtype);
+  if (scheme < CPC_PART_CONTIGUOUS || scheme > CPC_PART_STRIDED) return fail(CPC_E_ENUM, "unknown scheme %d", scheme);
+  if (x_out == x || x_out == y || y_out == x || y_out == y || x_out == y_out)
+    return fail(CPC_E_SIZE, "x_out and y_out must be buffers of their own");
+  if (int rc = check_offsets(rep_offsets, R, n)) return rc;
+  const size_t need = cpc_partition_workspace_bytes(rep_offsets, R, dtype, scheme);
+  if (!workspace) return fail(CPC_E_WORKSPACE, "workspace is NULL");
+  if (ws_bytes < need) return fail(CPC_E_WORKSPACE, "workspace too small: %zu bytes, need %zu", ws_bytes, need);
+  // subset bounds: contiguous and blocks split N evenly, floor(m N / M); the
+  // strided scheme's subset m has ceil((N - m) / M) rows
+  for (int64_t r = 0; r < R; ++r) {
+    const int64_t b = rep_offsets[r], N = rep_offsets[r + 1] - b;
+    const int64_t a = N / M, c = N % M;
+    for (int64_t m = 0; m < M; ++m)
+      offsets_out[r * M + m] =
+          b + (scheme == CPC_PART_STRIDED ? m * a + (m < c ? m : c) : (int64_t)(((__int128)m * N) / M));
+  }
+  offsets_out[R * M] = n;
+  if (n == 0) return CPC_SUCCESS;
+  HIP_OK(hipSetDevice(h->device));
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* b = (unsigned char*)workspace;
+  int64_t* drep = (int64_t*)b;
+  b += align_up(sizeof(int64_t) * (size_t)(R + 1));
+  uint32_t* R1 = nullptr;
+  if (scheme != CPC_PART_CONTIGUOUS) {
+    R1 = (uint32_t*)b;
+    b += align_up(sizeof(uint32_t) * (size_t)n);
+    uint32_t* R2 = (uint32_t*)b;
+    b += align_up(sizeof(uint32_t) * (size_t)n);
+    const cpc_options_t o = partition_rank_options();
+    const size_t used = (size_t)(b - (unsigned char*)workspace);
+    if (int rc = rank_impl(h, x, y, dtype, n, rep_offsets, R, &o, b, ws_bytes - used, R1, R2, stream, 1)) return rc;
+  }
+  // the host table stays alive in the handle until the next call (the copy is asynchronous)
+  Plan& P = plan_of(h);
+  P.part_rep.assign(rep_offsets, rep_offsets + R + 1);
+  HIP_OK(hipMemcpyAsync(drep, P.part_rep.data(), sizeof(int64_t) * (size_t)(R + 1), hipMemcpyHostToDevice, s));
+  HIP_OK(launch_partition(dtype == CPC_F32 ? 1 : 0, x, y, R1, drep, R, n, M, scheme, x_out, y_out, s));
   return CPC_SUCCESS;
 }
 

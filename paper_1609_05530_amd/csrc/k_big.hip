@@ -627,11 +627,11 @@ __global__ void __launch_bounds__(256) k_big_finalize(BigParams P, const double*
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, const void* y, int dtype_kw,
-                    int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s) {
+                    int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s, int margins) {
   if (P.nsegs == 0) return hipSuccess;
   const unsigned nt = (unsigned)P.nslots;  // tile slots in XCD order
   hipLaunchKernelGGL(k_big_zero_flags, dim3(nblk(P.nsegs, 256)), dim3(256), 0, s, P);
-  for (int margin = 0; margin < 2; ++margin) {
+  for (int margin = 0; margin < margins; ++margin) {
     const void* data = margin ? y : x;
     uint32_t *klo = B.ka, *khi = B.kb, *val = B.va;
     uint32_t *klo2 = B.kc, *khi2 = B.kd, *val2 = B.vb;

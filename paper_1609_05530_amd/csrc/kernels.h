@@ -125,8 +125,9 @@ struct BigBuffers {
   NewtonState* st;                        // per subset
   int* pending;                           // subsets still iterating
 };
+// margins = 1 ranks x alone (R2out and the staged y arrays are left as they are).
 hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, const void* y, int dtype_kw,
-                    int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s);
+                    int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s, int margins = 2);
 hipError_t big_solve(const BigParams& P, const BigBuffers& B, double tol, int max_iter, int fp64, int* pending_host,
                      hipStream_t s);
 hipError_t big_variance(const BigParams& P, const BigBuffers& B, int fp64, const double* theta_in, int var_method,
@@ -162,6 +163,13 @@ hipError_t launch_density_distance(int fam, int64_t P, const double* theta_a, co
                                    int panels, double* part, double* out, hipStream_t s);
 hipError_t launch_replicate_summary(int64_t S, const CombinedOut* comb, const CombinedOut* full, double* out,
                                     hipStream_t s);
+
+// Partitioning schemes of each replicate into M subsets (k_partition.hip):
+// rows of replicate r (rep[r] .. rep[r + 1] - 1) move to xo, yo by their
+// x-order position R1 / 2 - 1 (doubled ranks, ties by row order).
+enum { PART_CONTIGUOUS = 0, PART_BLOCKS = 1, PART_STRIDED = 2 };
+hipError_t launch_partition(int f32, const void* x, const void* y, const uint32_t* R1, const int64_t* rep,
+                            int64_t R, int64_t n, int64_t M, int scheme, void* xo, void* yo, hipStream_t s);
 
 // Spearman-inversion estimates per subset from doubled ranks (k_moment.hip);
 // H1, H2: 2 (n + K) int64 each.

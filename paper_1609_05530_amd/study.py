@@ -117,6 +117,58 @@ def run_grid(S: int = 50, prec: str = "fp64", seed0: int = 5000, panels: int = 2
     return rows
 
 
+PARTITION_STUDY_SCHEMES = ("contiguous", "unequal", "blocks", "strided")
+
+
+def unequal_offsets(N: int, M: int, S: int, seed: int) -> np.ndarray:
+    """Subset bounds of S replicates of N rows, each split into M contiguous
+    runs of unequal sizes: Dirichlet(1, ..., 1) proportions w (seeded numpy
+    draws), bounds floor(N (w_1 + ... + w_m)), the last one N."""
+    rng = np.random.default_rng(seed)
+    out = [0]
+    for s in range(S):
+        c = np.floor(N * np.cumsum(rng.dirichlet(np.ones(M)))).astype(np.int64)
+        c[-1] = N
+        out.extend((s * N + np.maximum.accumulate(c)).tolist())
+    return np.array(out, dtype=np.int64)
+
+
+def partition_cell(family: str, theta: float, N: int, M: int, S: int, schemes=PARTITION_STUDY_SCHEMES,
+                   seed: int = 1, prec: str = "fp64", x=None, y=None, full=None):
+    """The partitioning study that Sec. 4 leaves as future work, for one
+    cell: the same S replicates of N rows split into M subsets by each
+    scheme, fitted and combined per replicate (eq. 16), and summarised
+    against the full-data estimates like the grid (eq. 17, 18, bias, MSE);
+    also the mean combined estimate's distance from theta and the spread of
+    the combined estimates. Schemes: those of cpc_partition ("contiguous",
+    "blocks", "strided") and "unequal" (contiguous runs of Dirichlet(1)
+    sizes, the unequal subsets that Sec. 4 says the inverse-variance weights
+    account for). One dict per scheme."""
+    from . import fit_batched, partition, replicate_summary
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    if x is None:
+        x, y = draw(family, theta, S, N, seed, dtype=dtype)
+    if full is None:
+        full = fit_full(x, y, family, N, S, prec=prec)
+    rep = np.arange(0, S * N + 1, N, dtype=np.int64)
+    gofs = np.arange(0, S * M + 1, M, dtype=np.int64)
+    out = []
+    for scheme in schemes:
+        if scheme == "unequal":
+            xo, yo, offs = x, y, unequal_offsets(N, M, S, seed + 7919)
+        else:
+            xo, yo, offs = partition(x, y, rep, M, scheme)
+        sub = fit_batched(xo, yo, offs, gofs, [family] * S, prec=prec)
+        s = replicate_summary(sub.raw_comb, full.raw_comb).cpu().numpy()
+        comb = sub.raw_comb[:, 0].cpu().numpy()
+        out.append({"scheme": scheme, "family": family, "theta": theta, "N": N, "M": M, "S": int(s[4]),
+                    "theta_combined_sim": float(s[0]), "theta_full_sim": float(s[1]), "bias": float(s[2]),
+                    "mse": float(s[3]), "bias_vs_theta": float(np.nanmean(comb) - theta),
+                    "sd_combined": float(np.nanstd(comb))})
+        del xo, yo, sub
+    return out
+
+
 def outside_paper_bounds(rows, slack: float = 1.0):
     """Rows whose |bias|, MSE or L1 / L2 exceed Sec. 3.2's bounds times slack."""
     bad = []
