@@ -37,6 +37,10 @@ struct cpc_context {
   int have_times;
   int* pending_host;        // pinned: subsets of the streaming path still iterating
   hipStream_t cap_stream;   // the fit is captured here in graph mode (default priority)
+  // second branch of a phase: the buckets after the first run here, forked
+  // from and joined back to the call's stream (default priority)
+  hipStream_t aux_stream;
+  hipEvent_t fork_ev[kPhases], join_ev[kPhases];
   void* graph;              // GraphCache: the instantiated graph of the last graph-mode call
   void* tuner;              // Tuner: rank-kernel launch shapes chosen per workload signature
 };
@@ -684,15 +688,54 @@ int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* 
                   hipStream_t s) {
   const int kw = (dtype == CPC_F64) ? 2 : 1;
   const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
+  // The buckets of a phase touch disjoint subsets: they run on two streams at
+  // once, s and the auxiliary one (a captured graph gets two branches), so
+  // that a bucket does not wait for the previous one's last workgroups; the
+  // join puts the phase's end back on s. Buckets are dealt longest first to
+  // the branch with less work, the work of a bucket taken as its rows times
+  // the family's cost per row relative to the Gaussian's (fit and variance
+  // passes measured on the benchmark workload: Frank about 1.3, Gumbel 1.6;
+  // ranks cost the same for every family).
+  const std::vector<Bucket>& bl = (ph == 0) ? P.rank_buckets : P.fit_buckets;
+  const int32_t* ord = (ph == 0) ? P.order_rank.data() : P.order_fit.data();
+  const bool two = ph < 3 && bl.size() > 1;
+  std::vector<char> on_aux(bl.size(), 0);
+  if (two) {
+    std::vector<std::pair<double, size_t>> w(bl.size());
+    for (size_t i = 0; i < bl.size(); ++i) {
+      double rows = 0.0;
+      for (int32_t k = 0; k < bl[i].count; ++k) rows += (double)P.subs[ord[bl[i].first + k]].n;
+      const double f = (ph == 0 || bl[i].fam == FAM_GAUSSIAN) ? 1.0 : (bl[i].fam == FAM_FRANK ? 1.3 : 1.6);
+      w[i] = {rows * f, i};
+    }
+    std::stable_sort(w.begin(), w.end(), [](const auto& p, const auto& q) { return p.first > q.first; });
+    double load[2] = {0.0, 0.0};
+    for (const auto& e : w) {
+      const int br = load[1] < load[0] ? 1 : 0;
+      on_aux[e.second] = (char)br;
+      load[br] += e.first;
+    }
+    HIP_OK(hipEventRecord(h->fork_ev[ph], s));
+    HIP_OK(hipStreamWaitEvent(h->aux_stream, h->fork_ev[ph], 0));
+  }
+  auto stream_of = [&](const Bucket& b) { return on_aux[(size_t)(&b - bl.data())] ? h->aux_stream : s; };
+  hipStream_t a = two ? h->aux_stream : s;
+  auto join = [&]() -> int {
+    if (two) {
+      HIP_OK(hipEventRecord(h->join_ev[ph], a));
+      HIP_OK(hipStreamWaitEvent(s, h->join_ev[ph], 0));
+    }
+    return CPC_SUCCESS;
+  };
   switch (ph) {
     case 0: {
       RankParams rp = rank_params(c, x, y, o);
       for (const Bucket& b : P.rank_buckets) {
         rp.order = c.order_rank + b.first;
-        HIP_OK(launch_rank_shape(b.shape >= 0 ? b.shape : kRankDefaultShape[b.cls], kw, rp, b.count, s));
+        HIP_OK(launch_rank_shape(b.shape >= 0 ? b.shape : kRankDefaultShape[b.cls], kw, rp, b.count, stream_of(b)));
       }
       HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, nullptr, nullptr, s));
-      return CPC_SUCCESS;
+      return join();
     }
     case 1: {
       FitParams fp;
@@ -704,10 +747,10 @@ int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* 
       fp.tol = o.tol;
       for (const Bucket& b : P.fit_buckets) {
         fp.order = c.order_fit + b.first;
-        HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, s));
+        HIP_OK(launch_fit_wg(b.cls, b.fam, fp64, fp, b.count, stream_of(b)));
       }
       HIP_OK(big_solve(c.big, c.bb, o.tol, o.max_iter, fp64, graph ? nullptr : h->pending_host, s));
-      return CPC_SUCCESS;
+      return join();
     }
     case 2: {
       VarParams vp;
@@ -720,10 +763,10 @@ int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* 
       vp.out = (ResultOut*)out;
       for (const Bucket& b : P.fit_buckets) {
         vp.order = c.order_fit + b.first;
-        HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
+        HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, stream_of(b)));
       }
       HIP_OK(big_variance(c.big, c.bb, fp64, nullptr, o.var, MODE_FIT, nullptr, (ResultOut*)out, s));
-      return CPC_SUCCESS;
+      return join();
     }
     default:
       HIP_OK(launch_combine((const ResultOut*)out, c.gofs, G, (CombinedOut*)comb, s));
@@ -809,6 +852,17 @@ int cpc_create(int device, cpc_handle_t* out) {
       return fail(CPC_E_HIP, "hipEventCreate failed");
     }
   }
+  bool ok = hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking) == hipSuccess;
+  int made = 0;
+  for (; ok && made < kPhases; ++made)
+    ok = hipEventCreateWithFlags(&h->fork_ev[made], hipEventDisableTiming) == hipSuccess &&
+         hipEventCreateWithFlags(&h->join_ev[made], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    *out = h;
+    (void)cpc_destroy(h);  // (destroys what was made; the rest is null)
+    *out = nullptr;
+    return fail(CPC_E_HIP, "creating the auxiliary stream or its events failed");
+  }
   *out = h;
   return CPC_SUCCESS;
 }
@@ -821,6 +875,11 @@ int cpc_destroy(cpc_handle_t h) {
   delete (GraphCache*)h->graph;
   delete (Tuner*)h->tuner;
   (void)hipStreamDestroy(h->cap_stream);
+  if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+  for (int i = 0; i < kPhases; ++i) {
+    if (h->fork_ev[i]) (void)hipEventDestroy(h->fork_ev[i]);
+    if (h->join_ev[i]) (void)hipEventDestroy(h->join_ev[i]);
+  }
   for (int i = 0; i <= kPhases; ++i) (void)hipEventDestroy(h->ev[i]);
   (void)hipHostFree(h->pending_host);
   delete (Plan*)h->plan;
