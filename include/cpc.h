@@ -298,10 +298,10 @@ size_t cpc_partition_workspace_bytes(const int64_t* rep_offsets, int64_t R, int3
  * host, R M + 1 values, written before the call returns), inside the
  * replicate's own row range. Inside a subset the rows keep their stored order
  * (CPC_PART_CONTIGUOUS) or follow the x-order (the other schemes); more
- * subsets than rows leave some empty. The x-order comes from the rank
- * kernels of eq. (12) with ties by row order (on x alone for replicates of
- * more than 16384 rows; smaller ones are ranked by the workgroup kernels,
- * which take y along). x must be finite: with a NaN or an infinity in a
+ * subsets than rows leave some empty. The x-order comes from a stable sort
+ * of x (ties by row order): replicates of more than 16384 rows are sorted
+ * on the streaming path and their rows gathered in order, smaller ones are
+ * ranked by the workgroup rank kernels of eq. (12), which take y along. x must be finite: with a NaN or an infinity in a
  * replicate, its output is a permutation of its rows in an unspecified order.
  * The result is ready when the stream has run the call's work; offsets_out
  * and x_out / y_out can be passed to cpc_fit_batched (one group of M subsets

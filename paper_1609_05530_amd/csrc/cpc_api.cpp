@@ -994,10 +994,14 @@ int cpc_fit_batched_noalloc(cpc_handle_t h, const void* x, const void* y, int32_
 }
 
 // The body of cpc_rank; margins = 1 leaves the y ranks of subsets above
-// kResidentMaxRows unwritten (the workgroup kernels rank both margins).
+// kResidentMaxRows unwritten (the workgroup kernels rank both margins). With
+// big_sorted, x of those subsets is only sorted: their R1 is not written,
+// and *big_sorted / *big receive the sorted payloads and the streaming
+// path's tables (big->nsegs = 0 when there is no such subset).
 static int rank_impl(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
                      int64_t K, const cpc_options_t* opt, void* workspace, size_t ws_bytes, uint32_t* R1,
-                     uint32_t* R2, void* stream, int margins) {
+                     uint32_t* R2, void* stream, int margins, const uint32_t** big_sorted = nullptr,
+                     BigParams* big = nullptr) {
   if (int rc = check_handle(h)) return rc;
   if (!x || !y || !offsets || !R1 || !R2) return fail(CPC_E_NULL, "a required pointer is NULL");
   if (n < 0) return fail(CPC_E_SIZE, "n < 0");
@@ -1039,7 +1043,8 @@ static int rank_impl(cpc_handle_t h, const void* x, const void* y, int32_t dtype
       HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
   }
   set_big(c, P, o.n_min);
-  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s, margins));
+  if (big) *big = c.big;
+  HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s, margins, big_sorted));
   return CPC_SUCCESS;
 }
 
@@ -1239,6 +1244,11 @@ int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, i
   int64_t* drep = (int64_t*)b;
   b += align_up(sizeof(int64_t) * (size_t)(R + 1));
   uint32_t* R1 = nullptr;
+  // replicates above kResidentMaxRows: x sorted on the streaming path and
+  // the rows gathered from the sorted payloads (no ranks formed)
+  const uint32_t* big_sorted = nullptr;
+  BigParams big;
+  std::memset(&big, 0, sizeof(big));
   if (scheme != CPC_PART_CONTIGUOUS) {
     R1 = (uint32_t*)b;
     b += align_up(sizeof(uint32_t) * (size_t)n);
@@ -1246,13 +1256,23 @@ int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, i
     b += align_up(sizeof(uint32_t) * (size_t)n);
     const cpc_options_t o = partition_rank_options();
     const size_t used = (size_t)(b - (unsigned char*)workspace);
-    if (int rc = rank_impl(h, x, y, dtype, n, rep_offsets, R, &o, b, ws_bytes - used, R1, R2, stream, 1)) return rc;
+    if (int rc = rank_impl(h, x, y, dtype, n, rep_offsets, R, &o, b, ws_bytes - used, R1, R2, stream, 1,
+                           &big_sorted, &big))
+      return rc;
   }
   // the host table stays alive in the handle until the next call (the copy is asynchronous)
   Plan& P = plan_of(h);
   P.part_rep.assign(rep_offsets, rep_offsets + R + 1);
   HIP_OK(hipMemcpyAsync(drep, P.part_rep.data(), sizeof(int64_t) * (size_t)(R + 1), hipMemcpyHostToDevice, s));
-  HIP_OK(launch_partition(dtype == CPC_F32 ? 1 : 0, x, y, R1, drep, R, n, M, scheme, x_out, y_out, s));
+  const int f32 = dtype == CPC_F32 ? 1 : 0;
+  const bool gather = big.nsegs > 0 && big_sorted != nullptr;
+  bool small = !gather;  // a replicate left to the scatter kernel
+  for (int64_t r = 0; r < R && !small; ++r) {
+    const int64_t N = rep_offsets[r + 1] - rep_offsets[r];
+    small = N > 0 && N <= kResidentMaxRows;
+  }
+  if (small) HIP_OK(launch_partition(f32, x, y, R1, drep, R, n, M, scheme, gather ? 1 : 0, x_out, y_out, s));
+  if (gather) HIP_OK(launch_partition_gather(f32, big, big_sorted, x, y, M, scheme, x_out, y_out, s));
   return CPC_SUCCESS;
 }
 

@@ -13,6 +13,12 @@
 // One thread per row, a grid-stride loop over at most 16384 workgroups (a
 // thread has few rows, so many loads are in flight); x, y and R1 are read
 // coalesced and each replicate's writes are a permutation of its own rows.
+// Replicates of more than kResidentMaxRows rows take the gather below
+// instead: their x is sorted on the streaming path, whose payloads give the
+// row at each sorted position, so output row o (subset m, its q-th row)
+// reads the row at position p = o (blocks) or p = q M + m (strided); the
+// writes are coalesced and the reads stay inside the replicate, whose
+// tiles the streaming path's slots keep on one XCD.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -22,8 +28,8 @@ namespace cpc {
 template <typename T>
 __global__ void __launch_bounds__(256) k_partition(const T* __restrict__ x, const T* __restrict__ y,
                                                    const uint32_t* __restrict__ R1, const int64_t* __restrict__ rep,
-                                                   int64_t R, int64_t n, uint32_t M, int scheme, T* __restrict__ xo,
-                                                   T* __restrict__ yo) {
+                                                   int64_t R, int64_t n, uint32_t M, int scheme, int skip_big,
+                                                   T* __restrict__ xo, T* __restrict__ yo) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     int64_t dest = i;
@@ -39,6 +45,7 @@ __global__ void __launch_bounds__(256) k_partition(const T* __restrict__ x, cons
       }
       const int64_t b = rep[lo];
       const uint32_t N = (uint32_t)(rep[lo + 1] - b);
+      if (skip_big && N > (uint32_t)kResidentMaxRows) continue;  // the gather's rows
       const uint32_t p = (R1[i] >> 1) - 1u;
       if (p >= N) continue;  // not a position of this replicate: nothing is written
       if (scheme == PART_BLOCKS) {
@@ -54,18 +61,69 @@ __global__ void __launch_bounds__(256) k_partition(const T* __restrict__ x, cons
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_partition_gather(BigParams P, const uint32_t* __restrict__ sorted_rows,
+                                                          const T* __restrict__ x, const T* __restrict__ y,
+                                                          uint32_t M, int scheme, T* __restrict__ xo,
+                                                          T* __restrict__ yo) {
+  const int64_t ti = P.xorder[blockIdx.x];
+  if (ti < 0) return;  // idle slot (uniform)
+  const BigTile t = P.tiles[ti];
+  const BigSeg sg = P.segs[t.seg];
+  const uint32_t N = (uint32_t)sg.n;
+  const uint32_t a = N / M, c = N - a * M;
+  const uint32_t big = (a + 1u) * c;  // rows of the subsets that hold a + 1 rows
+  // the tile's index range is output rows, so that the writes are coalesced
+  // (walking sorted positions instead, the strided writes scatter: 1.5x slower)
+  for (int k = threadIdx.x; k < t.count; k += blockDim.x) {
+    const uint32_t o = (uint32_t)(t.start + k);  // output row within the replicate
+    uint32_t p = o;
+    if (scheme == PART_STRIDED) {  // o is row q of subset m: position q M + m
+      uint32_t m, q;
+      if (o < big) {
+        m = o / (a + 1u);
+        q = o - m * (a + 1u);
+      } else {  // (a >= 1 here, since o < N = a M + c)
+        const uint32_t r = o - big;
+        q = r % a;
+        m = c + r / a;
+      }
+      p = q * M + m;
+    }
+    const uint32_t row = sorted_rows[sg.roff + p];
+    if (row >= N) continue;  // not a row of this replicate: nothing is written
+    xo[sg.begin + o] = x[sg.begin + row];
+    yo[sg.begin + o] = y[sg.begin + row];
+  }
+}
+
+hipError_t launch_partition_gather(int f32, const BigParams& P, const uint32_t* sorted_rows, const void* x,
+                                   const void* y, int64_t M, int scheme, void* xo, void* yo, hipStream_t s) {
+  if (P.nsegs == 0 || P.nslots == 0) return hipSuccess;
+  const unsigned nt = (unsigned)P.nslots;
+  if (f32)
+    hipLaunchKernelGGL(k_partition_gather<float>, dim3(nt), dim3(256), 0, s, P, sorted_rows, (const float*)x,
+                       (const float*)y, (uint32_t)M, scheme, (float*)xo, (float*)yo);
+  else
+    hipLaunchKernelGGL(k_partition_gather<double>, dim3(nt), dim3(256), 0, s, P, sorted_rows, (const double*)x,
+                       (const double*)y, (uint32_t)M, scheme, (double*)xo, (double*)yo);
+  return hipGetLastError();
+}
+
 hipError_t launch_partition(int f32, const void* x, const void* y, const uint32_t* R1, const int64_t* rep,
-                            int64_t R, int64_t n, int64_t M, int scheme, void* xo, void* yo, hipStream_t s) {
+                            int64_t R, int64_t n, int64_t M, int scheme, int skip_big, void* xo, void* yo,
+                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int threads = 256;
   int64_t blocks = (n + threads - 1) / threads;
   if (blocks > 16384) blocks = 16384;
   if (f32)
     hipLaunchKernelGGL(k_partition<float>, dim3((unsigned)blocks), dim3(threads), 0, s, (const float*)x,
-                       (const float*)y, R1, rep, R, n, (uint32_t)M, scheme, (float*)xo, (float*)yo);
+                       (const float*)y, R1, rep, R, n, (uint32_t)M, scheme, skip_big, (float*)xo, (float*)yo);
   else
     hipLaunchKernelGGL(k_partition<double>, dim3((unsigned)blocks), dim3(threads), 0, s, (const double*)x,
-                       (const double*)y, R1, rep, R, n, (uint32_t)M, scheme, (double*)xo, (double*)yo);
+                       (const double*)y, R1, rep, R, n, (uint32_t)M, scheme, skip_big, (double*)xo,
+                       (double*)yo);
   return hipGetLastError();
 }
 
