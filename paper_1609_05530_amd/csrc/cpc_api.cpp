@@ -683,50 +683,66 @@ int run_fit(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t
 // at a time: rank -> fit -> variance -> combine. In graph mode nothing here
 // waits on the host: the streaming path's Newton loop runs its full pass
 // budget, its kernels returning at once when every subset is done.
+// The buckets of a launch list touch disjoint subsets: they run on two
+// streams at once, the call's stream s and the handle's auxiliary one (a
+// captured graph gets two branches), so that a bucket does not wait for the
+// previous one's last workgroups; the join puts the end back on s. Buckets
+// are dealt longest first to the branch with less work, the work of a
+// bucket taken as its rows times the family's cost per row relative to the
+// Gaussian's (fit and variance passes measured on the benchmark workload:
+// Frank about 1.3, Gumbel 1.6; ranks cost the same for every family).
+struct Branches {
+  bool two = false;
+  std::vector<char> on_aux;
+  hipStream_t stream(cpc_handle_t h, const std::vector<Bucket>& bl, const Bucket& b, hipStream_t s) const {
+    return two && on_aux[(size_t)(&b - bl.data())] ? h->aux_stream : s;
+  }
+};
+
+int fork_buckets(cpc_handle_t h, const Plan& P, const std::vector<Bucket>& bl, const int32_t* ord, bool by_family,
+                 int ev, hipStream_t s, Branches& br) {
+  br.two = bl.size() > 1;
+  br.on_aux.assign(bl.size(), 0);
+  if (!br.two) return CPC_SUCCESS;
+  std::vector<std::pair<double, size_t>> w(bl.size());
+  for (size_t i = 0; i < bl.size(); ++i) {
+    double rows = 0.0;
+    for (int32_t k = 0; k < bl[i].count; ++k) rows += (double)P.subs[ord[bl[i].first + k]].n;
+    const double f = (!by_family || bl[i].fam == FAM_GAUSSIAN) ? 1.0 : (bl[i].fam == FAM_FRANK ? 1.3 : 1.6);
+    w[i] = {rows * f, i};
+  }
+  std::stable_sort(w.begin(), w.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+  double load[2] = {0.0, 0.0};
+  for (const auto& e : w) {
+    const int side = load[1] < load[0] ? 1 : 0;
+    br.on_aux[e.second] = (char)side;
+    load[side] += e.first;
+  }
+  HIP_OK(hipEventRecord(h->fork_ev[ev], s));
+  HIP_OK(hipStreamWaitEvent(h->aux_stream, h->fork_ev[ev], 0));
+  return CPC_SUCCESS;
+}
+
+int join_buckets(cpc_handle_t h, const Branches& br, int ev, hipStream_t s) {
+  if (!br.two) return CPC_SUCCESS;
+  HIP_OK(hipEventRecord(h->join_ev[ev], h->aux_stream));
+  HIP_OK(hipStreamWaitEvent(s, h->join_ev[ev], 0));
+  return CPC_SUCCESS;
+}
+
 int enqueue_phase(int ph, cpc_handle_t h, const Plan& P, Carved& c, const void* x, const void* y, int32_t dtype,
                   int64_t G, const Options& o, cpc_subset_result_t* out, cpc_combined_t* comb, bool graph,
                   hipStream_t s) {
   const int kw = (dtype == CPC_F64) ? 2 : 1;
   const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
-  // The buckets of a phase touch disjoint subsets: they run on two streams at
-  // once, s and the auxiliary one (a captured graph gets two branches), so
-  // that a bucket does not wait for the previous one's last workgroups; the
-  // join puts the phase's end back on s. Buckets are dealt longest first to
-  // the branch with less work, the work of a bucket taken as its rows times
-  // the family's cost per row relative to the Gaussian's (fit and variance
-  // passes measured on the benchmark workload: Frank about 1.3, Gumbel 1.6;
-  // ranks cost the same for every family).
   const std::vector<Bucket>& bl = (ph == 0) ? P.rank_buckets : P.fit_buckets;
-  const int32_t* ord = (ph == 0) ? P.order_rank.data() : P.order_fit.data();
-  const bool two = ph < 3 && bl.size() > 1;
-  std::vector<char> on_aux(bl.size(), 0);
-  if (two) {
-    std::vector<std::pair<double, size_t>> w(bl.size());
-    for (size_t i = 0; i < bl.size(); ++i) {
-      double rows = 0.0;
-      for (int32_t k = 0; k < bl[i].count; ++k) rows += (double)P.subs[ord[bl[i].first + k]].n;
-      const double f = (ph == 0 || bl[i].fam == FAM_GAUSSIAN) ? 1.0 : (bl[i].fam == FAM_FRANK ? 1.3 : 1.6);
-      w[i] = {rows * f, i};
-    }
-    std::stable_sort(w.begin(), w.end(), [](const auto& p, const auto& q) { return p.first > q.first; });
-    double load[2] = {0.0, 0.0};
-    for (const auto& e : w) {
-      const int br = load[1] < load[0] ? 1 : 0;
-      on_aux[e.second] = (char)br;
-      load[br] += e.first;
-    }
-    HIP_OK(hipEventRecord(h->fork_ev[ph], s));
-    HIP_OK(hipStreamWaitEvent(h->aux_stream, h->fork_ev[ph], 0));
+  Branches br;
+  if (ph < 3) {
+    if (int rc = fork_buckets(h, P, bl, (ph == 0) ? P.order_rank.data() : P.order_fit.data(), ph != 0, ph, s, br))
+      return rc;
   }
-  auto stream_of = [&](const Bucket& b) { return on_aux[(size_t)(&b - bl.data())] ? h->aux_stream : s; };
-  hipStream_t a = two ? h->aux_stream : s;
-  auto join = [&]() -> int {
-    if (two) {
-      HIP_OK(hipEventRecord(h->join_ev[ph], a));
-      HIP_OK(hipStreamWaitEvent(s, h->join_ev[ph], 0));
-    }
-    return CPC_SUCCESS;
-  };
+  auto stream_of = [&](const Bucket& b) { return br.stream(h, bl, b, s); };
+  auto join = [&]() -> int { return join_buckets(h, br, ph, s); };
   switch (ph) {
     case 0: {
       RankParams rp = rank_params(c, x, y, o);
@@ -1034,18 +1050,20 @@ static int rank_impl(cpc_handle_t h, const void* x, const void* y, int32_t dtype
   rp.R2out = R2;
   rp.state = c.state;
   const int kw = (dtype == CPC_F64) ? 2 : 1;
+  Branches br;
+  if (int rc = fork_buckets(h, P, P.rank_buckets, P.order_rank.data(), false, 0, s, br)) return rc;
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
     // a shape forced through opt->schedule for the classes it serves; else the class default
     if (o.schedule > 0 && kw == 1 && kRankShapes[o.schedule - 1].cap == kClassThreads[b.cls] * kClassItems[b.cls])
-      HIP_OK(launch_rank_shape(o.schedule - 1, kw, rp, b.count, s));
+      HIP_OK(launch_rank_shape(o.schedule - 1, kw, rp, b.count, br.stream(h, P.rank_buckets, b, s)));
     else
-      HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, s));
+      HIP_OK(launch_rank_wg(b.cls, kw, rp, b.count, br.stream(h, P.rank_buckets, b, s)));
   }
   set_big(c, P, o.n_min);
   if (big) *big = c.big;
   HIP_OK(big_rank(c.big, c.bb, x, y, kw, 0, o.ties, R1, R2, s, margins, big_sorted));
-  return CPC_SUCCESS;
+  return join_buckets(h, br, 0, s);
 }
 
 int cpc_rank(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
@@ -1088,12 +1106,15 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
   rp.n_min = o.n_min;
   rp.rows = c.rows;
   rp.state = c.state;
+  Branches br;
+  if (int rc = fork_buckets(h, P, P.rank_buckets, P.order_rank.data(), false, 0, s, br)) return rc;
   for (const Bucket& b : P.rank_buckets) {
     rp.order = c.order_rank + b.first;
-    HIP_OK(launch_rank_wg(b.cls, 1, rp, b.count, s));
+    HIP_OK(launch_rank_wg(b.cls, 1, rp, b.count, br.stream(h, P.rank_buckets, b, s)));
   }
   set_big(c, P, o.n_min);
   HIP_OK(big_rank(c.big, c.bb, R1, R2, 1, 1, o.ties, nullptr, nullptr, s));
+  if (int rc = join_buckets(h, br, 0, s)) return rc;
   VarParams vp;
   std::memset(&vp, 0, sizeof(vp));
   vp.subs = c.subs;
@@ -1104,12 +1125,14 @@ int cpc_variance(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t
   vp.theta_in = theta;
   vp.var_out = var;
   const int fp64 = (o.prec == CPC_PREC_FP64) ? 1 : 0;
+  Branches bv;
+  if (int rc = fork_buckets(h, P, P.fit_buckets, P.order_fit.data(), true, 2, s, bv)) return rc;
   for (const Bucket& b : P.fit_buckets) {
     vp.order = c.order_fit + b.first;
-    HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, s));
+    HIP_OK(launch_var_wg(b.cls, b.fam, fp64, vp, b.count, bv.stream(h, P.fit_buckets, b, s)));
   }
   HIP_OK(big_variance(c.big, c.bb, fp64, theta, o.var, MODE_VARIANCE, var, nullptr, s));
-  return CPC_SUCCESS;
+  return join_buckets(h, bv, 2, s);
 }
 
 int cpc_eval(cpc_handle_t h, const uint32_t* R1, const uint32_t* R2, int64_t n, const int64_t* offsets, int64_t K,
