@@ -1382,24 +1382,50 @@ int moment_fit(bool kendall, cpc_handle_t h, const uint32_t* R1, const uint32_t*
   P.gofs.assign(group_offsets, group_offsets + G + 1);
   HIP_OK(hipMemcpyAsync(dsubs, P.subs.data(), sizeof(SubDesc) * (size_t)K, hipMemcpyHostToDevice, s));
   HIP_OK(hipMemcpyAsync(dgofs, P.gofs.data(), sizeof(int64_t) * (size_t)(G + 1), hipMemcpyHostToDevice, s));
-  // one launch per run of groups of one family (subsets in order)
+  // one launch per run of groups of one family (subsets in order); the runs
+  // touch disjoint subsets and rows, so with more than one they are dealt,
+  // most rows first, to the call's stream and the auxiliary one (each
+  // launch otherwise ends with a partly idle last wave of workgroups)
+  std::vector<std::pair<int64_t, int64_t>> runs;  // (first group, end group)
   for (int64_t g = 0; g < G;) {
     int64_t h2 = g;
     while (h2 < G && family_per_group[h2] == family_per_group[g]) ++h2;
-    const int64_t m0 = group_offsets[g], m1 = group_offsets[h2];
-    if (m1 > m0) {
-      if (kendall)
-        HIP_OK(launch_kendall(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, W0, W1, C, flag,
-                              (ResultOut*)out, s));
-      else
-      {
-        int64_t n_max = 0;
-        for (int64_t m = m0; m < m1; ++m) n_max = std::max<int64_t>(n_max, offsets[m + 1] - offsets[m]);
-        HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, n_max, H1, H2,
-                               (ResultOut*)out, s));
-      }
-    }
+    if (group_offsets[h2] > group_offsets[g]) runs.push_back({g, h2});
     g = h2;
+  }
+  const bool two = runs.size() > 1;
+  std::vector<char> on_aux(runs.size(), 0);
+  if (two) {
+    std::vector<std::pair<int64_t, size_t>> w(runs.size());
+    for (size_t i = 0; i < runs.size(); ++i)
+      w[i] = {offsets[group_offsets[runs[i].second]] - offsets[group_offsets[runs[i].first]], i};
+    std::stable_sort(w.begin(), w.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    int64_t load[2] = {0, 0};
+    for (const auto& e : w) {
+      const int side = load[1] < load[0] ? 1 : 0;
+      on_aux[e.second] = (char)side;
+      load[side] += e.first;
+    }
+    HIP_OK(hipEventRecord(h->fork_ev[1], s));
+    HIP_OK(hipStreamWaitEvent(h->aux_stream, h->fork_ev[1], 0));
+  }
+  for (size_t i = 0; i < runs.size(); ++i) {
+    const int64_t g = runs[i].first;
+    const int64_t m0 = group_offsets[g], m1 = group_offsets[runs[i].second];
+    hipStream_t rs = on_aux[i] ? h->aux_stream : s;
+    if (kendall) {
+      HIP_OK(launch_kendall(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, W0, W1, C, flag,
+                            (ResultOut*)out, rs));
+    } else {
+      int64_t n_max = 0;
+      for (int64_t m = m0; m < m1; ++m) n_max = std::max<int64_t>(n_max, offsets[m + 1] - offsets[m]);
+      HIP_OK(launch_spearman(family_per_group[g], R1, R2, dsubs, m0, m1 - m0, o.n_min, n_max, H1, H2,
+                             (ResultOut*)out, rs));
+    }
+  }
+  if (two) {
+    HIP_OK(hipEventRecord(h->join_ev[1], h->aux_stream));
+    HIP_OK(hipStreamWaitEvent(s, h->join_ev[1], 0));
   }
   HIP_OK(launch_combine((const ResultOut*)out, dgofs, G, (CombinedOut*)comb, s));
   return CPC_SUCCESS;
