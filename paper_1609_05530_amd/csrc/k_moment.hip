@@ -300,30 +300,39 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
     const int64_t k0 = t * C, k1 = min(k0 + C, NH);
     __shared__ long long tot[2][MT];
     if constexpr (LDSB) {
-      // exact int32 sums in LDS (|sum| <= n^2 < 2^31 for n <= 16384)
+      // exact int32 sums in LDS (|sum| <= n^2 < 2^31 for n <= 16384), one
+      // margin's bins at a time (n + 1 words, so that two workgroups share a
+      // CU); each row's u-order term waits in the workspace between the two
+      // (the slots of the global-bin path; a thread reads back only its own
+      // rows, the second bins stay in LDS for the psi pass below)
       extern __shared__ int hb[];
-      int* B1 = hb;
-      int* B2 = hb + NH;
-      for (int64_t k = t; k < NH; k += MT) { B1[k] = 0; B2[k] = 0; }
-      __syncthreads();
-      for (int64_t i = t; i < n; i += MT) {
-        const uint32_t x = R1[i], y = R2[i];
-        atomicAdd(&B1[x >> 1], (int)((long long)y - n1));
-        atomicAdd(&B2[y >> 1], (int)((long long)x - n1));
+      double* WU = (double*)(P.H1 + 2 * (o + P.base + sid));
+      for (int mg = 0; mg < 2; ++mg) {
+        for (int64_t k = t; k < NH; k += MT) hb[k] = 0;
+        __syncthreads();
+        for (int64_t i = t; i < n; i += MT) {
+          const uint32_t x = R1[i], y = R2[i];
+          if (mg == 0)
+            atomicAdd(&hb[x >> 1], (int)((long long)y - n1));
+          else
+            atomicAdd(&hb[y >> 1], (int)((long long)x - n1));
+        }
+        __syncthreads();
+        int t1 = 0;
+        for (int64_t k = k1 - 1; k >= k0; --k) {
+          t1 += hb[k]; hb[k] = t1;
+        }
+        tot[0][t] = t1;
+        __syncthreads();
+        int c1 = 0;
+        for (int u = t + 1; u < MT; ++u) c1 += (int)tot[0][u];
+        for (int64_t k = k0; k < k1; ++k) hb[k] += c1;
+        __syncthreads();
+        if (mg == 0) {
+          for (int64_t i = t; i < n; i += MT) WU[i] = (double)hb[R1[i] >> 1];
+          __syncthreads();
+        }
       }
-      __syncthreads();
-      int t1 = 0, t2 = 0;
-      for (int64_t k = k1 - 1; k >= k0; --k) {
-        t1 += B1[k]; B1[k] = t1;
-        t2 += B2[k]; B2[k] = t2;
-      }
-      tot[0][t] = t1;
-      tot[1][t] = t2;
-      __syncthreads();
-      int c1 = 0, c2 = 0;
-      for (int u = t + 1; u < MT; ++u) { c1 += (int)tot[0][u]; c2 += (int)tot[1][u]; }
-      for (int64_t k = k0; k < k1; ++k) { B1[k] += c1; B2[k] += c2; }
-      __syncthreads();
     } else {
       long long* H1 = P.H1 + 2 * (o + P.base + sid);
       long long* H2 = P.H2 + 2 * (o + P.base + sid);
@@ -359,7 +368,7 @@ __global__ void __launch_bounds__(MT) k_spearman(MomParams P) {
       double w;
       if constexpr (LDSB) {
         extern __shared__ int hb[];
-        w = (double)hb[x >> 1] + (double)hb[NH + (y >> 1)];
+        w = ((const double*)(P.H1 + 2 * (o + P.base + sid)))[i] + (double)hb[y >> 1];
       } else {
         w = (double)P.H1[2 * (o + P.base + sid) + (x >> 1)] + (double)P.H2[2 * (o + P.base + sid) + (y >> 1)];
       }
@@ -938,10 +947,10 @@ hipError_t launch_spearman(int fam, const uint32_t* R1, const uint32_t* R2, cons
   if (K <= 0) return hipSuccess;
   const dim3 grid((unsigned)K), block(MT);
   if (n_max <= kSpearmanLdsRows) {
-    const size_t lds = 2 * sizeof(int) * (size_t)(n_max + 1);
+    const size_t lds = sizeof(int) * (size_t)(n_max + 1);
     static bool attr = false;  // allow the largest dynamic LDS once per process
     if (!attr) {
-      const int most = (int)(2 * sizeof(int) * (kSpearmanLdsRows + 1));
+      const int most = (int)(sizeof(int) * (kSpearmanLdsRows + 1));
       hipError_t e = hipFuncSetAttribute((const void*)k_spearman<FAM_GAUSSIAN, true>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, most);
       if (e == hipSuccess)
