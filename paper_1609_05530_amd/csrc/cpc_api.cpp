@@ -1012,11 +1012,11 @@ int cpc_fit_batched_noalloc(cpc_handle_t h, const void* x, const void* y, int32_
 // The body of cpc_rank; margins = 1 leaves the y ranks of subsets above
 // kResidentMaxRows unwritten (the workgroup kernels rank both margins). With
 // big_sorted, x of those subsets is only sorted: their R1 is not written,
-// and *big_sorted / *big receive the sorted payloads and the streaming
-// path's tables (big->nsegs = 0 when there is no such subset).
+// and *big_sorted / *big receive the sorted order and the streaming path's
+// tables (big->nsegs = 0 when there is no such subset).
 static int rank_impl(cpc_handle_t h, const void* x, const void* y, int32_t dtype, int64_t n, const int64_t* offsets,
                      int64_t K, const cpc_options_t* opt, void* workspace, size_t ws_bytes, uint32_t* R1,
-                     uint32_t* R2, void* stream, int margins, const uint32_t** big_sorted = nullptr,
+                     uint32_t* R2, void* stream, int margins, BigSorted* big_sorted = nullptr,
                      BigParams* big = nullptr) {
   if (int rc = check_handle(h)) return rc;
   if (!x || !y || !offsets || !R1 || !R2) return fail(CPC_E_NULL, "a required pointer is NULL");
@@ -1269,7 +1269,7 @@ int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, i
   uint32_t* R1 = nullptr;
   // replicates above kResidentMaxRows: x sorted on the streaming path and
   // the rows gathered from the sorted payloads (no ranks formed)
-  const uint32_t* big_sorted = nullptr;
+  BigSorted big_sorted = {nullptr, nullptr, nullptr};
   BigParams big;
   std::memset(&big, 0, sizeof(big));
   if (scheme != CPC_PART_CONTIGUOUS) {
@@ -1288,7 +1288,7 @@ int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, i
   P.part_rep.assign(rep_offsets, rep_offsets + R + 1);
   HIP_OK(hipMemcpyAsync(drep, P.part_rep.data(), sizeof(int64_t) * (size_t)(R + 1), hipMemcpyHostToDevice, s));
   const int f32 = dtype == CPC_F32 ? 1 : 0;
-  const bool gather = big.nsegs > 0 && big_sorted != nullptr;
+  const bool gather = big.nsegs > 0 && big_sorted.rows != nullptr;
   bool small = !gather;  // a replicate left to the scatter kernel
   for (int64_t r = 0; r < R && !small; ++r) {
     const int64_t N = rep_offsets[r + 1] - rep_offsets[r];

@@ -628,7 +628,7 @@ static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1
 
 hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, const void* y, int dtype_kw,
                     int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s, int margins,
-                    const uint32_t** sorted_rows) {
+                    BigSorted* sorted) {
   if (P.nsegs == 0) return hipSuccess;
   const unsigned nt = (unsigned)P.nslots;  // tile slots in XCD order
   hipLaunchKernelGGL(k_big_zero_flags, dim3(nblk(P.nsegs, 256)), dim3(256), 0, s, P);
@@ -656,8 +656,10 @@ hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, cons
       std::swap(khi, khi2);
       std::swap(val, val2);
     }
-    if (sorted_rows) {
-      *sorted_rows = val;
+    if (sorted) {
+      sorted->rows = val;
+      sorted->klo = klo;
+      sorted->khi = khi;
       return hipGetLastError();
     }
     uint32_t* Rm = margin ? B.R2 : B.R1;

@@ -16,9 +16,12 @@
 // Replicates of more than kResidentMaxRows rows take the gather below
 // instead: their x is sorted on the streaming path, whose payloads give the
 // row at each sorted position, so output row o (subset m, its q-th row)
-// reads the row at position p = o (blocks) or p = q M + m (strided); the
-// writes are coalesced and the reads stay inside the replicate, whose
-// tiles the streaming path's slots keep on one XCD.
+// takes the row at position p = o (blocks) or p = q M + m (strided). Each
+// 8-byte read from a random place in the replicate brings in a whole line,
+// which bounds the gather; for blocks, x is the inverse of the position's
+// order-preserving key instead (read in order; a key of 0 is read from x,
+// which keeps the sign of -0), so that only y is read at random. The
+// writes are coalesced.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -61,11 +64,24 @@ __global__ void __launch_bounds__(256) k_partition(const T* __restrict__ x, cons
   }
 }
 
+// The value whose order-preserving key is k (the key turns a non-negative
+// value's bits b into b with the top bit set, a negative one's into ~b);
+// false for the key of +-0, whose sign the key does not keep.
+__device__ __forceinline__ bool value_of_key(uint32_t k, float& v) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  v = __uint_as_float(b);
+  return b != 0u;
+}
+__device__ __forceinline__ bool value_of_key(uint64_t k, double& v) {
+  const uint64_t b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  v = __longlong_as_double((long long)b);
+  return b != 0ull;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_partition_gather(BigParams P, const uint32_t* __restrict__ sorted_rows,
-                                                          const T* __restrict__ x, const T* __restrict__ y,
-                                                          uint32_t M, int scheme, T* __restrict__ xo,
-                                                          T* __restrict__ yo) {
+__global__ void __launch_bounds__(256) k_partition_gather(BigParams P, BigSorted so, const T* __restrict__ x,
+                                                          const T* __restrict__ y, uint32_t M, int scheme,
+                                                          T* __restrict__ xo, T* __restrict__ yo) {
   const int64_t ti = P.xorder[blockIdx.x];
   if (ti < 0) return;  // idle slot (uniform)
   const BigTile t = P.tiles[ti];
@@ -90,22 +106,32 @@ __global__ void __launch_bounds__(256) k_partition_gather(BigParams P, const uin
       }
       p = q * M + m;
     }
-    const uint32_t row = sorted_rows[sg.roff + p];
+    const int64_t c = sg.roff + p;
+    const uint32_t row = so.rows[c];
     if (row >= N) continue;  // not a row of this replicate: nothing is written
-    xo[sg.begin + o] = x[sg.begin + row];
+    T xv;
+    bool from_key = false;
+    if (scheme == PART_BLOCKS) {  // keys in order (strided: a stride of M, dearer than x itself)
+      if constexpr (sizeof(T) == 8)
+        from_key = value_of_key(((uint64_t)so.khi[c] << 32) | so.klo[c], xv);
+      else
+        from_key = value_of_key(so.klo[c], xv);
+    }
+    if (!from_key) xv = x[sg.begin + row];
+    xo[sg.begin + o] = xv;
     yo[sg.begin + o] = y[sg.begin + row];
   }
 }
 
-hipError_t launch_partition_gather(int f32, const BigParams& P, const uint32_t* sorted_rows, const void* x,
-                                   const void* y, int64_t M, int scheme, void* xo, void* yo, hipStream_t s) {
+hipError_t launch_partition_gather(int f32, const BigParams& P, const BigSorted& so, const void* x, const void* y,
+                                   int64_t M, int scheme, void* xo, void* yo, hipStream_t s) {
   if (P.nsegs == 0 || P.nslots == 0) return hipSuccess;
   const unsigned nt = (unsigned)P.nslots;
   if (f32)
-    hipLaunchKernelGGL(k_partition_gather<float>, dim3(nt), dim3(256), 0, s, P, sorted_rows, (const float*)x,
+    hipLaunchKernelGGL(k_partition_gather<float>, dim3(nt), dim3(256), 0, s, P, so, (const float*)x,
                        (const float*)y, (uint32_t)M, scheme, (float*)xo, (float*)yo);
   else
-    hipLaunchKernelGGL(k_partition_gather<double>, dim3(nt), dim3(256), 0, s, P, sorted_rows, (const double*)x,
+    hipLaunchKernelGGL(k_partition_gather<double>, dim3(nt), dim3(256), 0, s, P, so, (const double*)x,
                        (const double*)y, (uint32_t)M, scheme, (double*)xo, (double*)yo);
   return hipGetLastError();
 }

@@ -125,14 +125,20 @@ struct BigBuffers {
   NewtonState* st;                        // per subset
   int* pending;                           // subsets still iterating
 };
+// The sorted order of x on the streaming path: entry roff + p of a subset
+// holds the row (within the subset) at its sorted position p and that row's
+// order-preserving key (low and high words; the high words only for FP64).
+struct BigSorted {
+  const uint32_t* rows;
+  const uint32_t* klo;
+  const uint32_t* khi;
+};
 // margins = 1 ranks x alone (R2out and the staged y arrays are left as they
-// are). sorted_rows != nullptr: x is only sorted (stably, so ties keep row
-// order); no ranks are formed and *sorted_rows points at the payloads in
-// sorted order: entry roff + p of a subset holds the row (within the
-// subset) at its sorted position p.
+// are). sorted != nullptr: x is only sorted (stably, so ties keep row
+// order), no ranks are formed, and *sorted receives the sorted order.
 hipError_t big_rank(const BigParams& P, const BigBuffers& B, const void* x, const void* y, int dtype_kw,
                     int int_keys, int ties, uint32_t* R1out, uint32_t* R2out, hipStream_t s, int margins = 2,
-                    const uint32_t** sorted_rows = nullptr);
+                    BigSorted* sorted = nullptr);
 hipError_t big_solve(const BigParams& P, const BigBuffers& B, double tol, int max_iter, int fp64, int* pending_host,
                      hipStream_t s);
 hipError_t big_variance(const BigParams& P, const BigBuffers& B, int fp64, const double* theta_in, int var_method,
@@ -179,10 +185,10 @@ hipError_t launch_partition(int f32, const void* x, const void* y, const uint32_
                             int64_t R, int64_t n, int64_t M, int scheme, int skip_big, void* xo, void* yo,
                             hipStream_t s);
 // The x-order schemes for the replicates of the streaming path, from their
-// sorted payloads (big_rank with sorted_rows): output row o of a replicate
-// takes the row at the sorted position its scheme assigns to o.
-hipError_t launch_partition_gather(int f32, const BigParams& P, const uint32_t* sorted_rows, const void* x,
-                                   const void* y, int64_t M, int scheme, void* xo, void* yo, hipStream_t s);
+// sorted order (big_rank with sorted): output row o of a replicate takes
+// the row at the sorted position its scheme assigns to o.
+hipError_t launch_partition_gather(int f32, const BigParams& P, const BigSorted& so, const void* x, const void* y,
+                                   int64_t M, int scheme, void* xo, void* yo, hipStream_t s);
 
 // Spearman-inversion estimates per subset from doubled ranks (k_moment.hip);
 // H1, H2: 2 (n + K) int64 each.
