@@ -286,8 +286,10 @@ typedef enum {
  * R+1 values); 0 if rep_offsets is not a partition of 0 .. rep_offsets[R] or
  * an argument is out of range. About 36 bytes per row for the x-order
  * schemes (doubled ranks of both margins and the rank kernels' own
- * workspace, + 88 per row of replicates above 16384 rows), plus the
- * replicate table of 8 (R + 1) bytes (all that CPC_PART_CONTIGUOUS needs). */
+ * workspace, + 88 per row of replicates above 16384 rows), 2 values per
+ * row more for CPC_PART_STRIDED (its rows in blocks order before their
+ * transpose), plus the replicate table of 8 (R + 1) bytes (all that
+ * CPC_PART_CONTIGUOUS needs). */
 size_t cpc_partition_workspace_bytes(const int64_t* rep_offsets, int64_t R, int32_t dtype, int32_t scheme);
 
 /* Splits every replicate r (rows rep_offsets[r] .. rep_offsets[r+1] - 1, N_r

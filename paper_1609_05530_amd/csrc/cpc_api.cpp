@@ -1225,6 +1225,9 @@ size_t cpc_partition_workspace_bytes(const int64_t* rep_offsets, int64_t R, int3
   if (scheme < CPC_PART_CONTIGUOUS || scheme > CPC_PART_STRIDED) return 0;
   if (check_offsets(rep_offsets, R, rep_offsets[R]) != CPC_SUCCESS) return 0;
   size_t need = align_up(sizeof(int64_t) * (size_t)(R + 1));
+  // strided: the rows in blocks order before their transpose
+  if (scheme == CPC_PART_STRIDED)
+    need += 2 * align_up((dtype == CPC_F64 ? 8 : 4) * (size_t)rep_offsets[R]);
   if (scheme != CPC_PART_CONTIGUOUS) {
     const cpc_options_t o = partition_rank_options();
     need += 2 * align_up(sizeof(uint32_t) * (size_t)rep_offsets[R]) +
@@ -1266,6 +1269,13 @@ int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, i
   unsigned char* b = (unsigned char*)workspace;
   int64_t* drep = (int64_t*)b;
   b += align_up(sizeof(int64_t) * (size_t)(R + 1));
+  void *tx = nullptr, *ty = nullptr;
+  if (scheme == CPC_PART_STRIDED) {
+    const size_t eb = align_up((dtype == CPC_F64 ? 8 : 4) * (size_t)n);
+    tx = b;
+    ty = b + eb;
+    b += 2 * eb;
+  }
   uint32_t* R1 = nullptr;
   // replicates above kResidentMaxRows: x sorted on the streaming path and
   // the rows gathered from the sorted payloads (no ranks formed)
@@ -1295,7 +1305,23 @@ int cpc_partition(cpc_handle_t h, const void* x, const void* y, int32_t dtype, i
     small = N > 0 && N <= kResidentMaxRows;
   }
   if (small) HIP_OK(launch_partition(f32, x, y, R1, drep, R, n, M, scheme, gather ? 1 : 0, x_out, y_out, s));
-  if (gather) HIP_OK(launch_partition_gather(f32, big, big_sorted, x, y, M, scheme, x_out, y_out, s));
+  if (gather && scheme == CPC_PART_STRIDED) {
+    // the blocks order (whose x comes from the keys in order), then its
+    // transpose into the strided order: both read and write along rows
+    HIP_OK(launch_partition_gather(f32, big, big_sorted, x, y, M, CPC_PART_BLOCKS, tx, ty, s));
+    int64_t max_tiles = 0;
+    for (int64_t r = 0; r < R; ++r) {
+      const int64_t N = rep_offsets[r + 1] - rep_offsets[r];
+      if (N <= kResidentMaxRows) continue;
+      const int64_t Q = (N + M - 1) / M, Mc = std::min<int64_t>(M, N);
+      max_tiles = std::max<int64_t>(max_tiles, ((Q + 31) / 32) * ((Mc + 31) / 32));
+    }
+    if ((int64_t)big.nsegs * max_tiles >= ((int64_t)1 << 31))
+      return fail(CPC_E_UNSUPPORTED, "too many transpose tiles");
+    HIP_OK(launch_partition_transpose(f32, big, tx, ty, M, max_tiles, x_out, y_out, s));
+  } else if (gather) {
+    HIP_OK(launch_partition_gather(f32, big, big_sorted, x, y, M, scheme, x_out, y_out, s));
+  }
   return CPC_SUCCESS;
 }
 

@@ -136,6 +136,59 @@ hipError_t launch_partition_gather(int f32, const BigParams& P, const BigSorted&
   return hipGetLastError();
 }
 
+// Strided rows from blocks-order rows, one 32 x 32 tile of (q, m) per
+// workgroup: read along m (consecutive positions q M + m), written along q
+// (consecutive rows of subset m) through LDS; blocks run over the
+// replicates' tiles, replicate by replicate.
+template <typename T>
+__global__ void __launch_bounds__(256) k_partition_transpose(BigParams P, const T* __restrict__ tx,
+                                                             const T* __restrict__ ty, uint32_t M, int64_t max_tiles,
+                                                             T* __restrict__ xo, T* __restrict__ yo) {
+  __shared__ T sx[32][33];
+  __shared__ T sy[32][33];
+  const int64_t seg = (int64_t)blockIdx.x / max_tiles;
+  const uint32_t tile = (uint32_t)((int64_t)blockIdx.x - seg * max_tiles);
+  const BigSeg sg = P.segs[seg];
+  const uint32_t N = (uint32_t)sg.n;
+  const uint32_t a = N / M, c = N - a * M, Q = a + (c ? 1u : 0u);
+  const uint32_t Mc = M < N ? M : N;  // (columns m >= N are empty)
+  const uint32_t tiles_m = (Mc + 31u) / 32u;
+  if ((uint64_t)tile >= (uint64_t)((Q + 31u) / 32u) * tiles_m) return;  // (uniform)
+  const uint32_t tq = tile / tiles_m, tm = tile - tq * tiles_m;
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;
+  for (int i = ly; i < 32; i += 8) {
+    const uint32_t q = tq * 32u + (uint32_t)i, m = tm * 32u + (uint32_t)lx;
+    const uint64_t p = (uint64_t)q * M + m;
+    if (m < M && p < N) {
+      sx[i][lx] = tx[sg.begin + (int64_t)p];
+      sy[i][lx] = ty[sg.begin + (int64_t)p];
+    }
+  }
+  __syncthreads();
+  for (int j = ly; j < 32; j += 8) {
+    const uint32_t m = tm * 32u + (uint32_t)j, q = tq * 32u + (uint32_t)lx;
+    const uint64_t p = (uint64_t)q * M + m;
+    if (m < M && p < N) {
+      const int64_t o = sg.begin + (int64_t)(m * a + (m < c ? m : c) + q);
+      xo[o] = sx[lx][j];
+      yo[o] = sy[lx][j];
+    }
+  }
+}
+
+hipError_t launch_partition_transpose(int f32, const BigParams& P, const void* tx, const void* ty, int64_t M,
+                                      int64_t max_tiles, void* xo, void* yo, hipStream_t s) {
+  if (P.nsegs == 0 || max_tiles <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((int64_t)P.nsegs * max_tiles);
+  if (f32)
+    hipLaunchKernelGGL(k_partition_transpose<float>, dim3(blocks), dim3(256), 0, s, P, (const float*)tx,
+                       (const float*)ty, (uint32_t)M, max_tiles, (float*)xo, (float*)yo);
+  else
+    hipLaunchKernelGGL(k_partition_transpose<double>, dim3(blocks), dim3(256), 0, s, P, (const double*)tx,
+                       (const double*)ty, (uint32_t)M, max_tiles, (double*)xo, (double*)yo);
+  return hipGetLastError();
+}
+
 hipError_t launch_partition(int f32, const void* x, const void* y, const uint32_t* R1, const int64_t* rep,
                             int64_t R, int64_t n, int64_t M, int scheme, int skip_big, void* xo, void* yo,
                             hipStream_t s) {

@@ -189,6 +189,12 @@ hipError_t launch_partition(int f32, const void* x, const void* y, const uint32_
 // the row at the sorted position its scheme assigns to o.
 hipError_t launch_partition_gather(int f32, const BigParams& P, const BigSorted& so, const void* x, const void* y,
                                    int64_t M, int scheme, void* xo, void* yo, hipStream_t s);
+// Strided from blocks order for the replicates of the streaming path: row q
+// of subset m, at position q M + m of the blocks-order rows tx, ty, goes to
+// m a + min(m, c) + q of xo, yo (N = a M + c); max_tiles: the most 32 x 32
+// tiles of (q, m) any of those replicates has.
+hipError_t launch_partition_transpose(int f32, const BigParams& P, const void* tx, const void* ty, int64_t M,
+                                      int64_t max_tiles, void* xo, void* yo, hipStream_t s);
 
 // Spearman-inversion estimates per subset from doubled ranks (k_moment.hip);
 // H1, H2: 2 (n + K) int64 each.
